@@ -1,0 +1,203 @@
+/*
+ * gmg.h -- C ABI of an MI355X (gfx950) implementation of adaptive geometric
+ * multigrid with local smoothing for Q_k finite elements on 2:1-balanced
+ * quad/hex forests (Clevenger, Heister, Kanschat, Kronbichler,
+ * arXiv:1904.03317).
+ *
+ * What is solved (Sec. 2.1): find u in V_h, the conforming Q_k space on the
+ * leaf mesh with hanging nodes eliminated (Sec. 2.3) and u = 0 on the domain
+ * boundary, such that  sum_K a_K int_K grad u . grad v = int f_h v  for all v,
+ * with a cell-wise constant coefficient a_K (Sec. 4.3) and f_h the nodal
+ * interpolant of the given nodal values.  The method (Sec. 1, 2.2, 2.3, 4.1):
+ * conjugate gradients in FP64, preconditioned by one V-cycle (Alg. 2) with
+ * local smoothing on the level meshes, a Chebyshev-Jacobi smoother (Alg. 1
+ * with Chebyshev acceleration), transfer operators that are the embedding and
+ * its Euclidean adjoint, and an exact coarse solve.  The V-cycle runs in FP32
+ * or FP64 (mixed precision as in Sec. 4.1).
+ *
+ * Conventions
+ *  - Every call returns int: 0 = OK, GMG_NOT_CONVERGED (+1) = solve finished
+ *    without reaching the tolerance (outputs are still written), negative =
+ *    error.  gmg_last_error() returns a thread-local message for the last
+ *    failing call on this thread.  No C++ exception crosses this ABI.
+ *  - Pointers named d_* are device pointers (HIP device memory of the current
+ *    device); all other pointers are host pointers.  The caller owns every
+ *    buffer it passes in.  Arrays returned through gmg_problem_array() are
+ *    owned by the library and stay valid until the problem is destroyed.
+ *  - Device work is ordered on the caller's stream; calls that return host
+ *    results (solve, vcycle timings, bind) synchronise that stream first.
+ *  - Geometry: coarse cells are unit squares/cubes [o, o+1]^d at distinct
+ *    integer origins o.  A cell of level l has side 2^-l; anchors are given in
+ *    global integer units of 2^-20.  Maximum level 18.
+ *  - Canonical cell order: by coarse cell, then z-order (Morton, child id
+ *    x + 2y + 4z) of the anchor -- depth-first order of the forest.
+ *  - A level DoF flag is 0 = S (smoothed on this level), 1 = I (interface:
+ *    node of a level-l cell lying in the closure of a coarser leaf), 2 = D
+ *    (on the domain boundary).  Sec. 2.3, Fig. 1.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GMG_OK = 0,
+  GMG_NOT_CONVERGED = 1,
+  GMG_E_INVAL = -1,
+  GMG_E_NOMEM_HOST = -2,
+  GMG_E_NOMEM_DEVICE = -3,
+  GMG_E_BUDGET = -4,
+  GMG_E_BREAKDOWN = -5,
+  GMG_E_NAN = -6,
+  GMG_E_HIP = -7,
+  GMG_E_STATE = -8
+};
+
+typedef struct gmg_mesh_s* gmg_mesh;
+typedef struct gmg_problem_s* gmg_problem;
+typedef struct gmg_server_s* gmg_server;
+
+/* Solver options.  Defaults from gmg_options_default(): degree 2, FP32
+ * V-cycle, Chebyshev degree 4 on [0.08, 1.2] * lambda_max (Sec. 4.1), 10
+ * eigenvalue-estimate iterations (Sec. 4.1), rtol 1e-10 on the
+ * unpreconditioned residual (Sec. 4.1, 4.3), max_iter 100. */
+typedef struct {
+  int32_t degree;        /* k = 1..4 */
+  int32_t mg_precision;  /* 32: FP32 V-cycle inside FP64 CG; 64: FP64 throughout */
+  int32_t cheb_degree;   /* smoothing steps per smoother call, >= 1 */
+  double cheb_lo;        /* lower end of the damped range, fraction of lambda_max */
+  double cheb_hi;        /* upper end, fraction of lambda_max */
+  int32_t eig_iters;     /* CG steps of the lambda_max estimate */
+  double rtol;           /* stop when ||b - A u||_2 <= rtol ||b||_2 */
+  int32_t max_iter;      /* CG iteration cap */
+  int32_t use_graph;     /* 1: replay the V-cycle as a captured HIP graph */
+} gmg_options;
+
+void gmg_options_default(gmg_options* opts);
+const char* gmg_last_error(void);
+
+/* ---------------------------------------------------------------- forest
+ * Sec. 2.2 (mesh hierarchy by isotropic refinement), Sec. 2.3 (forest,
+ * levels, leaf mesh), Sec. 3.5 (2:1 balance).  Host only. */
+
+/* New forest of level-0 leaves.  origins: [n_coarse * dim] integer origins,
+ * distinct.  dim in {2,3}; 1 <= n_coarse <= 32.  Errors: GMG_E_INVAL. */
+int gmg_mesh_create(int dim, int n_coarse, const int32_t* origins, gmg_mesh* out);
+/* Refine the flagged leaves (flags[n_leaves], canonical order, nonzero =
+ * refine), then close the mesh to 2:1 balance: any two leaves whose closures
+ * touch differ by at most one level (this is the paper's complete layer of
+ * level l-1 cells around the level-l cells).  Writes the new leaf count. */
+int gmg_mesh_refine(gmg_mesh m, const uint8_t* flags, int64_t* n_leaves_after);
+int gmg_mesh_num_leaves(gmg_mesh m, int64_t* n);
+/* Leaves in canonical order: level[n], anchor[n*dim] (global, units 2^-20). */
+int gmg_mesh_leaves(gmg_mesh m, int8_t* level, int64_t* anchor);
+int gmg_mesh_dim(gmg_mesh m, int* dim);
+int gmg_mesh_destroy(gmg_mesh m);
+
+/* ---------------------------------------------------------------- problem
+ * Host setup: leaf DoF numbering with hanging-node constraints (Sec. 2.3),
+ * level DoFs with the S/I/D splitting (Sec. 2.3, Fig. 1), copy map from the
+ * leaf vector into the level vectors, transfer (family) maps (Sec. 2.2).
+ * cell_coeff: [n_leaves] a_K > 0 in canonical leaf order, or NULL for 1.
+ * The mesh is only read; it may be destroyed afterwards. */
+int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* cell_coeff,
+                       gmg_problem* out);
+
+typedef struct {
+  int32_t dim, degree, n_levels, mg_precision;
+  int64_t n_dofs;        /* leaf DoFs incl. Dirichlet nodes, excl. hanging nodes */
+  int64_t n_hanging;
+  int64_t n_leaves;
+  int64_t n_free;        /* non-Dirichlet leaf DoFs */
+  int64_t level_dofs[24];
+  int64_t level_cells[24];
+  double lambda_max[24]; /* eigenvalue estimates, valid after gmg_problem_bind */
+  size_t workspace_bytes;
+} gmg_info;
+int gmg_problem_info(gmg_problem p, gmg_info* out);
+
+/* Library-owned host arrays for bit-exact checks (valid until destroy).
+ * which / element type / length:
+ *   GMG_ARR_LEAF_CELLMAP  int32  n_leaves*(k+1)^d  DoF id, or -(h+1) for hanging node h
+ *   GMG_ARR_LEAF_DIRICHLET uint8 n_dofs            1 = Dirichlet node
+ *   GMG_ARR_CON_OFFSETS   int64  n_hanging+1       CSR offsets of the constraints
+ *   GMG_ARR_CON_MASTERS   int32  nnz              master DoF ids, z-major order
+ *   GMG_ARR_CON_WEIGHTS   double nnz              coarse basis at the hanging node
+ *   GMG_ARR_COPY_LEVEL    int8   n_dofs            level holding leaf DoF i as S or D
+ *   GMG_ARR_COPY_INDEX    int32  n_dofs            its index on that level
+ *   GMG_ARR_LEVEL_CELLMAP int32  level_cells*(k+1)^d (level given)
+ *   GMG_ARR_LEVEL_FLAGS   uint8  level_dofs        0 S, 1 I, 2 D
+ *   GMG_ARR_LEVEL_PARENT  int32  level_cells/2^d   parent index in level-1 cells */
+enum {
+  GMG_ARR_LEAF_CELLMAP = 1,
+  GMG_ARR_LEAF_DIRICHLET = 2,
+  GMG_ARR_CON_OFFSETS = 3,
+  GMG_ARR_CON_MASTERS = 4,
+  GMG_ARR_CON_WEIGHTS = 5,
+  GMG_ARR_COPY_LEVEL = 6,
+  GMG_ARR_COPY_INDEX = 7,
+  GMG_ARR_LEVEL_CELLMAP = 8,
+  GMG_ARR_LEVEL_FLAGS = 9,
+  GMG_ARR_LEVEL_PARENT = 10
+};
+int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int64_t* count);
+
+/* Device memory the problem needs (maps, level and CG vectors, coarse
+ * inverse).  The caller allocates it (any HIP device allocation, e.g. a torch
+ * uint8 tensor) and keeps it alive until gmg_problem_destroy. */
+int gmg_problem_workspace_bytes(gmg_problem p, size_t* bytes);
+/* Upload maps into d_workspace and run the device setup on `stream`: Jacobi
+ * diagonals, lambda_max estimates (FP64 Lanczos from CG, Sec. 4.1), exact
+ * coarse inverse (FP64).  Synchronises the stream.  d_workspace must be
+ * 256-byte aligned.  Errors: GMG_E_INVAL (too small), GMG_E_HIP. */
+int gmg_problem_bind(gmg_problem p, void* d_workspace, size_t bytes, hipStream_t stream);
+int gmg_problem_destroy(gmg_problem p);
+
+/* ---------------------------------------------------------------- solve */
+
+/* Load vector b = C^T M C f (Sec. 2.1 right-hand side with the nodal
+ * interpolant; C eliminates hanging nodes), Dirichlet rows zero.
+ * d_f: [n_dofs] nodal values (FP64); d_b: [n_dofs]. */
+int gmg_rhs(gmg_problem p, const double* d_f, double* d_b, hipStream_t stream);
+
+/* CG with one V-cycle as preconditioner, x0 = 0, until
+ * ||r||_2 <= rtol ||b||_2 (Sec. 4.1/4.3).  d_f: nodal right-hand side
+ * [n_dofs] (FP64, device); NULL means f = 1.  d_u: [n_dofs] solution.
+ * iterations: CG iterations done.  history (host, may be NULL):
+ * [max_iter+1] relative residual norms, entry 0 = 1.  Returns GMG_OK,
+ * GMG_NOT_CONVERGED, GMG_E_NAN (non-finite residual) or GMG_E_BREAKDOWN
+ * (p.Ap <= 0 or r.z <= 0).  Synchronises the stream. */
+int gmg_solve(gmg_problem p, const double* d_f, double* d_u, int32_t* iterations,
+              double* history, hipStream_t stream);
+/* Same as gmg_solve with a precomputed load vector d_b. */
+int gmg_solve_rhs(gmg_problem p, const double* d_b, double* d_u, int32_t* iterations,
+                  double* history, hipStream_t stream);
+
+/* Test hooks (stream-ordered, no synchronisation):
+ * leaf operator q = C^T A C p with Dirichlet rows zeroed (FP64, [n_dofs]);
+ * level operator on level l (element type = mg precision, [level_dofs[l]]):
+ *   variant 0 (smoother): y = A_l x over all level cells, every row written
+ *     (rows of S nodes give A^S x^S when x is zero on I and D nodes);
+ *   variant 1 (edge): y^S = A^{SI} x^I: input restricted to I nodes, output
+ *     to S rows, other rows 0;
+ * one V-cycle z = B r (FP64 in and out, [n_dofs]). */
+int gmg_apply_leaf(gmg_problem p, const double* d_in, double* d_out, hipStream_t stream);
+int gmg_apply_level(gmg_problem p, int level, int variant, const void* d_in, void* d_out,
+                    hipStream_t stream);
+int gmg_vcycle(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream);
+
+/* Seconds of device time of the last gmg_solve* on this problem (events on
+ * the caller's stream): [0] whole solve, [1] sum of V-cycles, [2] number of
+ * V-cycles. */
+int gmg_problem_last_timing(gmg_problem p, double* out3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

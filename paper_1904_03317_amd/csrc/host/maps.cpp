@@ -1,0 +1,517 @@
+#include "maps.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+namespace gmg {
+
+namespace {
+
+// Per-axis node code.  Nodes at the cell ends and (even k) at the midpoint
+// are identified by their exact dyadic coordinate (units 2^-21, relative to
+// the lower corner of the coarse bounding box).  Interior Gauss-Lobatto
+// points (k >= 3) never coincide with a node of another cell level or
+// position; they are identified by (level, cell index, j), tagged by bit 31.
+struct AxisCoder {
+  int k;
+  int64_t lo;  // box lower corner along the axis, units 2^-20
+  uint32_t code(int level, int64_t a, int j) const {
+    int64_t s = side_of(level);
+    int64_t X;
+    if (j == 0)
+      X = 2 * a;
+    else if (j == k)
+      X = 2 * (a + s);
+    else if ((k % 2 == 0) && 2 * j == k)
+      X = 2 * a + s;
+    else {
+      uint64_t c = uint64_t((a - lo) / s);
+      return 0x80000000u | (uint32_t(level) << 26) | (uint32_t(j) << 23) | uint32_t(c);
+    }
+    return uint32_t(X - 2 * lo);
+  }
+};
+
+inline u128 make_key(const uint32_t* c, int dim) {
+  u128 k = c[0];
+  k |= u128(c[1]) << 32;
+  if (dim == 3) k |= u128(c[2]) << 64;
+  return k;
+}
+
+struct Ctx {
+  const Forest& f;
+  int dim, k, n, npc;
+  AxisCoder ax[3];
+  FE1D fe;
+  Ctx(const Forest& f_, int k_) : f(f_), dim(f_.dim()), k(k_), n(k_ + 1) {
+    npc = 1;
+    for (int i = 0; i < dim; ++i) npc *= n;
+    for (int i = 0; i < 3; ++i) ax[i] = AxisCoder{k, int64_t(f.box_lo()[i]) << kDepth};
+    fe = make_fe1d(k);
+  }
+  // codes[i][j] of a cell
+  void cell_codes(const Cell& c, uint32_t codes[3][5]) const {
+    for (int i = 0; i < dim; ++i)
+      for (int j = 0; j < n; ++j) codes[i][j] = ax[i].code(c.level, c.a[i], j);
+  }
+  u128 node_key(const uint32_t codes[3][5], int lidx) const {
+    uint32_t c[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i) {
+      c[i] = codes[i][lidx % n];
+      lidx /= n;
+    }
+    return make_key(c, dim);
+  }
+  // node on the boundary of the domain (a union of unit cells): some unit
+  // cell around it is not a coarse cell
+  bool on_boundary(u128 key) const {
+    int64_t cand[3][2];
+    int nc[3] = {1, 1, 1};
+    cand[2][0] = 0;
+    bool any_int = false;
+    for (int i = 0; i < dim; ++i) {
+      uint32_t c = uint32_t(key >> (32 * i));
+      int64_t lo = ax[i].lo;
+      if (c & 0x80000000u) {
+        int level = (c >> 26) & 31;
+        int64_t ci = c & ((1u << 23) - 1);
+        int64_t a = lo + ci * side_of(level);
+        cand[i][0] = floor_to(a, int64_t(1) << kDepth) >> kDepth;
+      } else {
+        int64_t X = int64_t(c) + 2 * lo;   // units 2^-21
+        int64_t unit = int64_t(1) << (kDepth + 1);
+        int64_t q = floor_to(X, unit) / unit;
+        if (X % unit == 0) {
+          cand[i][0] = q - 1;
+          cand[i][1] = q;
+          nc[i] = 2;
+          any_int = true;
+        } else {
+          cand[i][0] = q;
+        }
+      }
+    }
+    if (!any_int) return false;
+    for (int z = 0; z < nc[2]; ++z)
+      for (int y = 0; y < nc[1]; ++y)
+        for (int x = 0; x < nc[0]; ++x) {
+          int64_t u[3] = {cand[0][x], cand[1][y], cand[2][z]};
+          if (f.tree_of_unit(u) < 0) return true;
+        }
+    return false;
+  }
+  Cell parent_of(const Cell& c) const {
+    Cell p = c;
+    p.level = c.level - 1;
+    int64_t S = side_of(p.level);
+    for (int i = 0; i < dim; ++i) p.a[i] = (int32_t)floor_to(c.a[i], S);
+    return p;
+  }
+  // leaf neighbours of the parent of a level-l cell (level l-1, across faces,
+  // edges and corners); returns offsets whose neighbour is a leaf
+  int leaf_neighbours(const Cell& p, std::array<int, 3>* out) const {
+    int m = 0;
+    int64_t S = side_of(p.level);
+    for (auto& off : f.offsets()) {
+      int64_t na[3] = {p.a[0] + off[0] * S, p.a[1] + off[1] * S, dim == 3 ? p.a[2] + off[2] * S : 0};
+      if (f.status(p.level, na) == 1) out[m++] = off;
+    }
+    return m;
+  }
+  // per-axis K-local indices in the closure of the parent's neighbour at
+  // offset `off`; false if K does not touch it
+  bool touch(const Cell& K, const Cell& P, const std::array<int, 3>& off, int lists[3][5],
+             int cnt[3]) const {
+    int64_t S = side_of(P.level), s = side_of(K.level);
+    for (int i = 0; i < dim; ++i) {
+      if (off[i] == 1) {
+        if (K.a[i] + s != P.a[i] + S) return false;
+        lists[i][0] = k;
+        cnt[i] = 1;
+      } else if (off[i] == -1) {
+        if (K.a[i] != P.a[i]) return false;
+        lists[i][0] = 0;
+        cnt[i] = 1;
+      } else {
+        for (int j = 0; j < n; ++j) lists[i][j] = j;
+        cnt[i] = n;
+      }
+    }
+    if (dim == 2) {
+      lists[2][0] = 0;
+      cnt[2] = 1;
+    }
+    return true;
+  }
+};
+
+struct HangRec {
+  int64_t start = 0;   // masters in the pools
+  int32_t nm = 0;
+  int32_t id = -1;     // hanging id (first touch), -1 until numbered
+};
+
+}  // namespace
+
+namespace {
+struct PhaseTimer {
+  bool on = std::getenv("GMG_TRACE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    auto n = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[gmg maps] %-18s %8.3f s\n", what, std::chrono::duration<double>(n - t).count());
+    t = n;
+  }
+};
+}  // namespace
+
+Maps build_maps(const Forest& f, int k, const double* coeff) {
+  PhaseTimer T;
+  Ctx C(f, k);
+  const int dim = C.dim, n = C.n, npc = C.npc;
+  Maps M;
+  M.dim = dim;
+  M.k = k;
+  M.n = n;
+  M.npc = npc;
+  M.mf = 1;
+  for (int i = 0; i < dim; ++i) M.mf *= (2 * k + 1);
+  M.own_words = (M.mf + 31) / 32;
+  M.fe = C.fe;
+  const auto& leaves = f.leaves();
+  const int64_t nl = (int64_t)leaves.size();
+  M.n_leaves = nl;
+  M.leaf_level.resize(nl);
+  M.leaf_coeff.resize(nl);
+  for (int64_t i = 0; i < nl; ++i) {
+    M.leaf_level[i] = leaves[i].c.level;
+    M.leaf_coeff[i] = coeff ? coeff[i] : 1.0;
+    if (!(M.leaf_coeff[i] > 0.0) || !std::isfinite(M.leaf_coeff[i]))
+      fail(-1, "cell coefficients must be positive and finite");
+  }
+
+  // ---------------------------------------------------------- hanging nodes
+  // a node of leaf K (level l) is hanging iff it lies in the closure of a
+  // level-(l-1) leaf N (a neighbour of K's parent) and is not a node of N;
+  // masters: N's nodes on the smallest entity holding it with nonzero
+  // weight, z-major order; weights: N's tensor Lagrange basis at the node.
+  KeyMap hang(1024);
+  std::vector<HangRec> hrec;
+  std::vector<u128> hpool_m;
+  std::vector<double> hpool_w;
+  {
+    std::array<int, 3> offs[26];
+    uint64_t last_parent = ~0ull;
+    int nn = 0;
+    for (int64_t ci = 0; ci < nl; ++ci) {
+      const Cell& K = leaves[ci].c;
+      if (K.level == 0) continue;
+      Cell P = C.parent_of(K);
+      uint64_t pk = f.key(P);
+      if (pk != last_parent) {
+        nn = C.leaf_neighbours(P, offs);
+        last_parent = pk;
+      }
+      if (nn == 0) continue;
+      uint32_t kc[3][5];
+      C.cell_codes(K, kc);
+      for (int q = 0; q < nn; ++q) {
+        const auto& off = offs[q];
+        int lists[3][5], cnt[3];
+        if (!C.touch(K, P, off, lists, cnt)) continue;
+        Cell N = P;
+        int64_t S = side_of(P.level), s = side_of(K.level);
+        for (int i = 0; i < dim; ++i) N.a[i] = (int32_t)(P.a[i] + off[i] * S);
+        uint32_t nc[3][5];
+        C.cell_codes(N, nc);
+        for (int jz = 0; jz < cnt[2]; ++jz)
+          for (int jy = 0; jy < cnt[1]; ++jy)
+            for (int jx = 0; jx < cnt[0]; ++jx) {
+              int jl[3] = {lists[0][jx], lists[1][jy], lists[2][jz]};
+              uint32_t hc[3] = {kc[0][jl[0]], kc[1][jl[1]], dim == 3 ? kc[2][jl[2]] : 0};
+              const u128 key = make_key(hc, dim);
+              if (hang.get(key) >= 0) continue;
+              // per axis: fixed N index, or varying with the N basis weights
+              int fixedJ[3] = {0, 0, 0};
+              double w[3][5];
+              bool all_fixed = true;
+              for (int i = 0; i < dim; ++i) {
+                if (off[i] == 1) {
+                  fixedJ[i] = 0;
+                } else if (off[i] == -1) {
+                  fixedJ[i] = k;
+                } else {
+                  const uint32_t kcode = kc[i][jl[i]];
+                  fixedJ[i] = -1;
+                  for (int J = 0; J < n; ++J)
+                    if (nc[i][J] == kcode) fixedJ[i] = J;
+                  if (fixedJ[i] < 0) {
+                    all_fixed = false;
+                    int b = (int)((K.a[i] - P.a[i]) / s);
+                    double xi = 0.5 * b + 0.5 * C.fe.x[jl[i]];
+                    lagrange_values(C.fe, xi, w[i]);
+                  }
+                }
+              }
+              if (all_fixed) continue;
+              int rc[3];
+              for (int i = 0; i < 3; ++i) rc[i] = (i < dim && fixedJ[i] < 0) ? n : 1;
+              HangRec r;
+              r.start = (int64_t)hpool_m.size();
+              for (int a2 = 0; a2 < rc[2]; ++a2)
+                for (int a1 = 0; a1 < rc[1]; ++a1)
+                  for (int a0 = 0; a0 < rc[0]; ++a0) {
+                    const int av[3] = {a0, a1, a2};
+                    int J[3];
+                    double ww = 1.0;
+                    for (int i = 0; i < 3; ++i) {
+                      if (i < dim && fixedJ[i] < 0) {
+                        J[i] = av[i];
+                        ww *= w[i][J[i]];
+                      } else {
+                        J[i] = i < dim ? fixedJ[i] : 0;
+                      }
+                    }
+                    uint32_t mc[3] = {nc[0][J[0]], nc[1][J[1]], dim == 3 ? nc[2][J[2]] : 0};
+                    hpool_m.push_back(make_key(mc, dim));
+                    hpool_w.push_back(ww);
+                  }
+              r.nm = (int)((int64_t)hpool_m.size() - r.start);
+              hang.get_or_insert(key, (int32_t)hrec.size());
+              hrec.push_back(r);
+            }
+      }
+    }
+  }
+
+  T.mark("hanging");
+  // ---------------------------------------------------------- leaf numbering
+  KeyMap dofs(size_t(nl) * (dim == 3 ? k * k * k : k * k) + 64);
+  std::vector<u128> dof_keys;
+  std::vector<int8_t> dof_minlevel;
+  std::vector<int32_t> hang_order;
+  M.leaf_cellmap.resize(size_t(nl) * npc);
+  {
+    int32_t next = 0;
+    for (int64_t ci = 0; ci < nl; ++ci) {
+      const Cell& K = leaves[ci].c;
+      uint32_t kc[3][5];
+      C.cell_codes(K, kc);
+      for (int li = 0; li < npc; ++li) {
+        u128 key = C.node_key(kc, li);
+        int32_t h = hrec.empty() ? -1 : hang.get(key);
+        if (h >= 0) {
+          if (hrec[h].id < 0) {
+            hrec[h].id = (int32_t)hang_order.size();
+            hang_order.push_back(h);
+          }
+          M.leaf_cellmap[size_t(ci) * npc + li] = -(hrec[h].id + 1);
+          continue;
+        }
+        int32_t id = dofs.get_or_insert(key, next);
+        if (id == next) {
+          ++next;
+          dof_keys.push_back(key);
+          dof_minlevel.push_back(K.level);
+        } else if (K.level < dof_minlevel[id]) {
+          dof_minlevel[id] = K.level;
+        }
+        M.leaf_cellmap[size_t(ci) * npc + li] = id;
+      }
+    }
+    M.n_dofs = next;
+  }
+  T.mark("leaf numbering");
+  M.n_hanging = (int64_t)hang_order.size();
+  M.dirichlet.resize(M.n_dofs);
+  for (int64_t i = 0; i < M.n_dofs; ++i) M.dirichlet[i] = C.on_boundary(dof_keys[i]) ? 1 : 0;
+  M.con_off.assign(1, 0);
+  for (int32_t h : hang_order) {
+    const HangRec& r = hrec[h];
+    double sw = 0.0;
+    for (int q = 0; q < r.nm; ++q) {
+      int32_t id = dofs.get(hpool_m[r.start + q]);
+      if (id < 0) fail(-8, "constraint master is not a DoF (constraint chain)");
+      M.con_mas.push_back(id);
+      M.con_w.push_back(hpool_w[r.start + q]);
+      sw += hpool_w[r.start + q];
+    }
+    if (std::fabs(sw - 1.0) > 1e-12) fail(-8, "constraint weights do not sum to one");
+    M.con_off.push_back((int64_t)M.con_mas.size());
+  }
+  dofs = KeyMap(16);
+  T.mark("dirichlet+constraints");
+
+  // ---------------------------------------------------------- levels
+  const int L = f.max_level();
+  M.levels.resize(L + 1);
+  // bucket leaf DoFs by the level that owns them in the hierarchy
+  std::vector<int64_t> bstart(L + 2, 0);
+  for (int64_t i = 0; i < M.n_dofs; ++i) ++bstart[dof_minlevel[i] + 1];
+  for (int l = 0; l <= L; ++l) bstart[l + 1] += bstart[l];
+  std::vector<int64_t> bucket(M.n_dofs);
+  {
+    std::vector<int64_t> pos(bstart.begin(), bstart.end() - 1);
+    for (int64_t i = 0; i < M.n_dofs; ++i) bucket[pos[dof_minlevel[i]]++] = i;
+  }
+  M.copy_level.resize(M.n_dofs);
+  M.copy_index.resize(M.n_dofs);
+  KeyMap lmap(16);
+  for (int l = 0; l <= L; ++l) {
+    LevelData& D = M.levels[l];
+    D.level = l;
+    {
+      int64_t s = side_of(l);
+      uint64_t last = ~0ull;
+      for (int64_t li = 0; li < nl; ++li) {
+        const Cell& c = leaves[li].c;
+        if (c.level < l) continue;
+        Cell a = c;
+        a.level = (int8_t)l;
+        for (int i = 0; i < dim; ++i) a.a[i] = (int32_t)floor_to(c.a[i], s);
+        uint64_t kk = f.key(a);
+        if (kk == last) continue;
+        last = kk;
+        D.cells.push_back(a);
+        D.keys.push_back(kk);
+        D.leaf_index.push_back(c.level == l ? (int32_t)li : -1);
+      }
+    }
+    D.n_cells = (int64_t)D.cells.size();
+    lmap.reset(size_t(D.n_cells) * (dim == 3 ? k * k * k : k * k) + 64);
+    D.cellmap.resize(size_t(D.n_cells) * npc);
+    int32_t next = 0;
+    std::vector<u128> lkeys;
+    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+      uint32_t kc[3][5];
+      C.cell_codes(D.cells[ci], kc);
+      for (int li = 0; li < npc; ++li) {
+        u128 key = C.node_key(kc, li);
+        int32_t id = lmap.get_or_insert(key, next);
+        if (id == next) {
+          ++next;
+          lkeys.push_back(key);
+        }
+        D.cellmap[size_t(ci) * npc + li] = id;
+      }
+    }
+    D.n_dofs = next;
+    D.flags.assign(D.n_dofs, kFlagS);
+    if (l >= 1) {
+      std::array<int, 3> offs[26];
+      uint64_t last_parent = ~0ull;
+      int nn = 0;
+      for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+        const Cell& K = D.cells[ci];
+        Cell P = C.parent_of(K);
+        uint64_t pk = f.key(P);
+        if (pk != last_parent) {
+          nn = C.leaf_neighbours(P, offs);
+          last_parent = pk;
+        }
+        for (int q = 0; q < nn; ++q) {
+          int lists[3][5], cnt[3];
+          if (!C.touch(K, P, offs[q], lists, cnt)) continue;
+          for (int jz = 0; jz < cnt[2]; ++jz)
+            for (int jy = 0; jy < cnt[1]; ++jy)
+              for (int jx = 0; jx < cnt[0]; ++jx) {
+                int li = lists[0][jx] + n * (lists[1][jy] + n * lists[2][jz]);
+                D.flags[D.cellmap[size_t(ci) * npc + li]] = kFlagI;
+              }
+        }
+      }
+    }
+    for (int64_t i = 0; i < D.n_dofs; ++i)
+      if (C.on_boundary(lkeys[i])) D.flags[i] = kFlagD;
+    for (int64_t i = 0; i < D.n_dofs; ++i)
+      if (D.flags[i] == kFlagI) D.ilist.push_back((int32_t)i);
+    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+      for (int li = 0; li < npc; ++li)
+        if (D.flags[D.cellmap[size_t(ci) * npc + li]] == kFlagI) {
+          D.edge_cells.push_back((int32_t)ci);
+          break;
+        }
+    }
+    // copy map for the leaf DoFs owned by this level
+    for (int64_t b = bstart[l]; b < bstart[l + 1]; ++b) {
+      int64_t i = bucket[b];
+      int32_t id = lmap.get(dof_keys[i]);
+      if (id < 0 || D.flags[id] == kFlagI) fail(-8, "copy map: leaf DoF not an S/D node of its level");
+      M.copy_level[i] = (int8_t)l;
+      M.copy_index[i] = id;
+    }
+    T.mark("level numbering");
+    // families and transfer maps
+    if (l >= 1) {
+      const LevelData& Pl = M.levels[l - 1];
+      const int nf = 1 << dim;
+      if (D.n_cells % nf) fail(-8, "level cells do not come in sibling families");
+      D.n_fam = D.n_cells / nf;
+      const int m2 = 2 * k + 1;
+      D.parent.resize(D.n_fam);
+      D.famap.assign(size_t(D.n_fam) * M.mf, -1);
+      D.own.assign(size_t(D.n_fam) * M.own_words, 0u);
+      std::vector<int32_t> first(D.n_dofs, -1);
+      for (int64_t fi = 0; fi < D.n_fam; ++fi) {
+        Cell P = C.parent_of(D.cells[fi * nf]);
+        uint64_t pk = f.key(P);
+        auto it = std::lower_bound(Pl.keys.begin(), Pl.keys.end(), pk);
+        if (it == Pl.keys.end() || *it != pk) fail(-8, "family parent not found");
+        D.parent[fi] = (int32_t)(it - Pl.keys.begin());
+        for (int cid = 0; cid < nf; ++cid) {
+          const Cell& ch = D.cells[fi * nf + cid];
+          for (int i = 0; i < dim; ++i)
+            if (ch.a[i] != P.a[i] + ((cid >> i) & 1) * side_of(l))
+              fail(-8, "family children out of order");
+          for (int li = 0; li < npc; ++li) {
+            int jx = li % n, jy = (li / n) % n, jz = li / (n * n);
+            int fx = (cid & 1) * k + jx, fy = ((cid >> 1) & 1) * k + jy;
+            int fz = dim == 3 ? ((cid >> 2) & 1) * k + jz : 0;
+            int fidx = fx + m2 * (fy + m2 * fz);
+            int32_t v = D.cellmap[size_t(fi * nf + cid) * npc + li];
+            int32_t& slot = D.famap[size_t(fi) * M.mf + fidx];
+            if (slot >= 0 && slot != v) fail(-8, "inconsistent family map");
+            slot = v;
+          }
+        }
+        for (int q = 0; q < M.mf; ++q) {
+          int32_t v = D.famap[size_t(fi) * M.mf + q];
+          if (first[v] < 0) {
+            first[v] = (int32_t)fi;
+            D.own[size_t(fi) * M.own_words + q / 32] |= 1u << (q % 32);
+          }
+        }
+        // complete-layer rule: parent nodes touched by the transfer are S or D
+        for (int li = 0; li < npc; ++li)
+          if (Pl.flags[Pl.cellmap[size_t(D.parent[fi]) * npc + li]] == kFlagI)
+            fail(-8, "complete-layer rule violated");
+      }
+    }
+  }
+  T.mark("levels done");
+  // cell coefficients: leaves from the input, other cells the mean of their
+  // children (Sec. 4.3 coefficient, applied on every level)
+  for (int l = L; l >= 0; --l) {
+    LevelData& D = M.levels[l];
+    D.coeff.assign(D.n_cells, 0.0);
+    for (int64_t c = 0; c < D.n_cells; ++c)
+      if (D.leaf_index[c] >= 0) D.coeff[c] = M.leaf_coeff[D.leaf_index[c]];
+    if (l < L) {
+      const LevelData& F = M.levels[l + 1];
+      const int nf = 1 << dim;
+      for (int64_t fi = 0; fi < F.n_fam; ++fi) {
+        double s = 0.0;
+        for (int c = 0; c < nf; ++c) s += F.coeff[fi * nf + c];
+        D.coeff[F.parent[fi]] = s / nf;
+      }
+    }
+  }
+  return M;
+}
+
+}  // namespace gmg

@@ -1,0 +1,50 @@
+// DoF maps of the leaf mesh and of the level meshes (Sec. 2.3, Fig. 1):
+// node identity, Dirichlet nodes, hanging-node constraints, first-touch
+// numbering, S/I/D level splitting, copy map leaf -> level, and sibling
+// family maps used by the transfer operators (Sec. 2.2).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "fe1d.hpp"
+#include "forest.hpp"
+
+namespace gmg {
+
+enum : uint8_t { kFlagS = 0, kFlagI = 1, kFlagD = 2 };
+
+struct LevelData {
+  int level = 0;
+  int64_t n_cells = 0, n_dofs = 0, n_fam = 0;
+  std::vector<Cell> cells;            // canonical order
+  std::vector<uint64_t> keys;         // forest keys of the cells
+  std::vector<int32_t> leaf_index;    // leaf index of a cell that is a leaf, else -1
+  std::vector<int32_t> cellmap;       // [n_cells * npc] level DoF ids
+  std::vector<uint8_t> flags;         // [n_dofs]
+  std::vector<int32_t> parent;        // [n_fam] parent index among level-1 cells
+  std::vector<int32_t> famap;         // [n_fam * mf] level DoF ids of the family nodes
+  std::vector<uint32_t> own;          // [n_fam * own_words] family owns node bit
+  std::vector<double> coeff;          // [n_cells]
+  std::vector<int32_t> edge_cells;    // cells having an I node
+  std::vector<int32_t> ilist;         // I node ids
+};
+
+struct Maps {
+  int dim = 0, k = 0, n = 0, npc = 0, mf = 0, own_words = 0;
+  FE1D fe;
+  int64_t n_leaves = 0, n_dofs = 0, n_hanging = 0;
+  std::vector<int32_t> leaf_cellmap;  // [n_leaves * npc] DoF id or -(h+1)
+  std::vector<int8_t> leaf_level;
+  std::vector<double> leaf_coeff;
+  std::vector<uint8_t> dirichlet;     // [n_dofs]
+  std::vector<int64_t> con_off;       // [n_hanging+1]
+  std::vector<int32_t> con_mas;
+  std::vector<double> con_w;
+  std::vector<int8_t> copy_level;     // [n_dofs]
+  std::vector<int32_t> copy_index;    // [n_dofs]
+  std::vector<LevelData> levels;
+};
+
+Maps build_maps(const Forest& f, int k, const double* coeff);
+
+}  // namespace gmg

@@ -1,0 +1,89 @@
+// Instantiation of the kernel table for one (dim, k); included by inst_*.hip.
+#pragma once
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace gmg {
+
+template <typename T>
+inline dev::Mats<T> to_dev(const MatsH<T>& h) {
+  dev::Mats<T> m;
+  for (int i = 0; i < 25; ++i) {
+    m.M[i] = h.M[i];
+    m.K[i] = h.K[i];
+  }
+  for (int i = 0; i < 45; ++i) m.E[i] = h.E[i];
+  return m;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + dev::kBlock - 1) / dev::kBlock); }
+
+template <int DIM, int K>
+struct Inst {
+  static constexpr int N = K + 1;
+
+  template <typename T>
+  static void apply(const LevelView& v, const T* x, T* y, const MatsH<T>& m, hipStream_t s) {
+    if (!v.n_cells) return;
+    hipLaunchKernelGGL((dev::cell_apply<DIM, N, T, 0, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock), 0, s,
+                       v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.scale, v.scale0, x,
+                       (const T*)nullptr, y, (T*)nullptr, (int64_t)0, (const uint8_t*)nullptr, T(1), to_dev(m));
+  }
+  template <typename T>
+  static void edge(const LevelView& v, const T* x, T* y, T sign, const MatsH<T>& m, hipStream_t s) {
+    if (!v.n_edge) return;
+    hipLaunchKernelGGL((dev::cell_apply<DIM, N, T, 2, false>), dim3(grid_for(v.n_edge)), dim3(dev::kBlock), 0, s,
+                       v.n_edge, v.edge, v.n_cells, v.cmap, v.scale, v.scale0, x, (const T*)nullptr, y,
+                       (T*)nullptr, (int64_t)0, v.flags, sign, to_dev(m));
+  }
+  template <typename T>
+  static void prolong(const LevelView& f, const LevelView& c, const T* xc, T* xf, const MatsH<T>& m,
+                      hipStream_t s) {
+    if (!f.n_fam) return;
+    hipLaunchKernelGGL((dev::prolongate<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s, f.n_fam,
+                       f.famap, f.own, f.parent, c.n_cells, c.cmap, xc, xf, to_dev(m));
+  }
+  template <typename T>
+  static void restrict_(const LevelView& f, const LevelView& c, const T* g, T* t, T* dc, const MatsH<T>& m,
+                        hipStream_t s) {
+    if (!f.n_fam) return;
+    hipLaunchKernelGGL((dev::restrict_residual<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s,
+                       f.n_fam, f.famap, f.own, f.parent, c.n_cells, c.cmap, g, t, f.flags, dc, to_dev(m));
+  }
+  static void leaf_apply(const LeafView& v, const double* x, const double* xh, double* y, double* yh, bool mass,
+                         const MatsH<double>& m, hipStream_t s) {
+    if (!v.n_cells) return;
+    if (mass)
+      hipLaunchKernelGGL((dev::cell_apply<DIM, N, double, 1, true>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
+                         0, s, v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.mscale, 1.0, x, xh, y, yh,
+                         v.n_dofs, (const uint8_t*)nullptr, 1.0, to_dev(m));
+    else
+      hipLaunchKernelGGL((dev::cell_apply<DIM, N, double, 1, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
+                         0, s, v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.scale, 1.0, x, xh, y, yh,
+                         v.n_dofs, (const uint8_t*)nullptr, 1.0, to_dev(m));
+  }
+  static void diag(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
+    if (!v.n_cells) return;
+    hipLaunchKernelGGL((dev::cell_diag<DIM, N>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock), 0, s, v.n_cells,
+                       v.cmap, v.scale, v.scale0, d, to_dev(m));
+  }
+
+  static const KernelTable* table() {
+    static KernelTable t = {
+        {&apply<float>, &edge<float>, &prolong<float>, &restrict_<float>},
+        {&apply<double>, &edge<double>, &prolong<double>, &restrict_<double>},
+        &leaf_apply,
+        &diag,
+    };
+    return &t;
+  }
+};
+
+}  // namespace gmg
+
+#define GMG_INSTANTIATE(DIM, K)                                                        \
+  namespace {                                                                          \
+  struct Reg##DIM##K {                                                                 \
+    Reg##DIM##K() { gmg::register_table(DIM, K, gmg::Inst<DIM, K>::table()); }         \
+  } reg_##DIM##K;                                                                      \
+  }

@@ -1,0 +1,590 @@
+// HIP kernels for gfx950 (MI355X).  Matrix-free tensor-product operators on
+// axis-aligned cells (Sec. 3.2 matrix-free evaluation, here re-designed for
+// 64-wide wavefronts: one lane per cell, the whole cell tensor in registers,
+// coalesced structure-of-arrays index maps, scatter by hardware float
+// atomics), Chebyshev-Jacobi update (Sec. 4.1), family transfer operators
+// (Sec. 2.2) and CG vector kernels (FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gmg {
+namespace dev {
+
+constexpr int kBlock = 256;
+
+// 1D reference matrices passed by value (kernel arguments, read as scalars)
+template <typename T>
+struct Mats {
+  T M[25];
+  T K[25];
+  T E[45];   // (2k+1) x (k+1), row-major
+};
+
+// Consecutive hardware dispatch goes round-robin over the 8 XCDs, each with
+// its own L2.  Give each XCD one contiguous range of the logical block space
+// so that neighbouring cells (which share nodes) hit the same L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+  return x * q + (x < r ? x : r) + i;
+}
+__device__ __forceinline__ int64_t xcd_tid() { return xcd_block() * blockDim.x + threadIdx.x; }
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// ------------------------------------------------------------------ sweeps
+// 1D contraction along the axis with stride ST of an array of extent
+// N_IN along that axis: out[i] = sum_j A[i*N_IN + j] in[j].
+// The tensor of a cell is stored x fastest.
+
+// y = (sum over directions of K in that direction, M elsewhere) x, 3D
+template <int N, typename T>
+__device__ __forceinline__ void laplace3(const Mats<T>& m, const T (&u)[N * N * N], T (&out)[N * N * N]) {
+  T a[N * N * N], b[N * N * N];
+#pragma unroll
+  for (int zy = 0; zy < N * N; ++zy) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        sa += m.M[i * N + j] * u[zy * N + j];
+        sb += m.K[i * N + j] * u[zy * N + j];
+      }
+      a[zy * N + i] = sa;
+      b[zy * N + i] = sb;
+    }
+  }
+  // y direction: c = M_y a, e = K_y a + M_y b (in place per line)
+#pragma unroll
+  for (int z = 0; z < N; ++z) {
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      T la[N], lb[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        la[j] = a[(z * N + j) * N + x];
+        lb[j] = b[(z * N + j) * N + x];
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T sc = 0, se = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          sc += m.M[i * N + j] * la[j];
+          se += m.K[i * N + j] * la[j] + m.M[i * N + j] * lb[j];
+        }
+        a[(z * N + i) * N + x] = sc;
+        b[(z * N + i) * N + x] = se;
+      }
+    }
+  }
+  // z direction: out = M_z e + K_z c
+#pragma unroll
+  for (int yx = 0; yx < N * N; ++yx) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += m.M[i * N + j] * b[j * N * N + yx] + m.K[i * N + j] * a[j * N * N + yx];
+      out[i * N * N + yx] = s;
+    }
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void laplace2(const Mats<T>& m, const T (&u)[N * N], T (&out)[N * N]) {
+  T a[N * N], b[N * N];
+#pragma unroll
+  for (int y = 0; y < N; ++y)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        sa += m.M[i * N + j] * u[y * N + j];
+        sb += m.K[i * N + j] * u[y * N + j];
+      }
+      a[y * N + i] = sa;
+      b[y * N + i] = sb;
+    }
+#pragma unroll
+  for (int x = 0; x < N; ++x)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += m.K[i * N + j] * a[j * N + x] + m.M[i * N + j] * b[j * N + x];
+      out[i * N + x] = s;
+    }
+}
+
+// mass: out = (M x M [x M]) u
+template <int DIM, int N, typename T>
+__device__ __forceinline__ void mass_nd(const Mats<T>& m, T* u, T* out) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  T a[NP];
+#pragma unroll
+  for (int r = 0; r < NP / N; ++r)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += m.M[i * N + j] * u[r * N + j];
+      a[r * N + i] = s;
+    }
+  // y
+#pragma unroll
+  for (int z = 0; z < NP / (N * N); ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.M[i * N + j] * a[(z * N + j) * N + x];
+        out[(z * N + i) * N + x] = s;
+      }
+  if (DIM == 3) {
+#pragma unroll
+    for (int yx = 0; yx < N * N; ++yx) {
+      T l[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) l[j] = out[j * N * N + yx];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.M[i * N + j] * l[j];
+        out[i * N * N + yx] = s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ cell operator
+// MODE 0: plain gather/scatter (level operator, smoother and residual).
+// MODE 1: leaf operator: ids >= n_main address the hanging-node buffers.
+// MODE 2: edge operator on a cell subset: input restricted to I nodes,
+//         output to S nodes (y += sign * A^{SI} x^I).
+// MASS: mass matrix instead of the Laplacian.
+template <int DIM, int N, typename T, int MODE, bool MASS>
+__global__ void __launch_bounds__(kBlock) cell_apply(
+    int64_t n_items, const int32_t* __restrict__ list, int64_t n_cells,
+    const int32_t* __restrict__ cmap, const double* __restrict__ scale, double scale0,
+    const T* __restrict__ x, const T* __restrict__ xh, T* __restrict__ y, T* __restrict__ yh,
+    int64_t n_main, const uint8_t* __restrict__ flags, T sign, Mats<T> m) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  const int64_t t = xcd_tid();
+  if (t >= n_items) return;
+  const int64_t c = MODE == 2 ? (int64_t)list[t] : t;
+  int32_t id[NP];
+  T u[NP], v[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) id[j] = cmap[(int64_t)j * n_cells + c];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int32_t g = id[j];
+    if (MODE == 1) {
+      u[j] = g < n_main ? x[g] : xh[g - n_main];
+    } else if (MODE == 2) {
+      u[j] = flags[g] == 1 ? x[g] : T(0);
+    } else {
+      u[j] = x[g];
+    }
+  }
+  if (MASS) {
+    mass_nd<DIM, N, T>(m, u, v);
+  } else if (DIM == 3) {
+    laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(v));
+  } else {
+    laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
+  }
+  const T s = T(scale ? scale[c] : scale0) * sign;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int32_t g = id[j];
+    if (MODE == 1) {
+      if (g < n_main)
+        atomic_add(&y[g], s * v[j]);
+      else
+        atomic_add(&yh[g - n_main], s * v[j]);
+    } else if (MODE == 2) {
+      if (flags[g] == 0) atomic_add(&y[g], s * v[j]);
+    } else {
+      atomic_add(&y[g], s * v[j]);
+    }
+  }
+}
+
+// diagonal of the cell Laplacian, accumulated per node (FP64)
+template <int DIM, int N>
+__global__ void __launch_bounds__(kBlock) cell_diag(int64_t n_cells, const int32_t* __restrict__ cmap,
+                                                    const double* __restrict__ scale, double scale0,
+                                                    double* __restrict__ diag, Mats<double> m) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  const int64_t c = xcd_tid();
+  if (c >= n_cells) return;
+  const double s = scale ? scale[c] : scale0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int jx = j % N, jy = (j / N) % N, jz = j / (N * N);
+    double mx = m.M[jx * N + jx], my = m.M[jy * N + jy], kx = m.K[jx * N + jx], ky = m.K[jy * N + jy];
+    double v;
+    if (DIM == 3) {
+      double mz = m.M[jz * N + jz], kz = m.K[jz * N + jz];
+      v = kx * my * mz + mx * ky * mz + mx * my * kz;
+    } else {
+      v = kx * my + mx * ky;
+    }
+    atomic_add(&diag[cmap[(int64_t)j * n_cells + c]], s * v);
+  }
+}
+
+template <typename T>
+__global__ void make_dinv(int64_t n, const double* __restrict__ diag, const uint8_t* __restrict__ flags,
+                          T* __restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dinv[i] = flags[i] == 0 ? T(1.0 / diag[i]) : T(0);
+}
+
+// ------------------------------------------------------------------ transfer
+// Family of 2^d siblings: (2k+1)^d fine nodes, parent (k+1)^d nodes.
+// Prolongation x_f += E^{x d} x_c on the nodes this family owns; each fine
+// node is owned by exactly one family, so the global operator is applied
+// once per node without atomics.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) prolongate(
+    int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
+    const int32_t* __restrict__ parent, int64_t n_pcells, const int32_t* __restrict__ pmap,
+    const T* __restrict__ xc, T* __restrict__ xf, Mats<T> m) {
+  constexpr int N = K + 1, M2 = 2 * K + 1;
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
+  constexpr int NW = (MF + 31) / 32;
+  const int64_t f = xcd_tid();
+  if (f >= n_fam) return;
+  const int64_t p = parent[f];
+  T u[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) u[j] = xc[pmap[(int64_t)j * n_pcells + p]];
+  // x: N -> M2
+  constexpr int R1 = NP / N;
+  T a[R1 * M2];
+#pragma unroll
+  for (int r = 0; r < R1; ++r)
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += m.E[i * N + j] * u[r * N + j];
+      a[r * M2 + i] = s;
+    }
+  // y: N -> M2 over rows (z, x)
+  constexpr int NZ = DIM == 3 ? N : 1;
+  T b[NZ * M2 * M2];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < M2; ++x)
+#pragma unroll
+      for (int i = 0; i < M2; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.E[i * N + j] * a[(z * N + j) * M2 + x];
+        b[(z * M2 + i) * M2 + x] = s;
+      }
+  uint32_t ow[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) ow[w] = own[(int64_t)w * n_fam + f];
+  if (DIM == 2) {
+#pragma unroll
+    for (int q = 0; q < MF; ++q)
+      if ((ow[q / 32] >> (q % 32)) & 1u) {
+        const int32_t g = famap[(int64_t)q * n_fam + f];
+        xf[g] += b[q];
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < M2; ++i)
+#pragma unroll
+      for (int yx = 0; yx < M2 * M2; ++yx) {
+        const int q = i * M2 * M2 + yx;
+        if ((ow[q / 32] >> (q % 32)) & 1u) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) s += m.E[i * N + j] * b[j * M2 * M2 + yx];
+          const int32_t g = famap[(int64_t)q * n_fam + f];
+          xf[g] += s;
+        }
+      }
+  }
+}
+
+// Residual and restriction fused: r = g - t on owned free fine nodes (t is
+// reset to zero for the next operator accumulation), then
+// d_c += (E^T)^{x d} r scattered to the parent's nodes.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) restrict_residual(
+    int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
+    const int32_t* __restrict__ parent, int64_t n_pcells, const int32_t* __restrict__ pmap,
+    const T* __restrict__ g, T* __restrict__ t, const uint8_t* __restrict__ flags, T* __restrict__ dc,
+    Mats<T> m) {
+  constexpr int N = K + 1, M2 = 2 * K + 1;
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
+  constexpr int NW = (MF + 31) / 32;
+  constexpr int NZ = DIM == 3 ? M2 : 1;
+  const int64_t f = xcd_tid();
+  if (f >= n_fam) return;
+  uint32_t ow[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) ow[w] = own[(int64_t)w * n_fam + f];
+  // x contraction while loading: a[(z, y), J] = sum_i E[i][J] r[z, y, i]
+  T a[NZ * M2 * N];
+#pragma unroll
+  for (int zy = 0; zy < NZ * M2; ++zy) {
+    T r[M2];
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      const int q = zy * M2 + i;
+      r[i] = 0;
+      if ((ow[q / 32] >> (q % 32)) & 1u) {
+        const int32_t gid = famap[(int64_t)q * n_fam + f];
+        if (flags[gid] != 2) r[i] = g[gid] - t[gid];
+        t[gid] = 0;
+      }
+    }
+#pragma unroll
+    for (int J = 0; J < N; ++J) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * r[i];
+      a[zy * N + J] = s;
+    }
+  }
+  // y contraction
+  T b[NZ * N * N];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x)
+#pragma unroll
+      for (int J = 0; J < N; ++J) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * a[(z * M2 + i) * N + x];
+        b[(z * N + J) * N + x] = s;
+      }
+  const int64_t p = parent[f];
+  if (DIM == 2) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) atomic_add(&dc[pmap[(int64_t)j * n_pcells + p]], b[j]);
+  } else {
+#pragma unroll
+    for (int J = 0; J < N; ++J)
+#pragma unroll
+      for (int yx = 0; yx < N * N; ++yx) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * b[i * N * N + yx];
+        atomic_add(&dc[pmap[(int64_t)(J * N * N + yx) * n_pcells + p]], s);
+      }
+  }
+}
+
+// ------------------------------------------------------------------ vectors
+template <typename T>
+__global__ void fill(int64_t n, T* __restrict__ p, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void zero_list(int64_t n, const int32_t* __restrict__ list, T* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[list[i]] = T(0);
+}
+
+// Chebyshev step (Sec. 4.1 smoother): d = c1 d + c2 D^{-1} (g - t); x += d;
+// t = 0.  zero_start: d = c2 D^{-1} g; x = d (first step from x = 0).
+// Rows that are not smoothed have D^{-1} = 0 and keep d = 0.
+template <typename T>
+__global__ void cheb_step(int64_t n, T* __restrict__ x, T* __restrict__ d, const T* __restrict__ g,
+                          T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2, int zero_start) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T di = dinv[i];
+  if (zero_start) {
+    const T v = c2 * di * g[i];
+    d[i] = v;
+    x[i] = v;
+  } else {
+    const T v = c1 * d[i] + c2 * di * (g[i] - t[i]);
+    d[i] = v;
+    x[i] += v;
+    t[i] = T(0);
+  }
+}
+
+template <typename T>
+__global__ void copy_to_levels(int64_t n, const int32_t* __restrict__ copy, const double* __restrict__ r,
+                               T* __restrict__ lg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lg[copy[i]] = T(r[i]);
+}
+
+template <typename T>
+__global__ void copy_from_levels(int64_t n, const int32_t* __restrict__ copy, const T* __restrict__ lx,
+                                 double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = double(lx[copy[i]]);
+}
+
+// exact coarse solve: x0[S] = A0^{-1} d0[S] (FP64), other rows of x0 zero
+template <typename T>
+__global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, const double* __restrict__ ainv,
+                                                       const int32_t* __restrict__ idx, const T* __restrict__ d0,
+                                                       T* __restrict__ x0) {
+  extern __shared__ double sd[];
+  for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) x0[i] = T(0);
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) sd[i] = double(d0[idx[i]]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < n0; ++j) s += ainv[(int64_t)i * n0 + j] * sd[j];
+    x0[idx[i]] = T(s);
+  }
+}
+
+#ifdef GMG_SOLVER_TU
+// Non-template kernels: compiled in the solver translation unit only.
+// hanging nodes: xh[h] = sum_j w_hj x[m_hj]; condensation y[m_hj] += w_hj yh[h]
+__global__ void hang_fill(int64_t H, const int64_t* __restrict__ off, const int32_t* __restrict__ mas,
+                          const double* __restrict__ w, const double* __restrict__ x, double* __restrict__ xh) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  double s = 0.0;
+  for (int64_t p = off[h]; p < off[h + 1]; ++p) s += w[p] * x[mas[p]];
+  xh[h] = s;
+}
+
+__global__ void hang_condense(int64_t H, const int64_t* __restrict__ off, const int32_t* __restrict__ mas,
+                              const double* __restrict__ w, const double* __restrict__ yh, double* __restrict__ y) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  const double v = yh[h];
+  for (int64_t p = off[h]; p < off[h + 1]; ++p) atomic_add(&y[mas[p]], w[p] * v);
+}
+
+// ------------------------------------------------------------------ CG (FP64)
+constexpr int kDotBlocks = 1024;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+  return s;
+}
+
+// deterministic two-stage dot: fixed grid, fixed order
+__global__ void __launch_bounds__(kBlock) dot_partial(int64_t n, const double* __restrict__ a,
+                                                      const double* __restrict__ b, double* __restrict__ part) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+enum ScalarSlot { kRho = 0, kRhoOld, kAlpha, kBeta, kPq, kRr, kBb, kFirst, kNumScalars };
+
+// sums the partials (fixed order) and updates the CG scalars
+__global__ void __launch_bounds__(kBlock) cg_scalars(int nparts, const double* __restrict__ part,
+                                                     double* __restrict__ sc, int op) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x != 0) return;
+  if (op == 0) {  // rho = r.z ; beta
+    sc[kBeta] = sc[kFirst] != 0.0 ? 0.0 : v / sc[kRhoOld];
+    sc[kRho] = v;
+  } else if (op == 1) {  // pq = p.Ap ; alpha
+    sc[kPq] = v;
+    sc[kAlpha] = sc[kRho] / v;
+  } else if (op == 2) {  // rr ; shift rho
+    sc[kRr] = v;
+    sc[kRhoOld] = sc[kRho];
+    sc[kFirst] = 0.0;
+  } else if (op == 3) {
+    sc[kBb] = v;
+  }
+}
+
+__global__ void update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z,
+                         const double* __restrict__ sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = sc[kBeta];
+  if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+// x += alpha p ; r -= alpha q ; partial sums of r.r with the dot's grid
+__global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ sc, double* __restrict__ part) {
+  const double alpha = sc[kAlpha];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void copy_vec(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// eigenvalue-estimate helpers (FP64, level vectors)
+__global__ void eig_init(int64_t n, const uint8_t* __restrict__ flags, const double* __restrict__ dinv,
+                         double* __restrict__ r, double* __restrict__ z, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = flags[i] == 0 ? double(i % 12) - 5.5 : 0.0;
+  r[i] = v;
+  z[i] = dinv[i] * v;
+  p[i] = dinv[i] * v;
+}
+
+__global__ void axpy_zr(int64_t n, double alpha, const double* __restrict__ q, double* __restrict__ r,
+                        const double* __restrict__ dinv, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ri = r[i] - alpha * q[i];
+  r[i] = ri;
+  z[i] = dinv[i] * ri;
+}
+
+__global__ void xpby(int64_t n, const double* __restrict__ z, double beta, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+#endif  // GMG_SOLVER_TU
+
+}  // namespace dev
+}  // namespace gmg

@@ -1,0 +1,70 @@
+// Problem state: host maps, device views into the caller's workspace, and
+// the V-cycle / CG drivers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/gmg.h"
+#include "dispatch.hpp"
+#include "host/maps.hpp"
+
+namespace gmg {
+
+struct DevLevel {
+  LevelView v;
+  int64_t off = 0;     // offset in the concatenated level vectors
+  int64_t n_S = 0, n_I = 0;
+  const int32_t* ilist = nullptr;
+  double lam = 1.0;    // lambda_max estimate of D^{-1} A^S
+};
+
+struct Problem {
+  gmg_options opt{};
+  Maps maps;
+  const KernelTable* kt = nullptr;
+  MatsH<float> m32{};
+  MatsH<double> m64{};
+
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_need = 0;     // workspace bytes, fixed at creation
+  bool bound = false;
+  int device = -1;
+
+  std::vector<DevLevel> lv;
+  LeafView leaf;
+  int64_t n_total = 0;   // sum of level DoFs
+  int64_t n_dir = 0;
+  const int32_t* dir = nullptr;
+  const int64_t* con_off = nullptr;
+  const int32_t* con_mas = nullptr;
+  const double* con_w = nullptr;
+  const int32_t* copy = nullptr;
+  void *lx = nullptr, *lg = nullptr, *lt = nullptr, *ld = nullptr, *ldinv = nullptr;
+  double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
+  double *xh = nullptr, *yh = nullptr;
+  double *scal = nullptr, *part = nullptr;
+  double* ainv = nullptr;
+  const int32_t* cidx = nullptr;
+  int n0 = 0;
+  double* eig = nullptr;   // 5 FP64 vectors of the largest level
+  int64_t max_level_dofs = 0;
+  double* host = nullptr;  // pinned scalars
+  hipGraphExec_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+  double timing[3] = {0, 0, 0};
+  std::vector<hipEvent_t> ev;
+
+  ~Problem();
+};
+
+size_t plan_workspace(Problem& P, char* base);
+void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s);
+void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s);
+void vcycle(Problem& P, const double* r, double* z, hipStream_t s);
+int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s);
+void set_constant(double* p, int64_t n, double v, hipStream_t s);
+void apply_level_hook(Problem& P, int level, int variant, const void* x, void* y, hipStream_t s);
+
+}  // namespace gmg

@@ -1,0 +1,639 @@
+// Device setup, V-cycle with local smoothing (Alg. 2, Sec. 2.3) and
+// FP64 preconditioned CG (Sec. 1, 4.1) on one GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#define GMG_SOLVER_TU
+#include "kernels.hpp"
+#include "problem.hpp"
+
+namespace gmg {
+
+#define HIPCHECK(x)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) fail(GMG_E_HIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- table registry
+namespace {
+const KernelTable* g_tables[2][5] = {};
+}
+void register_table(int dim, int k, const KernelTable* t) { g_tables[dim - 2][k] = t; }
+const KernelTable* kernel_table(int dim, int k) {
+  if (dim < 2 || dim > 3 || k < 1 || k > 4) return nullptr;
+  return g_tables[dim - 2][k];
+}
+
+Problem::~Problem() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (host) (void)hipHostFree(host);
+}
+
+static unsigned grid1(int64_t n) {
+  int64_t g = (n + dev::kBlock - 1) / dev::kBlock;
+  return (unsigned)std::max<int64_t>(1, g);
+}
+static unsigned dot_grid(int64_t n) {
+  return (unsigned)std::min<int64_t>(dev::kDotBlocks, std::max<int64_t>(1, (n + dev::kBlock - 1) / dev::kBlock));
+}
+
+template <typename T>
+static void fill_dev(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = (unsigned)std::min<int64_t>(4096, grid1(n));
+  hipLaunchKernelGGL(dev::fill<T>, dim3(g), dim3(dev::kBlock), 0, s, n, p, v);
+}
+
+void set_constant(double* p, int64_t n, double v, hipStream_t s) { fill_dev(p, n, v, s); }
+
+// ---------------------------------------------------------------- workspace
+namespace {
+struct Planner {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T) + 1;
+    return p;
+  }
+};
+}  // namespace
+
+size_t plan_workspace(Problem& P, char* base) {
+  Maps& M = P.maps;
+  Planner pl{base};
+  const size_t esz = P.opt.mg_precision == 32 ? 4 : 8;
+  const int L = (int)M.levels.size() - 1;
+  P.lv.assign(L + 1, DevLevel{});
+  int64_t off = 0;
+  P.max_level_dofs = 0;
+  for (int l = 0; l <= L; ++l) {
+    LevelData& D = M.levels[l];
+    DevLevel& V = P.lv[l];
+    V.v.n_cells = D.n_cells;
+    V.v.n_dofs = D.n_dofs;
+    V.v.n_fam = D.n_fam;
+    V.v.n_edge = (int64_t)D.edge_cells.size();
+    V.off = off;
+    off += D.n_dofs;
+    V.n_I = (int64_t)D.ilist.size();
+    V.n_S = 0;
+    for (auto f : D.flags) V.n_S += f == kFlagS;
+    P.max_level_dofs = std::max(P.max_level_dofs, D.n_dofs);
+    V.v.cmap = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
+    bool uniform = true;
+    for (auto c : D.coeff) uniform = uniform && (c == D.coeff[0]);
+    double h = std::ldexp(1.0, -l);
+    double hd = M.dim == 3 ? h : 1.0;
+    if (uniform) {
+      V.v.scale = nullptr;
+      V.v.scale0 = (D.coeff.empty() ? 1.0 : D.coeff[0]) * hd;
+    } else {
+      V.v.scale = pl.take<double>(D.n_cells);
+    }
+    V.v.flags = pl.take<uint8_t>(D.n_dofs);
+    V.v.edge = pl.take<int32_t>(D.edge_cells.size());
+    V.ilist = pl.take<int32_t>(D.ilist.size());
+    if (l >= 1) {
+      V.v.famap = pl.take<int32_t>(size_t(D.n_fam) * M.mf);
+      V.v.own = pl.take<uint32_t>(size_t(D.n_fam) * M.own_words);
+      V.v.parent = pl.take<int32_t>(D.n_fam);
+    }
+  }
+  P.n_total = off;
+  P.lx = pl.take<char>(size_t(off) * esz);
+  P.lg = pl.take<char>(size_t(off) * esz);
+  P.lt = pl.take<char>(size_t(off) * esz);
+  P.ld = pl.take<char>(size_t(off) * esz);
+  P.ldinv = pl.take<char>(size_t(off) * esz);
+  const int64_t N = M.n_dofs, H = M.n_hanging;
+  P.leaf.n_cells = M.n_leaves;
+  P.leaf.n_dofs = N;
+  P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
+  P.leaf.scale = pl.take<double>(M.n_leaves);
+  P.leaf.mscale = pl.take<double>(M.n_leaves);
+  P.n_dir = 0;
+  for (auto d : M.dirichlet) P.n_dir += d;
+  P.dir = pl.take<int32_t>(P.n_dir);
+  P.con_off = pl.take<int64_t>(H + 1);
+  P.con_mas = pl.take<int32_t>(M.con_mas.size());
+  P.con_w = pl.take<double>(M.con_w.size());
+  P.copy = pl.take<int32_t>(N);
+  P.cx = pl.take<double>(N);
+  P.cr = pl.take<double>(N);
+  P.cz = pl.take<double>(N);
+  P.cp = pl.take<double>(N);
+  P.cq = pl.take<double>(N);
+  P.cb = pl.take<double>(N);
+  P.xh = pl.take<double>(H);
+  P.yh = pl.take<double>(H);
+  P.scal = pl.take<double>(dev::kNumScalars + 8);
+  P.part = pl.take<double>(dev::kDotBlocks);
+  int n0 = 0;
+  for (auto f : M.levels[0].flags) n0 += f == kFlagS;
+  if (n0 > 6000) fail(GMG_E_INVAL, "coarse level too large for the dense coarse solve (> 6000 free nodes)");
+  P.n0 = n0;
+  P.ainv = pl.take<double>(size_t(n0) * n0);
+  P.cidx = pl.take<int32_t>(n0);
+  P.eig = pl.take<double>(size_t(P.max_level_dofs) * 6);
+  return pl.off + 256;
+}
+
+// ---------------------------------------------------------------- setup
+namespace {
+
+template <typename T>
+void h2d(const T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return;
+  HIPCHECK(hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+template <typename T>
+std::vector<T> soa(const std::vector<T>& a, int64_t rows, int cols) {
+  std::vector<T> o(a.size());
+  for (int64_t r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) o[size_t(c) * rows + r] = a[size_t(r) * cols + c];
+  return o;
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix (bisection with
+// Sturm counts)
+double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
+  const int m = (int)d.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(mid) >= m)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+double dot_host(Problem& P, const double* a, const double* b, int64_t n, hipStream_t s) {
+  unsigned g = dot_grid(n);
+  hipLaunchKernelGGL(dev::dot_partial, dim3(g), dim3(dev::kBlock), 0, s, n, a, b, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)g, P.part, P.scal + dev::kNumScalars, 3);
+  HIPCHECK(hipMemcpyAsync(P.host + 8, P.scal + dev::kNumScalars + dev::kBb, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return P.host[8];
+}
+
+// lambda_max of D^{-1} A^S: Jacobi-PCG from (i mod 12) - 5.5 on S rows,
+// largest Ritz value of the Lanczos matrix from the CG coefficients
+// (Sec. 4.1 eigenvalue estimate)
+double estimate_lambda(Problem& P, int l, hipStream_t s) {
+  DevLevel& V = P.lv[l];
+  const int64_t n = V.v.n_dofs;
+  int iters = (int)std::min<int64_t>(P.opt.eig_iters, V.n_S);
+  if (iters <= 0) return 1.0;
+  double* dinv = P.eig;
+  double* r = P.eig + n;
+  double* z = P.eig + 2 * n;
+  double* p = P.eig + 3 * n;
+  double* q = P.eig + 4 * n;
+  double* diag = P.eig + 5 * n;
+  fill_dev(diag, n, 0.0, s);
+  P.kt->diag(V.v, diag, P.m64, s);
+  hipLaunchKernelGGL(dev::make_dinv<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags, dinv);
+  hipLaunchKernelGGL(dev::eig_init, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.flags, dinv, r, z, p);
+  double rho = dot_host(P, r, z, n, s);
+  std::vector<double> alphas, betas;
+  for (int j = 0; j < iters; ++j) {
+    if (!(rho > 0.0)) break;
+    fill_dev(q, n, 0.0, s);
+    P.kt->f64.apply(V.v, p, q, P.m64, s);
+    double pq = dot_host(P, p, q, n, s);
+    if (!(pq > 0.0)) break;
+    double alpha = rho / pq;
+    alphas.push_back(alpha);
+    if (j == iters - 1) break;
+    hipLaunchKernelGGL(dev::axpy_zr, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, alpha, q, r, dinv, z);
+    double rho_new = dot_host(P, r, z, n, s);
+    if (!(rho_new > 0.0)) break;
+    double beta = rho_new / rho;
+    betas.push_back(beta);
+    hipLaunchKernelGGL(dev::xpby, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, z, beta, p);
+    rho = rho_new;
+  }
+  const int m = (int)alphas.size();
+  if (m == 0) return 1.0;
+  std::vector<double> d(m), e(std::max(0, m - 1));
+  for (int j = 0; j < m; ++j) {
+    d[j] = 1.0 / alphas[j] + (j > 0 ? betas[j - 1] / alphas[j - 1] : 0.0);
+    if (j + 1 < m) e[j] = std::sqrt(betas[j]) / alphas[j];
+  }
+  return tridiag_max_eig(d, e);
+}
+
+// dense FP64 inverse of A_0 restricted to the S nodes of level 0
+std::vector<double> coarse_inverse(const Maps& M, std::vector<int32_t>& idx) {
+  const LevelData& D = M.levels[0];
+  const int n = M.n, npc = M.npc, dim = M.dim;
+  std::vector<int32_t> pos(D.n_dofs, -1);
+  idx.clear();
+  for (int64_t i = 0; i < D.n_dofs; ++i)
+    if (D.flags[i] == kFlagS) {
+      pos[i] = (int32_t)idx.size();
+      idx.push_back((int32_t)i);
+    }
+  const int n0 = (int)idx.size();
+  std::vector<double> A(size_t(n0) * n0, 0.0);
+  for (int64_t c = 0; c < D.n_cells; ++c) {
+    const double a = D.coeff[c];  // h = 1 on level 0
+    for (int i = 0; i < npc; ++i) {
+      int pi = pos[D.cellmap[c * npc + i]];
+      if (pi < 0) continue;
+      int ix = i % n, iy = (i / n) % n, iz = i / (n * n);
+      for (int j = 0; j < npc; ++j) {
+        int pj = pos[D.cellmap[c * npc + j]];
+        if (pj < 0) continue;
+        int jx = j % n, jy = (j / n) % n, jz = j / (n * n);
+        const double* Mm = M.fe.M;
+        const double* Kk = M.fe.K;
+        double v;
+        if (dim == 3)
+          v = Kk[ix * n + jx] * Mm[iy * n + jy] * Mm[iz * n + jz] + Mm[ix * n + jx] * Kk[iy * n + jy] * Mm[iz * n + jz] +
+              Mm[ix * n + jx] * Mm[iy * n + jy] * Kk[iz * n + jz];
+        else
+          v = Kk[ix * n + jx] * Mm[iy * n + jy] + Mm[ix * n + jx] * Kk[iy * n + jy];
+        A[size_t(pi) * n0 + pj] += a * v;
+      }
+    }
+  }
+  // Cholesky A = L L^T, then the inverse column by column
+  std::vector<double> Lm(A);
+  for (int j = 0; j < n0; ++j) {
+    double s = Lm[size_t(j) * n0 + j];
+    for (int k = 0; k < j; ++k) s -= Lm[size_t(j) * n0 + k] * Lm[size_t(j) * n0 + k];
+    if (!(s > 0.0)) fail(GMG_E_BREAKDOWN, "coarse matrix not positive definite");
+    double d = std::sqrt(s);
+    Lm[size_t(j) * n0 + j] = d;
+    for (int i = j + 1; i < n0; ++i) {
+      double t = Lm[size_t(i) * n0 + j];
+      for (int k = 0; k < j; ++k) t -= Lm[size_t(i) * n0 + k] * Lm[size_t(j) * n0 + k];
+      Lm[size_t(i) * n0 + j] = t / d;
+    }
+  }
+  std::vector<double> inv(size_t(n0) * n0, 0.0), y(n0);
+  for (int c = 0; c < n0; ++c) {
+    for (int i = 0; i < n0; ++i) {
+      double t = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= Lm[size_t(i) * n0 + k] * y[k];
+      y[i] = t / Lm[size_t(i) * n0 + i];
+    }
+    for (int i = n0 - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n0; ++k) t -= Lm[size_t(k) * n0 + i] * inv[size_t(k) * n0 + c];
+      inv[size_t(i) * n0 + c] = t / Lm[size_t(i) * n0 + i];
+    }
+  }
+  return inv;
+}
+
+}  // namespace
+
+void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
+  Maps& M = P.maps;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) fail(GMG_E_INVAL, "workspace must be 256-byte aligned");
+  if (bytes < P.ws_need) fail(GMG_E_INVAL, "workspace too small");
+  plan_workspace(P, (char*)ws);
+  P.ws = (char*)ws;
+  P.ws_bytes = bytes;
+  HIPCHECK(hipGetDevice(&P.device));
+  if (!P.host) HIPCHECK(hipHostMalloc((void**)&P.host, 64 * sizeof(double), hipHostMallocDefault));
+  if (P.ev.empty()) {
+    P.ev.resize(4);
+    for (auto& e : P.ev) HIPCHECK(hipEventCreate(&e));
+  }
+  const int L = (int)M.levels.size() - 1;
+  const bool f32 = P.opt.mg_precision == 32;
+  for (int l = 0; l <= L; ++l) {
+    LevelData& D = M.levels[l];
+    DevLevel& V = P.lv[l];
+    h2d(V.v.cmap, soa(D.cellmap, D.n_cells, M.npc), s);
+    if (V.v.scale) {
+      std::vector<double> sc(D.n_cells);
+      double hd = M.dim == 3 ? std::ldexp(1.0, -l) : 1.0;
+      for (int64_t c = 0; c < D.n_cells; ++c) sc[c] = D.coeff[c] * hd;
+      h2d(V.v.scale, sc, s);
+    }
+    h2d(V.v.flags, D.flags, s);
+    h2d(V.v.edge, D.edge_cells, s);
+    h2d(V.ilist, D.ilist, s);
+    if (l >= 1) {
+      h2d(V.v.famap, soa(D.famap, D.n_fam, M.mf), s);
+      h2d(V.v.own, soa(D.own, D.n_fam, M.own_words), s);
+      h2d(V.v.parent, D.parent, s);
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  {
+    std::vector<int32_t> cm(M.leaf_cellmap.size());
+    for (size_t i = 0; i < cm.size(); ++i) {
+      int32_t v = M.leaf_cellmap[i];
+      cm[i] = v >= 0 ? v : (int32_t)(M.n_dofs + (-v - 1));
+    }
+    h2d(P.leaf.cmap, soa(cm, M.n_leaves, M.npc), s);
+    std::vector<double> sc(M.n_leaves), ms(M.n_leaves);
+    for (int64_t c = 0; c < M.n_leaves; ++c) {
+      double h = std::ldexp(1.0, -M.leaf_level[c]);
+      sc[c] = M.leaf_coeff[c] * (M.dim == 3 ? h : 1.0);
+      ms[c] = M.dim == 3 ? h * h * h : h * h;
+    }
+    h2d(P.leaf.scale, sc, s);
+    h2d(P.leaf.mscale, ms, s);
+    std::vector<int32_t> dl;
+    for (int64_t i = 0; i < M.n_dofs; ++i)
+      if (M.dirichlet[i]) dl.push_back((int32_t)i);
+    h2d(P.dir, dl, s);
+    h2d(P.con_off, M.con_off, s);
+    h2d(P.con_mas, M.con_mas, s);
+    h2d(P.con_w, M.con_w, s);
+    std::vector<int32_t> cp(M.n_dofs);
+    for (int64_t i = 0; i < M.n_dofs; ++i) {
+      int64_t g = P.lv[M.copy_level[i]].off + M.copy_index[i];
+      if (g > INT32_MAX) fail(GMG_E_INVAL, "level vectors exceed 2^31 entries");
+      cp[i] = (int32_t)g;
+    }
+    h2d(P.copy, cp, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  std::vector<int32_t> cidx;
+  std::vector<double> inv = coarse_inverse(M, cidx);
+  h2d(P.ainv, inv, s);
+  h2d(P.cidx, cidx, s);
+  // level vectors start at zero: t is kept zero between operator uses
+  const size_t esz = f32 ? 4 : 8;
+  HIPCHECK(hipMemsetAsync(P.lx, 0, P.n_total * esz, s));
+  HIPCHECK(hipMemsetAsync(P.lt, 0, P.n_total * esz, s));
+  HIPCHECK(hipMemsetAsync(P.ld, 0, P.n_total * esz, s));
+  HIPCHECK(hipMemsetAsync(P.lg, 0, P.n_total * esz, s));
+  // Jacobi diagonals and eigenvalue estimates
+  for (int l = 0; l <= L; ++l) {
+    DevLevel& V = P.lv[l];
+    const int64_t n = V.v.n_dofs;
+    double* diag = P.eig + 5 * n;
+    fill_dev(diag, n, 0.0, s);
+    P.kt->diag(V.v, diag, P.m64, s);
+    if (f32)
+      hipLaunchKernelGGL(dev::make_dinv<float>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags,
+                         (float*)P.ldinv + V.off);
+    else
+      hipLaunchKernelGGL(dev::make_dinv<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags,
+                         (double*)P.ldinv + V.off);
+    V.lam = l >= 1 ? estimate_lambda(P, l, s) : 1.0;
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  if (P.graph) {
+    (void)hipGraphExecDestroy(P.graph);
+    P.graph = nullptr;
+  }
+  P.bound = true;
+}
+
+// ---------------------------------------------------------------- operators
+void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s) {
+  const Maps& M = P.maps;
+  const int64_t N = M.n_dofs, H = M.n_hanging;
+  if (H) hipLaunchKernelGGL(dev::hang_fill, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.con_off, P.con_mas, P.con_w, x, P.xh);
+  fill_dev(y, N, 0.0, s);
+  fill_dev(P.yh, H, 0.0, s);
+  P.kt->leaf_apply(P.leaf, x, P.xh, y, P.yh, mass, P.m64, s);
+  if (H)
+    hipLaunchKernelGGL(dev::hang_condense, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.con_off, P.con_mas, P.con_w, P.yh, y);
+  if (P.n_dir)
+    hipLaunchKernelGGL(dev::zero_list<double>, dim3(grid1(P.n_dir)), dim3(dev::kBlock), 0, s, P.n_dir, P.dir, y);
+}
+
+template <typename T>
+static const LevelOps<T>& ops(Problem& P);
+template <>
+const LevelOps<float>& ops<float>(Problem& P) { return P.kt->f32; }
+template <>
+const LevelOps<double>& ops<double>(Problem& P) { return P.kt->f64; }
+template <typename T>
+static const MatsH<T>& mats(Problem& P);
+template <>
+const MatsH<float>& mats<float>(Problem& P) { return P.m32; }
+template <>
+const MatsH<double>& mats<double>(Problem& P) { return P.m64; }
+
+// Chebyshev smoothing on level l (Sec. 4.1): m steps on A^S with Jacobi,
+// damping [lo, hi] * lambda_max.  zero_start: first step from x = 0
+// without an operator application.
+template <typename T>
+static void smooth(Problem& P, int l, bool zero_start, hipStream_t s) {
+  DevLevel& V = P.lv[l];
+  const int64_t n = V.v.n_dofs, o = V.off;
+  T *X = (T*)P.lx + o, *G = (T*)P.lg + o, *Tt = (T*)P.lt + o, *Dd = (T*)P.ld + o, *Di = (T*)P.ldinv + o;
+  const double a = P.opt.cheb_lo * V.lam, b = P.opt.cheb_hi * V.lam;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+  double rho_old = 1.0 / sigma;
+  const LevelOps<T>& op = ops<T>(P);
+  if (!zero_start) op.apply(V.v, X, Tt, mats<T>(P), s);
+  hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, X, Dd, G, Tt, Di, T(0),
+                     T(1.0 / theta), zero_start ? 1 : 0);
+  for (int j = 2; j <= P.opt.cheb_degree; ++j) {
+    op.apply(V.v, X, Tt, mats<T>(P), s);
+    const double rho = 1.0 / (2.0 * sigma - rho_old);
+    hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, X, Dd, G, Tt, Di,
+                       T(rho * rho_old), T(2.0 * rho / delta), 0);
+    rho_old = rho;
+  }
+}
+
+// One V-cycle with local smoothing (Alg. 2 in the storage-efficient form of
+// Sec. 2.3): leaf residual entries enter the hierarchy on the coarsest level
+// holding them as S nodes; smoothing acts on V^S only; the residual on S and
+// I rows is restricted; after prolongation the interface values enter the
+// post-smoothing right-hand side through A^{SI}.
+template <typename T>
+static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
+  const Maps& M = P.maps;
+  const int L = (int)P.lv.size() - 1;
+  const int64_t N = M.n_dofs;
+  T *X = (T*)P.lx, *G = (T*)P.lg, *Tt = (T*)P.lt;
+  const LevelOps<T>& op = ops<T>(P);
+  fill_dev(G, P.n_total, T(0), s);
+  hipLaunchKernelGGL(dev::copy_to_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, r, G);
+  for (int l = L; l >= 1; --l) {
+    DevLevel& V = P.lv[l];
+    if (V.n_S > 0) {
+      smooth<T>(P, l, true, s);
+      op.apply(V.v, X + V.off, Tt + V.off, mats<T>(P), s);
+    } else {
+      fill_dev(X + V.off, V.v.n_dofs, T(0), s);
+    }
+    op.restrict_(V.v, P.lv[l - 1].v, G + V.off, Tt + V.off, G + P.lv[l - 1].off, mats<T>(P), s);
+  }
+  hipLaunchKernelGGL(dev::coarse_solve<T>, dim3(1), dim3(dev::kBlock), P.n0 * sizeof(double), s,
+                     (int)P.lv[0].v.n_dofs, P.n0, P.ainv, P.cidx, G + P.lv[0].off, X + P.lv[0].off);
+  for (int l = 1; l <= L; ++l) {
+    DevLevel& V = P.lv[l];
+    op.prolong(V.v, P.lv[l - 1].v, X + P.lv[l - 1].off, X + V.off, mats<T>(P), s);
+    if (V.n_S > 0) {
+      op.edge(V.v, X + V.off, G + V.off, T(-1), mats<T>(P), s);
+      if (V.n_I)
+        hipLaunchKernelGGL(dev::zero_list<T>, dim3(grid1(V.n_I)), dim3(dev::kBlock), 0, s, V.n_I, V.ilist, X + V.off);
+      smooth<T>(P, l, false, s);
+    }
+  }
+  hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, X, z);
+}
+
+static void vcycle_any(Problem& P, const double* r, double* z, hipStream_t s) {
+  if (P.opt.mg_precision == 32)
+    vcycle_t<float>(P, r, z, s);
+  else
+    vcycle_t<double>(P, r, z, s);
+}
+
+void vcycle(Problem& P, const double* r, double* z, hipStream_t s) {
+  if (!P.bound) fail(GMG_E_STATE, "problem not bound");
+  vcycle_any(P, r, z, s);
+  HIPCHECK(hipGetLastError());
+}
+
+// the CG preconditioner: replay of a captured graph of one V-cycle on the
+// fixed CG buffers r -> z when enabled
+static void precondition(Problem& P, hipStream_t s) {
+  if (!P.opt.use_graph) {
+    vcycle_any(P, P.cr, P.cz, s);
+    return;
+  }
+  if (!P.graph) {
+    hipStream_t cs;
+    HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    vcycle_any(P, P.cr, P.cz, cs);
+    HIPCHECK(hipStreamEndCapture(cs, &g));
+    HIPCHECK(hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0));
+    HIPCHECK(hipGraphDestroy(g));
+    HIPCHECK(hipStreamDestroy(cs));
+  }
+  HIPCHECK(hipGraphLaunch(P.graph, s));
+}
+
+void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hipStream_t s) {
+  if (!P.bound) fail(GMG_E_STATE, "problem not bound");
+  if (l < 0 || l >= (int)P.lv.size()) fail(GMG_E_INVAL, "level out of range");
+  DevLevel& V = P.lv[l];
+  if (P.opt.mg_precision == 32) {
+    fill_dev((float*)y, V.v.n_dofs, 0.0f, s);
+    if (variant == 0)
+      P.kt->f32.apply(V.v, (const float*)x, (float*)y, P.m32, s);
+    else
+      P.kt->f32.edge(V.v, (const float*)x, (float*)y, 1.0f, P.m32, s);
+  } else {
+    fill_dev((double*)y, V.v.n_dofs, 0.0, s);
+    if (variant == 0)
+      P.kt->f64.apply(V.v, (const double*)x, (double*)y, P.m64, s);
+    else
+      P.kt->f64.edge(V.v, (const double*)x, (double*)y, 1.0, P.m64, s);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- CG
+int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s) {
+  if (!P.bound) fail(GMG_E_STATE, "problem not bound");
+  const int64_t N = P.maps.n_dofs;
+  const unsigned dg = dot_grid(N);
+  double* sc = P.scal;
+  HIPCHECK(hipEventRecord(P.ev[0], s));
+  fill_dev(u, N, 0.0, s);
+  fill_dev(P.cp, N, 0.0, s);
+  hipLaunchKernelGGL(dev::copy_vec, dim3(dot_grid(N)), dim3(dev::kBlock), 0, s, N, b, P.cr);
+  hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, b, b, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 3);
+  fill_dev(sc + dev::kFirst, 1, 1.0, s);
+  HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  const double bb = P.host[dev::kBb];
+  if (hist) hist[0] = bb > 0 ? 1.0 : 0.0;
+  *iters = 0;
+  P.timing[1] = 0.0;
+  P.timing[2] = 0.0;
+  if (!std::isfinite(bb)) return GMG_E_NAN;
+  if (bb == 0.0) {
+    HIPCHECK(hipEventRecord(P.ev[1], s));
+    HIPCHECK(hipEventSynchronize(P.ev[1]));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, P.ev[0], P.ev[1]);
+    P.timing[0] = ms * 1e-3;
+    return GMG_OK;
+  }
+  const double nb = std::sqrt(bb);
+  int status = GMG_NOT_CONVERGED;
+  for (int it = 1; it <= P.opt.max_iter; ++it) {
+    HIPCHECK(hipEventRecord(P.ev[2], s));
+    precondition(P, s);
+    HIPCHECK(hipEventRecord(P.ev[3], s));
+    hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cr, P.cz, P.part);
+    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 0);
+    hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
+    apply_leaf(P, P.cp, P.cq, false, s);
+    hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cp, P.cq, P.part);
+    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 1);
+    hipLaunchKernelGGL(dev::update_xr, dim3(dg), dim3(dev::kBlock), 0, s, N, u, P.cr, P.cp, P.cq, sc, P.part);
+    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 2);
+    HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, P.ev[2], P.ev[3]);
+    P.timing[1] += ms * 1e-3;
+    P.timing[2] += 1;
+    *iters = it;
+    const double rr = P.host[dev::kRr], rho = P.host[dev::kRho], pq = P.host[dev::kPq];
+    const double res = std::sqrt(rr);
+    if (hist) hist[it] = res / nb;
+    if (!std::isfinite(rr) || !std::isfinite(rho) || !std::isfinite(pq)) {
+      status = GMG_E_NAN;
+      break;
+    }
+    if (!(rho > 0.0) || !(pq > 0.0)) {
+      status = GMG_E_BREAKDOWN;
+      break;
+    }
+    if (res <= P.opt.rtol * nb) {
+      status = GMG_OK;
+      break;
+    }
+  }
+  HIPCHECK(hipEventRecord(P.ev[1], s));
+  HIPCHECK(hipEventSynchronize(P.ev[1]));
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, P.ev[0], P.ev[1]);
+  P.timing[0] = ms * 1e-3;
+  HIPCHECK(hipGetLastError());
+  return status;
+}
+
+}  // namespace gmg

@@ -1,0 +1,69 @@
+"""Shared test helpers: build the same seeded workload through the oracle and
+through the library."""
+import os
+import re
+
+import numpy as np
+
+import gmg_inputs as gi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    """Function names declared in include/gmg.h."""
+    txt = open(os.path.join(ROOT, "include", "gmg.h")).read()
+    return sorted(set(re.findall(r"\b(gmg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def recipe(coarse, g, cycles, marker):
+    return gi.MeshRecipe(coarse, g, cycles, marker)
+
+
+CASES = {
+    # name: (recipe, degree)
+    "lshape-q1": (recipe("lshape", 3, 3, "corner"), 1),
+    "lshape-q2": (recipe("lshape", 2, 3, "corner"), 2),
+    "lshape-q4": (recipe("lshape", 1, 3, "corner"), 4),
+    "fichera-q1": (recipe("fichera", 1, 2, "corner+random"), 1),
+    "fichera-q2": (recipe("fichera", 1, 2, "corner+random"), 2),
+    "fichera-q3": (recipe("fichera", 0, 2, "corner+random"), 3),
+    "fichera-q4": (recipe("fichera", 0, 2, "corner+random"), 4),
+    "cube-q2": (recipe("cube", 2, 2, "corner"), 2),
+}
+
+
+def oracle_problem(rec, k, coeff_kind="one", **kw):
+    from oracle import problem
+    f = problem.build_forest(rec)
+    coeff = gi.coeff_cells(coeff_kind, *f.leaves_arrays()) if coeff_kind != "one" else None
+    return problem.setup(f, k, coeff=coeff, **kw), coeff
+
+
+def library_problem(rec, k, coeff_kind="one", **opt):
+    from paper_1904_03317_amd import gmg
+    m = gmg.build_mesh(rec)
+    coeff = gi.coeff_cells(coeff_kind, *m.leaves()) if coeff_kind != "one" else None
+    P = gmg.Problem(m, gmg.options(degree=k, **opt), coeff=coeff)
+    return m, P, coeff
+
+
+def compare_maps(P, d):
+    """Bit-exact comparison of the library's host maps with the oracle's."""
+    k = d.k
+    npc = (k + 1) ** d.forest.dim
+    assert np.array_equal(P.array("LEAF_CELLMAP").reshape(-1, npc), d.leaf.cellmap)
+    assert np.array_equal(P.array("LEAF_DIRICHLET"), d.leaf.dirichlet)
+    assert np.array_equal(P.array("CON_OFFSETS"), d.leaf.c_offsets)
+    assert np.array_equal(P.array("CON_MASTERS"), d.leaf.c_masters)
+    if len(d.leaf.c_weights):
+        assert np.abs(P.array("CON_WEIGHTS") - d.leaf.c_weights).max() <= 1e-14
+    assert np.array_equal(P.array("COPY_LEVEL"), d.copy_level)
+    assert np.array_equal(P.array("COPY_INDEX"), d.copy_index)
+    info = P.info()
+    assert info.n_levels == len(d.levels)
+    for l, lev in enumerate(d.levels):
+        assert np.array_equal(P.array("LEVEL_CELLMAP", l).reshape(lev.cellmap.shape), lev.cellmap)
+        assert np.array_equal(P.array("LEVEL_FLAGS", l), lev.flags)
+        if l:
+            assert np.array_equal(P.array("LEVEL_PARENT", l), lev.parent_index)

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs.  Tolerances: FP64 operators 1e-13 relative (rounding order of
+atomic scatter), FP32 operators 2e-6, FP64 V-cycle 1e-11, FP64 solve 1e-10
+relative solution error at equal iteration counts; maps are compared
+bit-exactly on the host (test_native_host)."""
+import numpy as np
+import pytest
+
+import gmg_inputs as gi
+from helpers import CASES, library_problem, oracle_problem
+from oracle.assemble import level_coefficients, level_matrix
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _pair(case, prec=64, coeff="one", **kw):
+    rec, k = CASES[case]
+    op, _ = oracle_problem(rec, k, coeff_kind=coeff)
+    print(f"[gpu] case={case} k={k} prec={prec} coeff={coeff} N={op.n_dofs}", flush=True)
+    m, P, _ = library_problem(rec, k, coeff_kind=coeff, mg_precision=prec, **kw)
+    P.bind()
+    return op, P
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_leaf_operator_and_rhs(case):
+    op, P = _pair(case, coeff="checker" if CASES[case][0].coarse == "fichera" else "one")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(op.n_dofs)
+    x[~op.free] = 0
+    y = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    P.apply_leaf(dev(x), y)
+    assert rel(host(y), op.A @ x) <= 1e-13
+    f = 1.0 + rng.standard_normal(op.n_dofs)
+    b = torch.zeros_like(y)
+    P.rhs(dev(f), b)
+    assert rel(host(b), op.rhs(f)) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [(64, 1e-13), (32, 2e-6)])
+@pytest.mark.parametrize("case", ["lshape-q1", "fichera-q2", "fichera-q3", "fichera-q4"])
+def test_level_operators(case, prec, tol):
+    op, P = _pair(case, prec=prec, coeff="checker" if "fichera" in case else "one")
+    d = op.disc
+    lc = level_coefficients(d, op.coeff)
+    rng = np.random.default_rng(6)
+    tdt = torch.float64 if prec == 64 else torch.float32
+    for l, lev in enumerate(d.levels):
+        A = level_matrix(d, l, lc[l]).tocsr()
+        x = rng.standard_normal(lev.n_dofs)
+        y = torch.zeros(lev.n_dofs, dtype=tdt, device="cuda")
+        P.apply_level(l, 0, dev(x, tdt), y)
+        xr = x.astype(np.float32).astype(np.float64) if prec == 32 else x
+        assert rel(host(y).astype(np.float64), A @ xr) <= tol, l
+        # edge coupling A^{SI} x^I on S rows
+        S, I = lev.flags == 0, lev.flags == 1
+        want = np.zeros(lev.n_dofs)
+        want[S] = A[S][:, I] @ xr[I]
+        P.apply_level(l, 1, dev(x, tdt), y)
+        got = host(y).astype(np.float64)
+        if np.linalg.norm(want) > 0:
+            assert rel(got, want) <= tol, l
+        else:
+            assert np.abs(got).max() == 0.0
+
+
+@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "fichera-q1", "fichera-q2", "fichera-q3"])
+def test_lambda_and_vcycle_fp64(case):
+    op, P = _pair(case, coeff="checker" if "fichera" in case else "one")
+    info = P.info()
+    for l in range(1, info.n_levels):
+        assert abs(info.lambda_max[l] - op.mg.lam[l]) <= 1e-10 * op.mg.lam[l], l
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(op.n_dofs)
+    r[~op.free] = 0
+    z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    P.vcycle(dev(r), z)
+    assert rel(host(z), op.mg.vcycle(r)) <= 1e-11
+
+
+@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q2"])
+def test_vcycle_fp32_close_to_fp64(case):
+    op, P = _pair(case, prec=32)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(op.n_dofs)
+    r[~op.free] = 0
+    z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    P.vcycle(dev(r), z)
+    assert rel(host(z), op.mg.vcycle(r)) <= 1e-5
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+@pytest.mark.parametrize("case", ["lshape-q1", "fichera-q2", "fichera-q3", "cube-q2"])
+def test_solve_fp64_matches_oracle_iterate(case, use_graph):
+    op, P = _pair(case, use_graph=use_graph)
+    f = gi.rhs_nodal("noise", op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    assert st == 0 and ok
+    assert its == it
+    assert rel(host(u), x) <= 1e-10
+    assert np.allclose(h, hist, rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q1", "fichera-q3"])
+def test_solve_fp32_mg(case):
+    op, P = _pair(case, prec=32)
+    f = gi.rhs_nodal("noise", op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    assert st == 0 and h[-1] <= 1e-10
+    assert its <= it + 1
+    b = op.rhs(f)
+    uh = host(u)
+    assert np.linalg.norm(b - op.A @ uh) <= 1.0001e-10 * np.linalg.norm(b)
+    assert rel(uh, x) <= 1e-8
+
+
+def test_solve_variable_coefficient_q3():
+    op, P = _pair("fichera-q3", coeff="checker")
+    f = np.ones(op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    assert st == 0 and its == it and rel(host(u), x) <= 1e-10
+
+
+def test_zero_rhs_and_default_rhs():
+    op, P = _pair("lshape-q1")
+    u = torch.ones(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(np.zeros(op.n_dofs)), u)
+    assert st == 0 and its == 0 and np.abs(host(u)).max() == 0.0
+    st, its, h = P.solve(None, u)
+    x, it, hist, ok = op.solve(np.ones(op.n_dofs))
+    assert its == it and rel(host(u), x) <= 1e-10
+
+
+def test_not_converged_and_nan():
+    from paper_1904_03317_amd import gmg
+    rec, k = CASES["fichera-q2"]
+    m, P, _ = library_problem(rec, k, max_iter=2)
+    P.bind()
+    n = P.n_dofs
+    u = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(np.ones(n)), u)
+    assert st == gmg.GMG_NOT_CONVERGED and its == 2
+    f = np.ones(n)
+    f[n // 2] = np.nan
+    with pytest.raises(gmg.GMGError) as e:
+        P.solve(dev(f), u)
+    assert e.value.code == -6

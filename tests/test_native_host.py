@@ -1,0 +1,116 @@
+"""CPU tests of the native library: it loads, exports every symbol of
+include/gmg.h, its host-side forest and maps are bit-exact with the oracle's,
+and invalid input is rejected with an error code.  No GPU call is made."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import gmg_inputs as gi
+from helpers import CASES, compare_maps, header_functions, library_problem
+from oracle import problem as op
+from oracle.dofs import discretize
+from paper_1904_03317_amd import gmg
+
+
+def test_exports_every_header_function():
+    L = gmg.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(gmg.exported_symbols())
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_maps_bit_exact(case):
+    rec, k = CASES[case]
+    m, P, _ = library_problem(rec, k)
+    f = op.build_forest(rec)
+    lv, an = m.leaves()
+    olv, oan = f.leaves_arrays()
+    assert np.array_equal(lv, olv) and np.array_equal(an, oan)
+    compare_maps(P, discretize(f, k))
+
+
+@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2)])
+def test_workload_maps_bit_exact(name, g):
+    w = gi.workload(name, g=g)
+    m, P, _ = library_problem(w.recipe, w.degree)
+    f = op.build_forest(w.recipe)
+    compare_maps(P, discretize(f, w.degree))
+
+
+def test_closure_matches_oracle_random_flags():
+    rng = np.random.default_rng(11)
+    origins = gi.coarse_mesh("fichera")[1]
+    m = gmg.Mesh(3, origins)
+    from oracle.forest import Forest
+    f = Forest(3, origins)
+    for step in range(4):
+        n = m.n_leaves
+        flags = (rng.random(n) < (1.0 if step == 0 else 0.08)).astype(np.uint8)
+        m.refine(flags)
+        f.refine(flags)
+        lv, an = m.leaves()
+        olv, oan = f.leaves_arrays()
+        assert np.array_equal(lv, olv) and np.array_equal(an, oan)
+
+
+def test_uniform_counts_and_paper_117():
+    m = gmg.Mesh(3, gi.coarse_mesh("fichera")[1])
+    P = gmg.Problem(m, gmg.options(degree=2))
+    assert P.n_dofs == 117
+    for g in (1, 2, 3):
+        m = gmg.Mesh(3, gi.coarse_mesh("fichera")[1])
+        for _ in range(g):
+            m.refine(np.ones(m.n_leaves, np.uint8))
+        for k in (1, 2, 3):
+            P = gmg.Problem(m, gmg.options(degree=k))
+            n = 2 ** g
+            assert P.n_dofs == (2 * k * n + 1) ** 3 - (k * n) ** 3
+
+
+def test_errors_are_reported():
+    L = gmg.lib()
+    h = ctypes.c_void_p()
+    o = np.zeros(2, np.int32)
+    assert L.gmg_mesh_create(4, 1, o.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == gmg.GMG_OK - 1
+    assert b"dim" in L.gmg_last_error()
+    dup = np.array([0, 0, 0, 0], np.int32)
+    assert L.gmg_mesh_create(2, 2, dup.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) < 0
+    m = gmg.Mesh(2, [(0, 0)])
+    with pytest.raises(gmg.GMGError):
+        gmg.Problem(m, gmg.options(degree=7))
+    with pytest.raises(gmg.GMGError):
+        gmg.Problem(m, gmg.options(mg_precision=16))
+    with pytest.raises(gmg.GMGError):
+        gmg.Problem(m, gmg.options(), coeff=np.array([-1.0]))
+    P = gmg.Problem(m, gmg.options(degree=1))
+    # device calls before bind fail with a state error (no GPU touched)
+    x = np.zeros(P.n_dofs)
+    code = L.gmg_vcycle(P.h, x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p), None)
+    assert code == -8
+    with pytest.raises(ValueError):
+        m.refine(np.ones(5, np.uint8))
+
+
+def test_max_level_rejected():
+    m = gmg.Mesh(2, [(0, 0)])
+    for _ in range(18):
+        lv, an = m.leaves()
+        f = np.zeros(len(lv), np.uint8)
+        f[0] = 1
+        m.refine(f)
+    lv, an = m.leaves()
+    f = np.zeros(len(lv), np.uint8)
+    f[0] = 1
+    with pytest.raises(gmg.GMGError):
+        m.refine(f)
+
+
+def test_workspace_accounts_for_precision():
+    rec, k = CASES["fichera-q2"]
+    _, P32, _ = library_problem(rec, k, mg_precision=32)
+    _, P64, _ = library_problem(rec, k, mg_precision=64)
+    assert P64.workspace_bytes() > P32.workspace_bytes() > 0
