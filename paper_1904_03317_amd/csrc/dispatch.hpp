@@ -18,6 +18,14 @@ struct LevelView {
   const int32_t* famap = nullptr;   // SoA [mf][n_fam]
   const uint32_t* own = nullptr;    // SoA [own_words][n_fam]
   const int32_t* parent = nullptr;
+  // two-pass operator: slot of (cell, local node) in the node-major buffer,
+  // and per-node slot ranges
+  const int32_t* slot = nullptr;    // SoA [npc][n_cells]
+  const int32_t* soff = nullptr;    // [n_dofs + 1]
+  // restriction into the next coarser level: slot of (family, parent node)
+  const int32_t* rslot = nullptr;   // SoA [npc][n_fam]
+  // slot ranges of the contributions restricted from the next finer level
+  const int32_t* roff = nullptr;    // [n_dofs + 1]
 };
 
 struct LeafView {
@@ -25,6 +33,13 @@ struct LeafView {
   const int32_t* cmap = nullptr;    // SoA [npc][n_cells], hanging h as n_dofs + h
   const double* scale = nullptr;    // a_K h^{d-2}
   const double* mscale = nullptr;   // h^d
+  const int32_t* slot = nullptr;    // SoA [npc][n_cells] slot in the node-major buffer
+  const int32_t* soff = nullptr;    // [n_dofs + n_hanging + 1]
+  const int64_t* toff = nullptr;    // transposed constraints: per DoF, its hanging nodes
+  const int32_t* th = nullptr;
+  const double* tw = nullptr;
+  const uint8_t* dir = nullptr;     // [n_dofs] Dirichlet flag
+  int64_t n_hang = 0;
 };
 
 template <typename T>
@@ -34,24 +49,23 @@ struct MatsH {
 
 template <typename T>
 struct LevelOps {
-  // y += A x over all cells (plain gather/scatter)
-  void (*apply)(const LevelView&, const T* x, T* y, const MatsH<T>&, hipStream_t);
-  // y[S] += sign * A^{SI} x^I on the edge cells
+  // pass 1 of y = A x over all cells: cell results into the slots E
+  void (*apply_e)(const LevelView&, const T* x, T* E, const MatsH<T>&, hipStream_t);
+  // y[S] += sign * A^{SI} x^I on the edge cells (atomic scatter; test hook)
   void (*edge)(const LevelView&, const T* x, T* y, T sign, const MatsH<T>&, hipStream_t);
   // x_f += P x_c on owned fine nodes
   void (*prolong)(const LevelView& fine, const LevelView& coarse, const T* xc, T* xf, const MatsH<T>&,
                   hipStream_t);
-  // d_c += R (g - t) over free owned fine nodes; t := 0 on them
-  void (*restrict_)(const LevelView& fine, const LevelView& coarse, const T* g, T* t, T* dc,
-                    const MatsH<T>&, hipStream_t);
+  // family contributions of R r to the parent-node slots E
+  void (*restrict_e)(const LevelView& fine, const T* r, T* E, const MatsH<T>&, hipStream_t);
 };
 
 struct KernelTable {
   LevelOps<float> f32;
   LevelOps<double> f64;
-  // leaf operator / mass into y (n_dofs) and yh (hanging), both pre-zeroed
-  void (*leaf_apply)(const LeafView&, const double* x, const double* xh, double* y, double* yh, bool mass,
-                     const MatsH<double>&, hipStream_t);
+  // pass 1 of the leaf operator (or mass matrix): cell results into slots
+  void (*leaf_e)(const LeafView&, const double* x, const double* xh, double* E, bool mass,
+                 const MatsH<double>&, hipStream_t);
   void (*diag)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
 };
 

@@ -23,11 +23,11 @@ struct Inst {
   static constexpr int N = K + 1;
 
   template <typename T>
-  static void apply(const LevelView& v, const T* x, T* y, const MatsH<T>& m, hipStream_t s) {
+  static void apply_e(const LevelView& v, const T* x, T* E, const MatsH<T>& m, hipStream_t s) {
     if (!v.n_cells) return;
-    hipLaunchKernelGGL((dev::cell_apply<DIM, N, T, 0, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock), 0, s,
-                       v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.scale, v.scale0, x,
-                       (const T*)nullptr, y, (T*)nullptr, (int64_t)0, (const uint8_t*)nullptr, T(1), to_dev(m));
+    hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, T, false, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
+                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const T*)nullptr, (int64_t)0, E,
+                       to_dev(m));
   }
   template <typename T>
   static void edge(const LevelView& v, const T* x, T* y, T sign, const MatsH<T>& m, hipStream_t s) {
@@ -44,23 +44,22 @@ struct Inst {
                        f.famap, f.own, f.parent, c.n_cells, c.cmap, xc, xf, to_dev(m));
   }
   template <typename T>
-  static void restrict_(const LevelView& f, const LevelView& c, const T* g, T* t, T* dc, const MatsH<T>& m,
-                        hipStream_t s) {
+  static void restrict_e(const LevelView& f, const T* r, T* E, const MatsH<T>& m, hipStream_t s) {
     if (!f.n_fam) return;
-    hipLaunchKernelGGL((dev::restrict_residual<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s,
-                       f.n_fam, f.famap, f.own, f.parent, c.n_cells, c.cmap, g, t, f.flags, dc, to_dev(m));
+    hipLaunchKernelGGL((dev::restrict_to_slots<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s,
+                       f.n_fam, f.famap, f.own, r, f.rslot, E, to_dev(m));
   }
-  static void leaf_apply(const LeafView& v, const double* x, const double* xh, double* y, double* yh, bool mass,
-                         const MatsH<double>& m, hipStream_t s) {
+  static void leaf_e(const LeafView& v, const double* x, const double* xh, double* E, bool mass,
+                     const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;
     if (mass)
-      hipLaunchKernelGGL((dev::cell_apply<DIM, N, double, 1, true>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
-                         0, s, v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.mscale, 1.0, x, xh, y, yh,
-                         v.n_dofs, (const uint8_t*)nullptr, 1.0, to_dev(m));
+      hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(v.n_cells)),
+                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.mscale, 1.0, x, xh, v.n_dofs, E,
+                         to_dev(m));
     else
-      hipLaunchKernelGGL((dev::cell_apply<DIM, N, double, 1, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
-                         0, s, v.n_cells, (const int32_t*)nullptr, v.n_cells, v.cmap, v.scale, 1.0, x, xh, y, yh,
-                         v.n_dofs, (const uint8_t*)nullptr, 1.0, to_dev(m));
+      hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(v.n_cells)),
+                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, xh, v.n_dofs, E,
+                         to_dev(m));
   }
   static void diag(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;
@@ -70,9 +69,9 @@ struct Inst {
 
   static const KernelTable* table() {
     static KernelTable t = {
-        {&apply<float>, &edge<float>, &prolong<float>, &restrict_<float>},
-        {&apply<double>, &edge<double>, &prolong<double>, &restrict_<double>},
-        &leaf_apply,
+        {&apply_e<float>, &edge<float>, &prolong<float>, &restrict_e<float>},
+        {&apply_e<double>, &edge<double>, &prolong<double>, &restrict_e<double>},
+        &leaf_e,
         &diag,
     };
     return &t;

@@ -222,6 +222,41 @@ __global__ void __launch_bounds__(kBlock) cell_apply(
   }
 }
 
+// Two-pass operator, pass 1: every (cell, local node) owns one slot of the
+// node-major buffer E (the slots of a node are contiguous), so the cell
+// results are written with plain stores and no two lanes ever write the same
+// address.  Pass 2 (seg_*) sums the slots of each node in a fixed order:
+// deterministic and free of atomics.  LEAF: ids >= n_main address the
+// hanging-node part of the input.
+template <int DIM, int N, typename T, bool LEAF, bool MASS>
+__global__ void __launch_bounds__(kBlock) cell_to_slots(
+    int64_t n_cells, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
+    const double* __restrict__ scale, double scale0, const T* __restrict__ x, const T* __restrict__ xh,
+    int64_t n_main, T* __restrict__ E, Mats<T> m) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  const int64_t c = xcd_tid();
+  if (c >= n_cells) return;
+  T u[NP], v[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int32_t g = cmap[(int64_t)j * n_cells + c];
+    if (LEAF)
+      u[j] = g < n_main ? x[g] : xh[g - n_main];
+    else
+      u[j] = x[g];
+  }
+  if (MASS) {
+    mass_nd<DIM, N, T>(m, u, v);
+  } else if (DIM == 3) {
+    laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(v));
+  } else {
+    laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
+  }
+  const T s = T(scale ? scale[c] : scale0);
+#pragma unroll
+  for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
+}
+
 // diagonal of the cell Laplacian, accumulated per node (FP64)
 template <int DIM, int N>
 __global__ void __launch_bounds__(kBlock) cell_diag(int64_t n_cells, const int32_t* __restrict__ cmap,
@@ -257,7 +292,8 @@ __global__ void make_dinv(int64_t n, const double* __restrict__ diag, const uint
 // Family of 2^d siblings: (2k+1)^d fine nodes, parent (k+1)^d nodes.
 // Prolongation x_f += E^{x d} x_c on the nodes this family owns; each fine
 // node is owned by exactly one family, so the global operator is applied
-// once per node without atomics.
+// once per node without atomics.  All loads are unconditional (the family
+// map is valid for every node) so that they are issued together.
 template <int DIM, int K, typename T>
 __global__ void __launch_bounds__(kBlock) prolongate(
     int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
@@ -267,6 +303,7 @@ __global__ void __launch_bounds__(kBlock) prolongate(
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
   constexpr int NW = (MF + 31) / 32;
+  constexpr int NZ = DIM == 3 ? N : 1;
   const int64_t f = xcd_tid();
   if (f >= n_fam) return;
   const int64_t p = parent[f];
@@ -274,10 +311,9 @@ __global__ void __launch_bounds__(kBlock) prolongate(
 #pragma unroll
   for (int j = 0; j < NP; ++j) u[j] = xc[pmap[(int64_t)j * n_pcells + p]];
   // x: N -> M2
-  constexpr int R1 = NP / N;
-  T a[R1 * M2];
+  T a[NZ * N * M2];
 #pragma unroll
-  for (int r = 0; r < R1; ++r)
+  for (int r = 0; r < NZ * N; ++r)
 #pragma unroll
     for (int i = 0; i < M2; ++i) {
       T s = 0;
@@ -286,7 +322,6 @@ __global__ void __launch_bounds__(kBlock) prolongate(
       a[r * M2 + i] = s;
     }
   // y: N -> M2 over rows (z, x)
-  constexpr int NZ = DIM == 3 ? N : 1;
   T b[NZ * M2 * M2];
 #pragma unroll
   for (int z = 0; z < NZ; ++z)
@@ -302,41 +337,39 @@ __global__ void __launch_bounds__(kBlock) prolongate(
   uint32_t ow[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) ow[w] = own[(int64_t)w * n_fam + f];
-  if (DIM == 2) {
+  constexpr int NZF = DIM == 3 ? M2 : 1;
 #pragma unroll
-    for (int q = 0; q < MF; ++q)
-      if ((ow[q / 32] >> (q % 32)) & 1u) {
-        const int32_t g = famap[(int64_t)q * n_fam + f];
-        xf[g] += b[q];
+  for (int iz = 0; iz < NZF; ++iz) {
+    int32_t gid[M2 * M2];
+    T old[M2 * M2];
+#pragma unroll
+    for (int yx = 0; yx < M2 * M2; ++yx) gid[yx] = famap[(int64_t)(iz * M2 * M2 + yx) * n_fam + f];
+#pragma unroll
+    for (int yx = 0; yx < M2 * M2; ++yx) old[yx] = xf[gid[yx]];
+#pragma unroll
+    for (int yx = 0; yx < M2 * M2; ++yx) {
+      const int q = iz * M2 * M2 + yx;
+      T s;
+      if (DIM == 3) {
+        s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.E[iz * N + j] * b[j * M2 * M2 + yx];
+      } else {
+        s = b[yx];
       }
-  } else {
-#pragma unroll
-    for (int i = 0; i < M2; ++i)
-#pragma unroll
-      for (int yx = 0; yx < M2 * M2; ++yx) {
-        const int q = i * M2 * M2 + yx;
-        if ((ow[q / 32] >> (q % 32)) & 1u) {
-          T s = 0;
-#pragma unroll
-          for (int j = 0; j < N; ++j) s += m.E[i * N + j] * b[j * M2 * M2 + yx];
-          const int32_t g = famap[(int64_t)q * n_fam + f];
-          xf[g] += s;
-        }
-      }
+      if ((ow[q / 32] >> (q % 32)) & 1u) xf[gid[yx]] = old[yx] + s;
+    }
   }
 }
 
-// Residual and restriction fused: r = g - t on owned free fine nodes (t is
-// reset to zero for the next operator accumulation), then
-// d_c += (E^T)^{x d} r scattered to the parent's nodes.
+// Restriction (R = P^T) of the residual r (zero on Dirichlet rows) on the
+// nodes this family owns, contracted to the parent's nodes and written to
+// the parent-node slots of the coarse level (summed by a seg_* kernel).
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) restrict_residual(
+__global__ void __launch_bounds__(kBlock) restrict_to_slots(
     int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
-    const int32_t* __restrict__ parent, int64_t n_pcells, const int32_t* __restrict__ pmap,
-    const T* __restrict__ g, T* __restrict__ t, const uint8_t* __restrict__ flags, T* __restrict__ dc,
-    Mats<T> m) {
+    const T* __restrict__ r, const int32_t* __restrict__ rslot, T* __restrict__ E, Mats<T> m) {
   constexpr int N = K + 1, M2 = 2 * K + 1;
-  constexpr int NP = DIM == 3 ? N * N * N : N * N;
   constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
   constexpr int NW = (MF + 31) / 32;
   constexpr int NZ = DIM == 3 ? M2 : 1;
@@ -349,22 +382,22 @@ __global__ void __launch_bounds__(kBlock) restrict_residual(
   T a[NZ * M2 * N];
 #pragma unroll
   for (int zy = 0; zy < NZ * M2; ++zy) {
-    T r[M2];
+    int32_t gid[M2];
+    T rv[M2];
+#pragma unroll
+    for (int i = 0; i < M2; ++i) gid[i] = famap[(int64_t)(zy * M2 + i) * n_fam + f];
+#pragma unroll
+    for (int i = 0; i < M2; ++i) rv[i] = r[gid[i]];
 #pragma unroll
     for (int i = 0; i < M2; ++i) {
       const int q = zy * M2 + i;
-      r[i] = 0;
-      if ((ow[q / 32] >> (q % 32)) & 1u) {
-        const int32_t gid = famap[(int64_t)q * n_fam + f];
-        if (flags[gid] != 2) r[i] = g[gid] - t[gid];
-        t[gid] = 0;
-      }
+      if (!((ow[q / 32] >> (q % 32)) & 1u)) rv[i] = T(0);
     }
 #pragma unroll
     for (int J = 0; J < N; ++J) {
       T s = 0;
 #pragma unroll
-      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * r[i];
+      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * rv[i];
       a[zy * N + J] = s;
     }
   }
@@ -381,10 +414,9 @@ __global__ void __launch_bounds__(kBlock) restrict_residual(
         for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * a[(z * M2 + i) * N + x];
         b[(z * N + J) * N + x] = s;
       }
-  const int64_t p = parent[f];
   if (DIM == 2) {
 #pragma unroll
-    for (int j = 0; j < NP; ++j) atomic_add(&dc[pmap[(int64_t)j * n_pcells + p]], b[j]);
+    for (int j = 0; j < N * N; ++j) E[rslot[(int64_t)j * n_fam + f]] = b[j];
   } else {
 #pragma unroll
     for (int J = 0; J < N; ++J)
@@ -393,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) restrict_residual(
         T s = 0;
 #pragma unroll
         for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * b[i * N * N + yx];
-        atomic_add(&dc[pmap[(int64_t)(J * N * N + yx) * n_pcells + p]], s);
+        E[rslot[(int64_t)(J * N * N + yx) * n_fam + f]] = s;
       }
   }
 }
@@ -462,6 +494,62 @@ __global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, cons
   }
 }
 
+// ------------------------------------------------------------------ pass 2
+template <typename T>
+__device__ __forceinline__ T seg_sum(const int32_t* __restrict__ off, const T* __restrict__ E, int64_t i) {
+  T y = 0;
+  const int32_t e = off[i + 1];
+  for (int32_t p = off[i]; p < e; ++p) y += E[p];
+  return y;
+}
+
+// Chebyshev step on the operator result: d = c1 d + c2 D^{-1} (g - A x);
+// x += d.  Rows that are not smoothed have D^{-1} = 0.
+template <typename T>
+__global__ void seg_cheb(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E, T* __restrict__ x,
+                         T* __restrict__ d, const T* __restrict__ g, const T* __restrict__ dinv, T c1, T c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T y = seg_sum(off, E, i);
+  const T v = c1 * d[i] + c2 * dinv[i] * (g[i] - y);
+  d[i] = v;
+  x[i] += v;
+}
+
+// residual r = g - A x on free rows, 0 on Dirichlet rows (use_e = 0: A x = 0)
+template <typename T>
+__global__ void seg_residual(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
+                             const T* __restrict__ g, const uint8_t* __restrict__ flags, T* __restrict__ r,
+                             int use_e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T y = use_e ? seg_sum(off, E, i) : T(0);
+  r[i] = flags[i] == 2 ? T(0) : g[i] - y;
+}
+
+template <typename T>
+__global__ void seg_plain(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E, T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = seg_sum(off, E, i);
+}
+
+// g += restricted contributions; then the first Chebyshev step from x = 0:
+// d = c2 D^{-1} g, x = d
+template <typename T>
+__global__ void seg_restrict_start(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
+                                   T* __restrict__ g, T* __restrict__ x, T* __restrict__ d,
+                                   const T* __restrict__ dinv, T c2, int smooth) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T gi = g[i] + seg_sum(off, E, i);
+  g[i] = gi;
+  if (smooth) {
+    const T v = c2 * dinv[i] * gi;
+    d[i] = v;
+    x[i] = v;
+  }
+}
+
 #ifdef GMG_SOLVER_TU
 // Non-template kernels: compiled in the solver translation unit only.
 // hanging nodes: xh[h] = sum_j w_hj x[m_hj]; condensation y[m_hj] += w_hj yh[h]
@@ -480,6 +568,25 @@ __global__ void hang_condense(int64_t H, const int64_t* __restrict__ off, const 
   if (h >= H) return;
   const double v = yh[h];
   for (int64_t p = off[h]; p < off[h + 1]; ++p) atomic_add(&y[mas[p]], w[p] * v);
+}
+
+// leaf operator, pass 2: hanging-node sums, then DoF sums plus the
+// condensation y_m += sum_h w_hm y_h (transposed constraints, gathered)
+__global__ void seg_hang(int64_t H, const int32_t* __restrict__ off, const double* __restrict__ E,
+                         double* __restrict__ yh) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < H) yh[h] = seg_sum(off, E, h);
+}
+
+__global__ void seg_leaf(int64_t n, const int32_t* __restrict__ off, const double* __restrict__ E,
+                         const int64_t* __restrict__ toff, const int32_t* __restrict__ th,
+                         const double* __restrict__ tw, const double* __restrict__ yh,
+                         const uint8_t* __restrict__ dir, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = seg_sum(off, E, i);
+  for (int64_t p = toff[i]; p < toff[i + 1]; ++p) s += tw[p] * yh[th[p]];
+  y[i] = dir[i] ? 0.0 : s;
 }
 
 // ------------------------------------------------------------------ CG (FP64)

@@ -44,6 +44,7 @@ struct Problem {
   void *lx = nullptr, *lg = nullptr, *lt = nullptr, *ld = nullptr, *ldinv = nullptr;
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
   double *xh = nullptr, *yh = nullptr;
+  double* E = nullptr;     // node-major slots of the two-pass operator (used as float or double)
   double *scal = nullptr, *part = nullptr;
   double* ainv = nullptr;
   const int32_t* cidx = nullptr;

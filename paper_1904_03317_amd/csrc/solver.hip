@@ -72,6 +72,7 @@ size_t plan_workspace(Problem& P, char* base) {
   const int L = (int)M.levels.size() - 1;
   P.lv.assign(L + 1, DevLevel{});
   int64_t off = 0;
+  int64_t e_max = 0;
   P.max_level_dofs = 0;
   for (int l = 0; l <= L; ++l) {
     LevelData& D = M.levels[l];
@@ -87,6 +88,11 @@ size_t plan_workspace(Problem& P, char* base) {
     for (auto f : D.flags) V.n_S += f == kFlagS;
     P.max_level_dofs = std::max(P.max_level_dofs, D.n_dofs);
     V.v.cmap = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
+    V.v.slot = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
+    V.v.soff = pl.take<int32_t>(D.n_dofs + 1);
+    V.v.roff = l < L ? pl.take<int32_t>(D.n_dofs + 1) : nullptr;
+    e_max = std::max<int64_t>(e_max, D.n_cells * M.npc);
+    e_max = std::max<int64_t>(e_max, D.n_fam * M.npc);
     bool uniform = true;
     for (auto c : D.coeff) uniform = uniform && (c == D.coeff[0]);
     double h = std::ldexp(1.0, -l);
@@ -104,6 +110,7 @@ size_t plan_workspace(Problem& P, char* base) {
       V.v.famap = pl.take<int32_t>(size_t(D.n_fam) * M.mf);
       V.v.own = pl.take<uint32_t>(size_t(D.n_fam) * M.own_words);
       V.v.parent = pl.take<int32_t>(D.n_fam);
+      V.v.rslot = pl.take<int32_t>(size_t(D.n_fam) * M.npc);
     }
   }
   P.n_total = off;
@@ -118,6 +125,16 @@ size_t plan_workspace(Problem& P, char* base) {
   P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
   P.leaf.scale = pl.take<double>(M.n_leaves);
   P.leaf.mscale = pl.take<double>(M.n_leaves);
+  P.leaf.slot = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
+  P.leaf.soff = pl.take<int32_t>(N + H + 1);
+  P.leaf.toff = pl.take<int64_t>(N + 1);
+  P.leaf.th = pl.take<int32_t>(M.con_mas.size());
+  P.leaf.tw = pl.take<double>(M.con_mas.size());
+  P.leaf.dir = pl.take<uint8_t>(N);
+  P.leaf.n_hang = H;
+  e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
+  if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
+  P.E = pl.take<double>(e_max);
   P.n_dir = 0;
   for (auto d : M.dirichlet) P.n_dir += d;
   P.dir = pl.take<int32_t>(P.n_dir);
@@ -160,6 +177,19 @@ std::vector<T> soa(const std::vector<T>& a, int64_t rows, int cols) {
   for (int64_t r = 0; r < rows; ++r)
     for (int c = 0; c < cols; ++c) o[size_t(c) * rows + r] = a[size_t(r) * cols + c];
   return o;
+}
+
+// Slots of the two-pass operator: every (cell, local node) gets one entry of
+// a node-major buffer; the entries of a node are contiguous, in cell order.
+void build_slots(const std::vector<int32_t>& cm, int64_t nc, int npc, int64_t nn, std::vector<int32_t>& off,
+                 std::vector<int32_t>& slot_soa) {
+  off.assign(nn + 1, 0);
+  for (size_t i = 0; i < cm.size(); ++i) ++off[cm[i] + 1];
+  for (int64_t i = 0; i < nn; ++i) off[i + 1] += off[i];
+  std::vector<int32_t> pos(off.begin(), off.end() - 1);
+  slot_soa.resize(cm.size());
+  for (int64_t c = 0; c < nc; ++c)
+    for (int j = 0; j < npc; ++j) slot_soa[size_t(j) * nc + c] = pos[cm[size_t(c) * npc + j]]++;
 }
 
 // largest eigenvalue of a symmetric tridiagonal matrix (bisection with
@@ -225,8 +255,8 @@ double estimate_lambda(Problem& P, int l, hipStream_t s) {
   std::vector<double> alphas, betas;
   for (int j = 0; j < iters; ++j) {
     if (!(rho > 0.0)) break;
-    fill_dev(q, n, 0.0, s);
-    P.kt->f64.apply(V.v, p, q, P.m64, s);
+    P.kt->f64.apply_e(V.v, p, P.E, P.m64, s);
+    hipLaunchKernelGGL(dev::seg_plain<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, P.E, q);
     double pq = dot_host(P, p, q, n, s);
     if (!(pq > 0.0)) break;
     double alpha = rho / pq;
@@ -336,6 +366,25 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     LevelData& D = M.levels[l];
     DevLevel& V = P.lv[l];
     h2d(V.v.cmap, soa(D.cellmap, D.n_cells, M.npc), s);
+    {
+      std::vector<int32_t> off, sl;
+      build_slots(D.cellmap, D.n_cells, M.npc, D.n_dofs, off, sl);
+      h2d(V.v.slot, sl, s);
+      h2d(V.v.soff, off, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    if (l >= 1) {
+      // restriction slots: (family, parent node) -> coarse node-major entries
+      const LevelData& Pl = M.levels[l - 1];
+      std::vector<int32_t> pm(size_t(D.n_fam) * M.npc);
+      for (int64_t f = 0; f < D.n_fam; ++f)
+        for (int j = 0; j < M.npc; ++j) pm[size_t(f) * M.npc + j] = Pl.cellmap[size_t(D.parent[f]) * M.npc + j];
+      std::vector<int32_t> off, sl;
+      build_slots(pm, D.n_fam, M.npc, Pl.n_dofs, off, sl);
+      h2d(V.v.rslot, sl, s);
+      h2d(P.lv[l - 1].v.roff, off, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
     if (V.v.scale) {
       std::vector<double> sc(D.n_cells);
       double hd = M.dim == 3 ? std::ldexp(1.0, -l) : 1.0;
@@ -359,6 +408,33 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
       cm[i] = v >= 0 ? v : (int32_t)(M.n_dofs + (-v - 1));
     }
     h2d(P.leaf.cmap, soa(cm, M.n_leaves, M.npc), s);
+    {
+      std::vector<int32_t> off, sl;
+      build_slots(cm, M.n_leaves, M.npc, M.n_dofs + M.n_hanging, off, sl);
+      h2d(P.leaf.slot, sl, s);
+      h2d(P.leaf.soff, off, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    {
+      // transposed constraints: for each master DoF, its hanging nodes
+      std::vector<int64_t> toff(M.n_dofs + 1, 0);
+      for (auto m : M.con_mas) ++toff[m + 1];
+      for (int64_t i = 0; i < M.n_dofs; ++i) toff[i + 1] += toff[i];
+      std::vector<int64_t> pos(toff.begin(), toff.end() - 1);
+      std::vector<int32_t> th(M.con_mas.size());
+      std::vector<double> tw(M.con_mas.size());
+      for (int64_t h = 0; h < M.n_hanging; ++h)
+        for (int64_t q = M.con_off[h]; q < M.con_off[h + 1]; ++q) {
+          int64_t at = pos[M.con_mas[q]]++;
+          th[at] = (int32_t)h;
+          tw[at] = M.con_w[q];
+        }
+      h2d(P.leaf.toff, toff, s);
+      h2d(P.leaf.th, th, s);
+      h2d(P.leaf.tw, tw, s);
+      h2d(P.leaf.dir, M.dirichlet, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
     std::vector<double> sc(M.n_leaves), ms(M.n_leaves);
     for (int64_t c = 0; c < M.n_leaves; ++c) {
       double h = std::ldexp(1.0, -M.leaf_level[c]);
@@ -422,13 +498,10 @@ void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s
   const Maps& M = P.maps;
   const int64_t N = M.n_dofs, H = M.n_hanging;
   if (H) hipLaunchKernelGGL(dev::hang_fill, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.con_off, P.con_mas, P.con_w, x, P.xh);
-  fill_dev(y, N, 0.0, s);
-  fill_dev(P.yh, H, 0.0, s);
-  P.kt->leaf_apply(P.leaf, x, P.xh, y, P.yh, mass, P.m64, s);
-  if (H)
-    hipLaunchKernelGGL(dev::hang_condense, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.con_off, P.con_mas, P.con_w, P.yh, y);
-  if (P.n_dir)
-    hipLaunchKernelGGL(dev::zero_list<double>, dim3(grid1(P.n_dir)), dim3(dev::kBlock), 0, s, P.n_dir, P.dir, y);
+  P.kt->leaf_e(P.leaf, x, P.xh, P.E, mass, P.m64, s);
+  if (H) hipLaunchKernelGGL(dev::seg_hang, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.leaf.soff + N, P.E, P.yh);
+  hipLaunchKernelGGL(dev::seg_leaf, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.toff,
+                     P.leaf.th, P.leaf.tw, P.yh, P.leaf.dir, y);
 }
 
 template <typename T>
@@ -444,27 +517,45 @@ const MatsH<float>& mats<float>(Problem& P) { return P.m32; }
 template <>
 const MatsH<double>& mats<double>(Problem& P) { return P.m64; }
 
-// Chebyshev smoothing on level l (Sec. 4.1): m steps on A^S with Jacobi,
-// damping [lo, hi] * lambda_max.  zero_start: first step from x = 0
-// without an operator application.
+struct Cheb {
+  double theta, delta, sigma;
+};
+static Cheb cheb_of(const Problem& P, int l) {
+  const double a = P.opt.cheb_lo * P.lv[l].lam, b = P.opt.cheb_hi * P.lv[l].lam;
+  Cheb c;
+  c.theta = 0.5 * (b + a);
+  c.delta = 0.5 * (b - a);
+  c.sigma = c.theta / c.delta;
+  return c;
+}
+
+// Chebyshev smoothing steps on level l (Sec. 4.1 smoother): steps
+// first..m of the semi-iteration on D^{-1} A^S, each an operator application
+// (two passes) whose second pass performs the vector update.  Pre-smoothing
+// enters with step 1 already done (from x = 0, no operator needed);
+// post-smoothing starts at step 1 from the prolongated x, whose interface
+// values stay fixed so that every residual includes A^{SI} x^I.
 template <typename T>
-static void smooth(Problem& P, int l, bool zero_start, hipStream_t s) {
+static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
   DevLevel& V = P.lv[l];
   const int64_t n = V.v.n_dofs, o = V.off;
-  T *X = (T*)P.lx + o, *G = (T*)P.lg + o, *Tt = (T*)P.lt + o, *Dd = (T*)P.ld + o, *Di = (T*)P.ldinv + o;
-  const double a = P.opt.cheb_lo * V.lam, b = P.opt.cheb_hi * V.lam;
-  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
-  double rho_old = 1.0 / sigma;
+  T *X = (T*)P.lx + o, *G = (T*)P.lg + o, *Dd = (T*)P.ld + o, *Di = (T*)P.ldinv + o;
+  T* E = (T*)P.E;
+  const Cheb c = cheb_of(P, l);
+  double rho_old = 1.0 / c.sigma;
   const LevelOps<T>& op = ops<T>(P);
-  if (!zero_start) op.apply(V.v, X, Tt, mats<T>(P), s);
-  hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, X, Dd, G, Tt, Di, T(0),
-                     T(1.0 / theta), zero_start ? 1 : 0);
-  for (int j = 2; j <= P.opt.cheb_degree; ++j) {
-    op.apply(V.v, X, Tt, mats<T>(P), s);
-    const double rho = 1.0 / (2.0 * sigma - rho_old);
-    hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, X, Dd, G, Tt, Di,
-                       T(rho * rho_old), T(2.0 * rho / delta), 0);
-    rho_old = rho;
+  for (int j = 1; j <= P.opt.cheb_degree; ++j) {
+    double c1 = 0.0, c2 = 1.0 / c.theta;
+    if (j >= 2) {
+      const double rho = 1.0 / (2.0 * c.sigma - rho_old);
+      c1 = rho * rho_old;
+      c2 = 2.0 * rho / c.delta;
+      rho_old = rho;
+    }
+    if (j < first) continue;
+    op.apply_e(V.v, X, E, mats<T>(P), s);
+    hipLaunchKernelGGL(dev::seg_cheb<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, E, X, Dd, G, Di,
+                       T(c1), T(c2));
   }
 }
 
@@ -472,37 +563,44 @@ static void smooth(Problem& P, int l, bool zero_start, hipStream_t s) {
 // Sec. 2.3): leaf residual entries enter the hierarchy on the coarsest level
 // holding them as S nodes; smoothing acts on V^S only; the residual on S and
 // I rows is restricted; after prolongation the interface values enter the
-// post-smoothing right-hand side through A^{SI}.
+// post-smoothing residuals through A^{SI}.
 template <typename T>
 static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
   const Maps& M = P.maps;
   const int L = (int)P.lv.size() - 1;
   const int64_t N = M.n_dofs;
-  T *X = (T*)P.lx, *G = (T*)P.lg, *Tt = (T*)P.lt;
+  T *X = (T*)P.lx, *G = (T*)P.lg, *R = (T*)P.lt, *Dd = (T*)P.ld, *Di = (T*)P.ldinv;
+  T* E = (T*)P.E;
   const LevelOps<T>& op = ops<T>(P);
   fill_dev(G, P.n_total, T(0), s);
   hipLaunchKernelGGL(dev::copy_to_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, r, G);
+  if (L >= 1) {
+    // first pre-smoothing step on the finest level: x = D^{-1} g / theta
+    DevLevel& V = P.lv[L];
+    hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(V.v.n_dofs)), dim3(dev::kBlock), 0, s, V.v.n_dofs, X + V.off,
+                       Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0), T(1.0 / cheb_of(P, L).theta), 1);
+  }
   for (int l = L; l >= 1; --l) {
     DevLevel& V = P.lv[l];
+    const int64_t n = V.v.n_dofs;
     if (V.n_S > 0) {
-      smooth<T>(P, l, true, s);
-      op.apply(V.v, X + V.off, Tt + V.off, mats<T>(P), s);
-    } else {
-      fill_dev(X + V.off, V.v.n_dofs, T(0), s);
+      smooth_steps<T>(P, l, 2, s);
+      op.apply_e(V.v, X + V.off, E, mats<T>(P), s);
     }
-    op.restrict_(V.v, P.lv[l - 1].v, G + V.off, Tt + V.off, G + P.lv[l - 1].off, mats<T>(P), s);
+    hipLaunchKernelGGL(dev::seg_residual<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, E, G + V.off,
+                       V.v.flags, R + V.off, V.n_S > 0 ? 1 : 0);
+    op.restrict_e(V.v, R + V.off, E, mats<T>(P), s);
+    DevLevel& W = P.lv[l - 1];
+    const double c2 = l - 1 >= 1 ? 1.0 / cheb_of(P, l - 1).theta : 0.0;
+    hipLaunchKernelGGL(dev::seg_restrict_start<T>, dim3(grid1(W.v.n_dofs)), dim3(dev::kBlock), 0, s, W.v.n_dofs,
+                       W.v.roff, E, G + W.off, X + W.off, Dd + W.off, Di + W.off, T(c2), l - 1 >= 1 ? 1 : 0);
   }
   hipLaunchKernelGGL(dev::coarse_solve<T>, dim3(1), dim3(dev::kBlock), P.n0 * sizeof(double), s,
                      (int)P.lv[0].v.n_dofs, P.n0, P.ainv, P.cidx, G + P.lv[0].off, X + P.lv[0].off);
   for (int l = 1; l <= L; ++l) {
     DevLevel& V = P.lv[l];
     op.prolong(V.v, P.lv[l - 1].v, X + P.lv[l - 1].off, X + V.off, mats<T>(P), s);
-    if (V.n_S > 0) {
-      op.edge(V.v, X + V.off, G + V.off, T(-1), mats<T>(P), s);
-      if (V.n_I)
-        hipLaunchKernelGGL(dev::zero_list<T>, dim3(grid1(V.n_I)), dim3(dev::kBlock), 0, s, V.n_I, V.ilist, X + V.off);
-      smooth<T>(P, l, false, s);
-    }
+    if (V.n_S > 0) smooth_steps<T>(P, l, 1, s);
   }
   hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, X, z);
 }
@@ -545,18 +643,24 @@ void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hi
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
   if (l < 0 || l >= (int)P.lv.size()) fail(GMG_E_INVAL, "level out of range");
   DevLevel& V = P.lv[l];
+  const int64_t n = V.v.n_dofs;
   if (P.opt.mg_precision == 32) {
-    fill_dev((float*)y, V.v.n_dofs, 0.0f, s);
-    if (variant == 0)
-      P.kt->f32.apply(V.v, (const float*)x, (float*)y, P.m32, s);
-    else
+    if (variant == 0) {
+      P.kt->f32.apply_e(V.v, (const float*)x, (float*)P.E, P.m32, s);
+      hipLaunchKernelGGL(dev::seg_plain<float>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, (const float*)P.E,
+                         (float*)y);
+    } else {
+      fill_dev((float*)y, n, 0.0f, s);
       P.kt->f32.edge(V.v, (const float*)x, (float*)y, 1.0f, P.m32, s);
+    }
   } else {
-    fill_dev((double*)y, V.v.n_dofs, 0.0, s);
-    if (variant == 0)
-      P.kt->f64.apply(V.v, (const double*)x, (double*)y, P.m64, s);
-    else
+    if (variant == 0) {
+      P.kt->f64.apply_e(V.v, (const double*)x, P.E, P.m64, s);
+      hipLaunchKernelGGL(dev::seg_plain<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, P.E, (double*)y);
+    } else {
+      fill_dev((double*)y, n, 0.0, s);
       P.kt->f64.edge(V.v, (const double*)x, (double*)y, 1.0, P.m64, s);
+    }
   }
   HIPCHECK(hipGetLastError());
 }
