@@ -197,6 +197,60 @@ int gmg_vcycle(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream
  * V-cycles. */
 int gmg_problem_last_timing(gmg_problem p, double* out3);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop for many solves on different adaptive meshes (continuous
+ * batching): host threads build each request's maps as it arrives; a
+ * scheduler thread admits ready requests in arrival order whenever a slot
+ * and enough arena memory are free (first fit), sets them up on the device
+ * on the slot's stream and then advances every resident solve one CG
+ * iteration per tick, each on its own stream with its V-cycle replayed as a
+ * captured HIP graph.  A finished request frees its slot and memory for the
+ * next one.  Results do not depend on the other resident requests (all
+ * kernels are deterministic). */
+
+typedef struct {       /* seconds on the server clock (0 = gmg_server_create) */
+  double arrival;      /* submit */
+  double setup_done;   /* host maps built */
+  double admitted;     /* slot and memory granted */
+  double bound;        /* device set-up done, CG started */
+  double finished;     /* solution copied back (or failure) */
+} gmg_timing;
+
+typedef struct {
+  int64_t queued, running, completed, failed;
+  size_t arena_used, arena_peak, arena_bytes;
+  double dofs_done;    /* sum of DoFs of completed requests */
+  double clock;        /* server clock now */
+} gmg_server_stats_t;
+
+enum { GMG_REQ_QUEUED = 0, GMG_REQ_SETUP = 1, GMG_REQ_READY = 2, GMG_REQ_BINDING = 3, GMG_REQ_RUNNING = 4,
+       GMG_REQ_DONE = 5, GMG_REQ_FAILED = 6 };
+
+/* d_arena: device memory owned by the caller (256-byte aligned) that holds
+ * the workspaces of resident requests; arena_bytes is the HBM budget.
+ * max_slots: resident requests at most (1..64); host_threads: workers for
+ * host set-up and device binding (1..64).  Uses the current device. */
+int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int32_t host_threads,
+                      gmg_server* out);
+/* Queue a solve with nodal right-hand side f = f_value.  The server takes
+ * the mesh (the handle is invalid afterwards).  cell_coeff: [n_leaves] or
+ * NULL (copied).  A request larger than the arena fails with GMG_E_BUDGET. */
+int gmg_server_submit(gmg_server s, gmg_mesh mesh, const gmg_options* opts, const double* cell_coeff,
+                      double f_value, uint64_t* request_id);
+int gmg_server_poll(gmg_server s, uint64_t request_id, int32_t* state, int32_t* status);
+/* Block until the request is done or failed; GMG_E_STATE on timeout. */
+int gmg_server_wait(gmg_server s, uint64_t request_id, double timeout_s);
+/* Outputs of a finished request: u_host [n_dofs] (may be NULL; query n_dofs
+ * first with u_host = NULL), iterations, history [iterations+1], timing.
+ * Returns the solve status, or the failure code of a failed request. */
+int gmg_server_result(gmg_server s, uint64_t request_id, double* u_host, int64_t* n_dofs,
+                      int32_t* iterations, double* history, gmg_timing* timing);
+/* Forget a finished request. */
+int gmg_server_release(gmg_server s, uint64_t request_id);
+int gmg_server_stats(gmg_server s, gmg_server_stats_t* out);
+/* Stops the threads after the current tick; resident solves are abandoned. */
+int gmg_server_destroy(gmg_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,17 @@ struct DevLevel {
   double lam = 1.0;    // lambda_max estimate of D^{-1} A^S
 };
 
+// state of an asynchronous CG solve
+struct CgState {
+  bool running = false, pending = false, timed = false;
+  int it = 0;            // iterations done
+  int status = 0;
+  double nb = 0.0;       // ||b||
+  double* u = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<double> hist;
+};
+
 struct Problem {
   gmg_options opt{};
   Maps maps;
@@ -55,6 +66,7 @@ struct Problem {
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
   double timing[3] = {0, 0, 0};
+  CgState cg;
   std::vector<hipEvent_t> ev;
 
   ~Problem();
@@ -65,6 +77,8 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s);
 void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s);
 void vcycle(Problem& P, const double* r, double* z, hipStream_t s);
 int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s);
+void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed);
+bool cg_poll(Problem& P, bool block);
 void set_constant(double* p, int64_t n, double v, hipStream_t s);
 void apply_level_hook(Problem& P, int level, int variant, const void* x, void* y, hipStream_t s);
 

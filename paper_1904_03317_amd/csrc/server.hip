@@ -1,0 +1,495 @@
+// Serving loop: many Poisson solves on different adaptive meshes resident in
+// one HBM arena at once.  Host worker threads build each request's maps as
+// it arrives; the scheduler thread admits ready requests whenever a slot and
+// enough arena memory are free (first fit), binds them (upload and device
+// set-up on the slot's stream), and then advances every resident solve by
+// one CG iteration per tick, each on its own stream with its V-cycle replayed
+// as a captured HIP graph, so the work of different requests overlaps on the
+// device.  Requests leave when their residual reaches the tolerance and
+// their memory and slot go to the next ones (continuous batching at CG
+// iteration granularity).  All kernels are deterministic, so a result does
+// not depend on what else was resident.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/gmg.h"
+#include "host/forest.hpp"
+#include "problem.hpp"
+
+struct gmg_mesh_s {
+  std::unique_ptr<gmg::Forest> f;
+};
+
+namespace gmg {
+
+#define SRV_HIPCHECK(x)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess) gmg::fail(GMG_E_HIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+enum ReqState { kQueued = 0, kSetup = 1, kReady = 2, kBinding = 3, kRunning = 4, kDone = 5, kFailed = 6 };
+
+struct Request {
+  uint64_t id = 0;
+  int state = kQueued;
+  int status = 0;
+  std::string error;
+  std::unique_ptr<Forest> mesh;
+  gmg_options opt{};
+  std::vector<double> coeff;
+  double f_value = 1.0;
+  std::unique_ptr<Problem> P;
+  size_t ws_bytes = 0, arena_off = 0;
+  int slot = -1;
+  double* d_f = nullptr;   // inside the workspace tail: f (nodal) and u
+  double* d_u = nullptr;
+  gmg_timing t{};
+  std::vector<double> u_host;
+  int iterations = 0;
+  std::vector<double> hist;
+};
+
+// first-fit allocator over the arena (offsets), 256-byte granularity
+class Arena {
+ public:
+  explicit Arena(size_t bytes) : size_(bytes) { free_[0] = bytes; }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        *off = it->first;
+        size_t rest = it->second - n, start = it->first + n;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += n;
+        peak_ = std::max(peak_, used_);
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Server {
+  char* arena_base = nullptr;
+  Arena arena;
+  int max_slots = 1;
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<int> slot_free;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> setup_q;    // queued, waiting for a host worker
+  std::deque<Request*> ready_q;    // maps built, waiting for admission
+  std::deque<Request*> bind_q;     // admitted, waiting for device set-up
+  std::vector<Request*> running;
+  std::map<uint64_t, std::unique_ptr<Request>> all;
+  std::vector<std::thread> workers;
+  std::thread sched;
+  std::atomic<bool> stop{false};
+  uint64_t next_id = 1;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  int64_t completed = 0, failed = 0;
+  double dofs_done = 0.0;
+
+  Server(char* base, size_t bytes, int slots) : arena_base(base), arena(bytes), max_slots(slots) {}
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+size_t request_bytes(const Problem& P) { return P.ws_need + 2 * (size_t(P.maps.n_dofs) * 8 + 256); }
+
+void fail_request(Server& S, Request* r, int code, const std::string& msg) {
+  r->state = kFailed;
+  r->status = code;
+  r->error = msg;
+  r->t.finished = S.now();
+  ++S.failed;
+}
+
+void worker_loop(Server* S) {
+  SRV_HIPCHECK(hipSetDevice(S->device));
+  while (true) {
+    Request* r = nullptr;
+    bool bind_job = false;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->setup_q.empty() || !S->bind_q.empty(); });
+      if (S->stop) return;
+      if (!S->bind_q.empty()) {
+        r = S->bind_q.front();
+        S->bind_q.pop_front();
+        bind_job = true;
+      } else {
+        r = S->setup_q.front();
+        S->setup_q.pop_front();
+        r->state = kSetup;
+      }
+    }
+    try {
+      if (!bind_job) {
+        // host set-up: forest -> maps (no device work)
+        auto P = std::make_unique<Problem>();
+        P->opt = r->opt;
+        P->kt = kernel_table(r->mesh->dim(), r->opt.degree);
+        if (!P->kt) fail(GMG_E_INVAL, "no kernels for this dimension/degree");
+        P->maps = build_maps(*r->mesh, r->opt.degree, r->coeff.empty() ? nullptr : r->coeff.data());
+        const FE1D& fe = P->maps.fe;
+        for (int i = 0; i < 25; ++i) {
+          P->m64.M[i] = fe.M[i];
+          P->m64.K[i] = fe.K[i];
+          P->m32.M[i] = (float)fe.M[i];
+          P->m32.K[i] = (float)fe.K[i];
+        }
+        for (int i = 0; i < 45; ++i) {
+          P->m64.E[i] = fe.E[i];
+          P->m32.E[i] = (float)fe.E[i];
+        }
+        P->ws_need = plan_workspace(*P, nullptr);
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->P = std::move(P);
+        r->mesh.reset();
+        r->ws_bytes = request_bytes(*r->P);
+        r->t.setup_done = S->now();
+        if (r->ws_bytes > S->arena.size()) {
+          fail_request(*S, r, GMG_E_BUDGET, "request needs more device memory than the arena holds");
+          S->cv_done.notify_all();
+        } else {
+          r->state = kReady;
+          S->ready_q.push_back(r);
+        }
+      } else {
+        // device set-up on the request's slot stream
+        Problem& P = *r->P;
+        hipStream_t s = S->streams[r->slot];
+        char* base = S->arena_base + r->arena_off;
+        bind_problem(P, base, P.ws_need, s);
+        P.opt.use_graph = 1;
+        const int64_t N = P.maps.n_dofs;
+        size_t tail = (P.ws_need + 255) & ~size_t(255);
+        r->d_f = reinterpret_cast<double*>(base + tail);
+        r->d_u = reinterpret_cast<double*>(base + tail + ((size_t(N) * 8 + 255) & ~size_t(255)));
+        set_constant(r->d_f, N, r->f_value, s);
+        apply_leaf(P, r->d_f, P.cb, true, s);
+        cg_start(P, P.cb, r->d_u, s, false);
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->t.bound = S->now();
+        r->state = kRunning;
+        S->running.push_back(r);
+      }
+    } catch (const Error& e) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (bind_job) {
+        S->arena.release(r->arena_off, r->ws_bytes);
+        S->slot_free.push_back(r->slot);
+      }
+      fail_request(*S, r, e.code, e.what());
+      S->cv_done.notify_all();
+    } catch (const std::exception& e) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (bind_job) {
+        S->arena.release(r->arena_off, r->ws_bytes);
+        S->slot_free.push_back(r->slot);
+      }
+      fail_request(*S, r, GMG_E_INVAL, e.what());
+      S->cv_done.notify_all();
+    }
+  }
+}
+
+void scheduler_loop(Server* S) {
+  SRV_HIPCHECK(hipSetDevice(S->device));
+  while (!S->stop) {
+    bool idle = true;
+    {
+      // admission: FIFO over ready requests, first fit in the arena
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto it = S->ready_q.begin(); it != S->ready_q.end() && !S->slot_free.empty();) {
+        Request* r = *it;
+        size_t off;
+        if (S->arena.alloc(r->ws_bytes, &off)) {
+          r->arena_off = off;
+          r->slot = S->slot_free.back();
+          S->slot_free.pop_back();
+          r->state = kBinding;
+          r->t.admitted = S->now();
+          S->bind_q.push_back(r);
+          it = S->ready_q.erase(it);
+          S->cv_work.notify_all();
+          idle = false;
+        } else {
+          break;  // keep arrival order: wait for memory
+        }
+      }
+    }
+    std::vector<Request*> run;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      run = S->running;
+    }
+    for (Request* r : run) {
+      bool done = false;
+      int status = 0;
+      std::string err;
+      try {
+        done = cg_poll(*r->P, false);
+        status = r->P->cg.status;
+      } catch (const Error& e) {
+        done = true;
+        status = e.code;
+        err = e.what();
+      }
+      if (!done) continue;
+      idle = false;
+      Problem& P = *r->P;
+      hipStream_t s = S->streams[r->slot];
+      r->iterations = P.cg.it;
+      r->hist.assign(P.cg.hist.begin(), P.cg.hist.begin() + P.cg.it + 1);
+      r->u_host.resize(P.maps.n_dofs);
+      if (status >= 0) {
+        hipError_t e1 = hipMemcpyAsync(r->u_host.data(), r->d_u, P.maps.n_dofs * sizeof(double),
+                                       hipMemcpyDeviceToHost, s);
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+          status = GMG_E_HIP;
+          err = "copying the solution back failed";
+        }
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->running.erase(std::find(S->running.begin(), S->running.end(), r));
+      S->arena.release(r->arena_off, r->ws_bytes);
+      S->slot_free.push_back(r->slot);
+      r->t.finished = S->now();
+      r->status = status;
+      r->error = err;
+      r->state = status >= 0 ? kDone : kFailed;
+      if (status >= 0) {
+        ++S->completed;
+        S->dofs_done += (double)P.maps.n_dofs;
+      } else {
+        ++S->failed;
+      }
+      r->P.reset();   // drop host maps and device views; the arena range is free
+      S->cv_done.notify_all();
+    }
+    if (idle) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+}  // namespace gmg
+
+using gmg::Server;
+
+struct gmg_server_s {
+  std::unique_ptr<Server> S;
+};
+
+namespace {
+template <typename F>
+int sguard(F&& f) {
+  try {
+    return f();
+  } catch (const gmg::Error& e) {
+    gmg::set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    gmg::set_last_error(e.what());
+    return GMG_E_INVAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int32_t host_threads,
+                      gmg_server* out) {
+  return sguard([&] {
+    if (!d_arena || !out || max_slots < 1 || max_slots > 64 || host_threads < 1 || host_threads > 64)
+      gmg::fail(GMG_E_INVAL, "invalid server arguments");
+    if (reinterpret_cast<uintptr_t>(d_arena) & 255) gmg::fail(GMG_E_INVAL, "arena must be 256-byte aligned");
+    auto h = std::make_unique<gmg_server_s>();
+    h->S = std::make_unique<Server>((char*)d_arena, arena_bytes, max_slots);
+    Server& S = *h->S;
+    SRV_HIPCHECK(hipGetDevice(&S.device));
+    S.streams.resize(max_slots);
+    for (int i = 0; i < max_slots; ++i) {
+      SRV_HIPCHECK(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
+      S.slot_free.push_back(max_slots - 1 - i);
+    }
+    for (int i = 0; i < host_threads; ++i) S.workers.emplace_back(gmg::worker_loop, &S);
+    S.sched = std::thread(gmg::scheduler_loop, &S);
+    *out = h.release();
+    return 0;
+  });
+}
+
+int gmg_server_submit(gmg_server h, gmg_mesh mesh, const gmg_options* opts, const double* cell_coeff,
+                      double f_value, uint64_t* request_id) {
+  return sguard([&] {
+    if (!h || !mesh || !opts || !request_id) gmg::fail(GMG_E_INVAL, "null argument");
+    if (opts->degree < 1 || opts->degree > 4 || (opts->mg_precision != 32 && opts->mg_precision != 64) ||
+        opts->cheb_degree < 1 || opts->max_iter < 1 || !(opts->rtol > 0) || opts->eig_iters < 1 ||
+        !(opts->cheb_lo > 0) || !(opts->cheb_hi > opts->cheb_lo))
+      gmg::fail(GMG_E_INVAL, "invalid options");
+    Server& S = *h->S;
+    auto r = std::make_unique<gmg::Request>();
+    r->opt = *opts;
+    r->f_value = f_value;
+    const int64_t nl = (int64_t)mesh->f->leaves().size();
+    if (cell_coeff) r->coeff.assign(cell_coeff, cell_coeff + nl);
+    r->mesh = std::move(mesh->f);
+    delete mesh;
+    std::lock_guard<std::mutex> lk(S.mu);
+    r->id = S.next_id++;
+    r->t.arrival = S.now();
+    *request_id = r->id;
+    S.setup_q.push_back(r.get());
+    S.all[r->id] = std::move(r);
+    S.cv_work.notify_all();
+    return 0;
+  });
+}
+
+int gmg_server_poll(gmg_server h, uint64_t id, int32_t* state, int32_t* status) {
+  return sguard([&] {
+    if (!h || !state || !status) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    *state = it->second->state;
+    *status = it->second->status;
+    return 0;
+  });
+}
+
+int gmg_server_wait(gmg_server h, uint64_t id, double timeout_s) {
+  return sguard([&] {
+    if (!h) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    gmg::Request* r = it->second.get();
+    bool ok = S.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                 [&] { return r->state == gmg::kDone || r->state == gmg::kFailed; });
+    if (!ok) gmg::fail(GMG_E_STATE, "timeout waiting for request");
+    return 0;
+  });
+}
+
+int gmg_server_result(gmg_server h, uint64_t id, double* u_host, int64_t* n_dofs, int32_t* iterations,
+                      double* history, gmg_timing* t) {
+  return sguard([&] {
+    if (!h) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    gmg::Request* r = it->second.get();
+    if (r->state == gmg::kFailed) {
+      gmg::set_last_error(r->error);
+      if (t) *t = r->t;
+      return r->status;
+    }
+    if (r->state != gmg::kDone) gmg::fail(GMG_E_STATE, "request not finished");
+    if (n_dofs) *n_dofs = (int64_t)r->u_host.size();
+    if (u_host) std::memcpy(u_host, r->u_host.data(), r->u_host.size() * sizeof(double));
+    if (iterations) *iterations = r->iterations;
+    if (history) std::memcpy(history, r->hist.data(), r->hist.size() * sizeof(double));
+    if (t) *t = r->t;
+    return r->status;
+  });
+}
+
+int gmg_server_release(gmg_server h, uint64_t id) {
+  return sguard([&] {
+    if (!h) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    if (it->second->state != gmg::kDone && it->second->state != gmg::kFailed)
+      gmg::fail(GMG_E_STATE, "request still in flight");
+    S.all.erase(it);
+    return 0;
+  });
+}
+
+int gmg_server_stats(gmg_server h, gmg_server_stats_t* o) {
+  return sguard([&] {
+    if (!h || !o) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    o->queued = (int64_t)(S.setup_q.size() + S.ready_q.size());
+    o->running = (int64_t)(S.running.size() + S.bind_q.size());
+    o->completed = S.completed;
+    o->failed = S.failed;
+    o->arena_used = S.arena.used();
+    o->arena_peak = S.arena.peak();
+    o->arena_bytes = S.arena.size();
+    o->dofs_done = S.dofs_done;
+    o->clock = S.now();
+    return 0;
+  });
+}
+
+int gmg_server_destroy(gmg_server h) {
+  if (!h) return 0;
+  Server& S = *h->S;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+    S.cv_work.notify_all();
+  }
+  for (auto& t : S.workers) t.join();
+  if (S.sched.joinable()) S.sched.join();
+  for (auto s : S.streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  delete h;
+  return 0;
+}
+
+}  // extern "C"

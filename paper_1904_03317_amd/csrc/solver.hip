@@ -357,7 +357,7 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
   HIPCHECK(hipGetDevice(&P.device));
   if (!P.host) HIPCHECK(hipHostMalloc((void**)&P.host, 64 * sizeof(double), hipHostMallocDefault));
   if (P.ev.empty()) {
-    P.ev.resize(4);
+    P.ev.resize(5);
     for (auto& e : P.ev) HIPCHECK(hipEventCreate(&e));
   }
   const int L = (int)M.levels.size() - 1;
@@ -666,12 +666,23 @@ void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hi
 }
 
 // ---------------------------------------------------------------- CG
-int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s) {
+// Preconditioned CG (x0 = 0, stop at ||r|| <= rtol ||b||) as a state machine:
+// cg_start enqueues the set-up and the read-back of ||b||^2; every
+// cg_poll that finds the last read-back complete checks it and enqueues the
+// next iteration (V-cycle, r.z, p update, leaf operator, p.Ap, x/r update,
+// r.r, read-back).  The scalars alpha, beta, rho stay on the device.
+void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed) {
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
   const int64_t N = P.maps.n_dofs;
   const unsigned dg = dot_grid(N);
   double* sc = P.scal;
-  HIPCHECK(hipEventRecord(P.ev[0], s));
+  CgState& C = P.cg;
+  C = CgState{};
+  C.u = u;
+  C.stream = s;
+  C.timed = timed;
+  C.hist.assign(P.opt.max_iter + 1, 0.0);
+  if (timed) HIPCHECK(hipEventRecord(P.ev[0], s));
   fill_dev(u, N, 0.0, s);
   fill_dev(P.cp, N, 0.0, s);
   hipLaunchKernelGGL(dev::copy_vec, dim3(dot_grid(N)), dim3(dev::kBlock), 0, s, N, b, P.cr);
@@ -679,65 +690,115 @@ int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, 
   hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 3);
   fill_dev(sc + dev::kFirst, 1, 1.0, s);
   HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  const double bb = P.host[dev::kBb];
-  if (hist) hist[0] = bb > 0 ? 1.0 : 0.0;
-  *iters = 0;
+  HIPCHECK(hipEventRecord(P.ev[4], s));
+  C.pending = true;
+  C.running = true;
   P.timing[1] = 0.0;
   P.timing[2] = 0.0;
-  if (!std::isfinite(bb)) return GMG_E_NAN;
-  if (bb == 0.0) {
-    HIPCHECK(hipEventRecord(P.ev[1], s));
+}
+
+static void cg_enqueue_iteration(Problem& P) {
+  CgState& C = P.cg;
+  hipStream_t s = C.stream;
+  const int64_t N = P.maps.n_dofs;
+  const unsigned dg = dot_grid(N);
+  double* sc = P.scal;
+  if (C.timed) HIPCHECK(hipEventRecord(P.ev[2], s));
+  precondition(P, s);
+  if (C.timed) HIPCHECK(hipEventRecord(P.ev[3], s));
+  hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cr, P.cz, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 0);
+  hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
+  apply_leaf(P, P.cp, P.cq, false, s);
+  hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cp, P.cq, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 1);
+  hipLaunchKernelGGL(dev::update_xr, dim3(dg), dim3(dev::kBlock), 0, s, N, C.u, P.cr, P.cp, P.cq, sc, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 2);
+  HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipEventRecord(P.ev[4], s));
+  C.pending = true;
+}
+
+static void cg_finish(Problem& P, int status) {
+  CgState& C = P.cg;
+  C.status = status;
+  C.running = false;
+  if (C.timed) {
+    HIPCHECK(hipEventRecord(P.ev[1], C.stream));
     HIPCHECK(hipEventSynchronize(P.ev[1]));
     float ms = 0;
     (void)hipEventElapsedTime(&ms, P.ev[0], P.ev[1]);
     P.timing[0] = ms * 1e-3;
-    return GMG_OK;
   }
-  const double nb = std::sqrt(bb);
-  int status = GMG_NOT_CONVERGED;
-  for (int it = 1; it <= P.opt.max_iter; ++it) {
-    HIPCHECK(hipEventRecord(P.ev[2], s));
-    precondition(P, s);
-    HIPCHECK(hipEventRecord(P.ev[3], s));
-    hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cr, P.cz, P.part);
-    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 0);
-    hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
-    apply_leaf(P, P.cp, P.cq, false, s);
-    hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cp, P.cq, P.part);
-    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 1);
-    hipLaunchKernelGGL(dev::update_xr, dim3(dg), dim3(dev::kBlock), 0, s, N, u, P.cr, P.cp, P.cq, sc, P.part);
-    hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 2);
-    HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, P.ev[2], P.ev[3]);
-    P.timing[1] += ms * 1e-3;
-    P.timing[2] += 1;
-    *iters = it;
+}
+
+// returns true when the solve has finished (status in P.cg.status)
+bool cg_poll(Problem& P, bool block) {
+  CgState& C = P.cg;
+  if (!C.running) return true;
+  if (C.pending) {
+    if (block) {
+      HIPCHECK(hipEventSynchronize(P.ev[4]));
+    } else {
+      hipError_t e = hipEventQuery(P.ev[4]);
+      if (e == hipErrorNotReady) return false;
+      if (e != hipSuccess) fail(GMG_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+    }
+    C.pending = false;
+  }
+  if (C.it == 0) {
+    const double bb = P.host[dev::kBb];
+    C.hist[0] = bb > 0 ? 1.0 : 0.0;
+    if (!std::isfinite(bb)) {
+      cg_finish(P, GMG_E_NAN);
+      return true;
+    }
+    if (bb == 0.0) {
+      cg_finish(P, GMG_OK);
+      return true;
+    }
+    C.nb = std::sqrt(bb);
+  } else {
+    if (C.timed) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, P.ev[2], P.ev[3]);
+      P.timing[1] += ms * 1e-3;
+      P.timing[2] += 1;
+    }
     const double rr = P.host[dev::kRr], rho = P.host[dev::kRho], pq = P.host[dev::kPq];
     const double res = std::sqrt(rr);
-    if (hist) hist[it] = res / nb;
+    C.hist[C.it] = res / C.nb;
     if (!std::isfinite(rr) || !std::isfinite(rho) || !std::isfinite(pq)) {
-      status = GMG_E_NAN;
-      break;
+      cg_finish(P, GMG_E_NAN);
+      return true;
     }
     if (!(rho > 0.0) || !(pq > 0.0)) {
-      status = GMG_E_BREAKDOWN;
-      break;
+      cg_finish(P, GMG_E_BREAKDOWN);
+      return true;
     }
-    if (res <= P.opt.rtol * nb) {
-      status = GMG_OK;
-      break;
+    if (res <= P.opt.rtol * C.nb) {
+      cg_finish(P, GMG_OK);
+      return true;
+    }
+    if (C.it >= P.opt.max_iter) {
+      cg_finish(P, GMG_NOT_CONVERGED);
+      return true;
     }
   }
-  HIPCHECK(hipEventRecord(P.ev[1], s));
-  HIPCHECK(hipEventSynchronize(P.ev[1]));
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, P.ev[0], P.ev[1]);
-  P.timing[0] = ms * 1e-3;
+  ++C.it;
+  cg_enqueue_iteration(P);
+  return false;
+}
+
+int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s) {
+  cg_start(P, b, u, s, true);
+  while (!cg_poll(P, true)) {
+  }
+  *iters = P.cg.it;
+  if (hist)
+    for (int i = 0; i <= P.cg.it; ++i) hist[i] = P.cg.hist[i];
   HIPCHECK(hipGetLastError());
-  return status;
+  return P.cg.status;
 }
 
 }  // namespace gmg

@@ -34,6 +34,20 @@ class gmg_info(C.Structure):
                 ("workspace_bytes", C.c_size_t)]
 
 
+class gmg_timing(C.Structure):
+    _fields_ = [("arrival", C.c_double), ("setup_done", C.c_double), ("admitted", C.c_double),
+                ("bound", C.c_double), ("finished", C.c_double)]
+
+
+class gmg_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t),
+                ("arena_bytes", C.c_size_t), ("dofs_done", C.c_double), ("clock", C.c_double)]
+
+
+REQ_STATES = ["QUEUED", "SETUP", "READY", "BINDING", "RUNNING", "DONE", "FAILED"]
+
+
 class GMGError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"gmg error {code}: {msg}")
@@ -77,6 +91,15 @@ def lib():
         "gmg_apply_level": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp]),
         "gmg_vcycle": (C.c_int, [vp, vp, vp, vp]),
         "gmg_problem_last_timing": (C.c_int, [vp, C.POINTER(dbl)]),
+        "gmg_server_create": (C.c_int, [vp, C.c_size_t, i32, i32, C.POINTER(vp)]),
+        "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, dbl, C.POINTER(C.c_uint64)]),
+        "gmg_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(i32), C.POINTER(i32)]),
+        "gmg_server_wait": (C.c_int, [vp, C.c_uint64, dbl]),
+        "gmg_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(i64), C.POINTER(i32), vp,
+                                        C.POINTER(gmg_timing)]),
+        "gmg_server_release": (C.c_int, [vp, C.c_uint64]),
+        "gmg_server_stats": (C.c_int, [vp, C.POINTER(gmg_server_stats)]),
+        "gmg_server_destroy": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -93,7 +116,9 @@ def exported_symbols():
             "gmg_problem_create", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
             "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle",
-            "gmg_problem_last_timing"]
+            "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_poll",
+            "gmg_server_wait", "gmg_server_result", "gmg_server_release", "gmg_server_stats",
+            "gmg_server_destroy"]
 
 
 def _check(code):
@@ -245,6 +270,68 @@ class Problem:
             lib().gmg_problem_destroy(self.h)
             self.h = None
             self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (gmg_server_*): resident solves on one HBM arena."""
+
+    def __init__(self, arena_bytes, max_slots=8, host_threads=4, device="cuda"):
+        import torch
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(lib().gmg_server_create(_ptr(self.arena), self.arena.numel(), max_slots, host_threads,
+                                       C.byref(h)))
+        self.h = h
+
+    def submit(self, mesh: Mesh, opts=None, coeff=None, f_value=1.0):
+        """Queue a solve; the server takes the mesh."""
+        opts = opts if opts is not None else options()
+        c = None if coeff is None else np.ascontiguousarray(np.asarray(coeff, np.float64))
+        rid = C.c_uint64()
+        _check(lib().gmg_server_submit(self.h, mesh.h, C.byref(opts), _ptr(c), float(f_value), C.byref(rid)))
+        mesh.h = None
+        return rid.value
+
+    def poll(self, rid):
+        st, status = C.c_int32(), C.c_int32()
+        _check(lib().gmg_server_poll(self.h, rid, C.byref(st), C.byref(status)))
+        return REQ_STATES[st.value], status.value
+
+    def wait(self, rid, timeout=600.0):
+        _check(lib().gmg_server_wait(self.h, rid, float(timeout)))
+
+    def result(self, rid, max_iter=100):
+        n = C.c_int64()
+        it = C.c_int32()
+        t = gmg_timing()
+        code = lib().gmg_server_result(self.h, rid, None, C.byref(n), C.byref(it), None, C.byref(t))
+        _check(code)
+        u = np.zeros(n.value)
+        hist = np.zeros(max(max_iter, it.value) + 1)
+        code = _check(lib().gmg_server_result(self.h, rid, _ptr(u), C.byref(n), C.byref(it), _ptr(hist),
+                                              C.byref(t)))
+        return dict(status=code, u=u, iterations=it.value, history=hist[: it.value + 1],
+                    timing={f: getattr(t, f) for f, _ in gmg_timing._fields_})
+
+    def release(self, rid):
+        _check(lib().gmg_server_release(self.h, rid))
+
+    def stats(self):
+        s = gmg_server_stats()
+        _check(lib().gmg_server_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in gmg_server_stats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().gmg_server_destroy(self.h)
+            self.h = None
+            self.arena = None
 
     def __del__(self):
         try:
