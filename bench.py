@@ -50,6 +50,80 @@ def cpu_baseline(g_sample=2):
                       f"oracle FP64 CG solve only ({it} iterations, {t:.2f} s), BLAS limited to 1 thread"}
 
 
+def build_request_meshes(ids, threads=8):
+    """Library meshes of the serving-stream requests (input generation, done
+    before the stream starts)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import gmg_inputs as gi
+    from paper_1904_03317_amd import gmg
+
+    def one(r):
+        return gi.build_request_mesh(gi.request_spec(r), lambda d, o: gmg.Mesh(d, o),
+                                     lambda m, f: m.refine(f), lambda m: m.leaves())
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, ids))
+
+
+def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7):
+    """Open-loop serving stream of unit-cube Q2 requests (FP32 V-cycle, FP64
+    CG) with Poisson arrivals at `load` times the throughput measured in a
+    closed-loop warm-up.  Latency = completion - arrival on the server clock."""
+    import numpy as np
+
+    import gmg_inputs as gi
+    from paper_1904_03317_amd import gmg
+
+    opts = gmg.options(degree=2, mg_precision=32)
+    t0 = time.perf_counter()
+    warm_meshes = build_request_meshes(range(10000, 10000 + warm), threads)
+    meshes = build_request_meshes(range(n_req), threads)
+    log(f"serve: {n_req} request meshes built ({time.perf_counter() - t0:.1f} s)")
+    S = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=slots, host_threads=threads)
+    # closed loop: all warm-up requests at once
+    c0 = S.stats()["clock"]
+    ids = [S.submit(m, opts) for m in warm_meshes]
+    for i in ids:
+        S.wait(i, 600)
+    c1 = S.stats()["clock"]
+    rate = load * warm / (c1 - c0)
+    for i in ids:
+        S.release(i)
+    log(f"serve: closed-loop {warm / (c1 - c0):.1f} req/s -> arrival rate {rate:.1f} req/s")
+    arr = gi.arrivals(n_req, rate)
+    start = S.stats()["clock"]
+    ids = []
+    w0 = time.perf_counter()
+    for k, m in enumerate(meshes):
+        delay = arr[k] - (time.perf_counter() - w0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(S.submit(m, opts))
+    lat, its, dofs, status = [], [], 0.0, []
+    end = start
+    for i in ids:
+        S.wait(i, 1200)
+        r = S.result(i)
+        t = r["timing"]
+        lat.append(t["finished"] - t["arrival"])
+        its.append(r["iterations"])
+        dofs += len(r["u"])
+        status.append(r["status"])
+        end = max(end, t["finished"])
+        S.release(i)
+    st = S.stats()
+    S.close()
+    lat = np.array(lat)
+    span = end - start
+    return {"requests": n_req, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "arrival_rate_rps": rate, "throughput_rps": n_req / span,
+            "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
+            "cg_iterations_min": int(min(its)), "failed": int(sum(1 for s in status if s != 0)),
+            "slots": slots, "host_threads": threads, "arena_peak_gb": st["arena_peak"] / 2 ** 30,
+            "latency_includes": "queueing + host set-up + device set-up + solve + copy-back"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +132,7 @@ def main():
     ap.add_argument("--g", type=int, default=5, help="global refinements of the Fichera recipe")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--serve", type=int, default=64, help="requests in the serving stream (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -169,6 +244,11 @@ def main():
                           "speedup_vs_fp64_mg": r64["ms"] / r32["ms"],
                           "roofline_apply": {"achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                              "frac": a32 / HBM_PEAK_GBS, "t_launch_us": r32["t_apply"] * 1e6}}
+    if args.serve > 0:
+        log(f"serving stream: {args.serve} requests ...")
+        out["serve"] = serve_leg(args.serve)
+        log(f"serve: p50 {out['serve']['p50_s'] * 1e3:.1f} ms p99 {out['serve']['p99_s'] * 1e3:.1f} ms "
+            f"{out['serve']['throughput_rps']:.1f} req/s")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
