@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--g", type=int, default=5, help="global refinements of the Fichera recipe")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--serve", type=int, default=64, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -149,11 +149,19 @@ def main():
     mesh = gmg.build_mesh(w.recipe)
     log(f"mesh: {mesh.n_leaves} leaves ({time.perf_counter() - t0:.1f} s)")
 
+    # calibration copy of a known size for the HBM traffic counters
+    # (FETCH_SIZE / WRITE_SIZE of this copy divided by 256 MiB is the scale)
+    cal_a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    cal_b = torch.empty_like(cal_a)
+    cal_b.copy_(cal_a)
+    torch.cuda.synchronize()
+    del cal_a, cal_b
     results = {}
+    t0 = time.perf_counter()
+    base = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=64))
+    t_maps = time.perf_counter() - t0
     for prec in ([64] if args.no_fp32 else [64, 32]):
-        t0 = time.perf_counter()
-        P = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=prec))
-        t_maps = time.perf_counter() - t0
+        P = base.clone(gmg.options(degree=w.degree, mg_precision=prec))
         t0 = time.perf_counter()
         P.bind("cuda")
         torch.cuda.synchronize()
@@ -179,7 +187,9 @@ def main():
         wall = time.perf_counter() - t0
         log(f"  timed: {args.steps} solves, {wall / args.steps * 1e3:.2f} ms/solve, its {its}, res {h[-1]:.2e}")
         # dominant kernel: the operator application on the largest level
+        # (the variant used by the solve, and the other variant for reference)
         lmax = int(np.argmax(list(info.level_dofs)[:info.n_levels]))
+        alt = base.clone(gmg.options(degree=w.degree, mg_precision=prec, op_variant=1)).bind("cuda")
         nl = int(info.level_dofs[lmax])
         tdt = torch.float64 if prec == 64 else torch.float32
         x = torch.randn(nl, dtype=tdt, device="cuda")
@@ -194,14 +204,24 @@ def main():
             P.apply_level(lmax, 0, x, y)
         e1.record(stream)
         torch.cuda.synchronize()
-        # each call is a fill of y then the operator kernel; time the pair
+        # each call is both passes of the operator (slots, then per-node sums)
         t_apply = e0.elapsed_time(e1) / reps * 1e-3
+        for _ in range(3):
+            alt.apply_level(lmax, 0, x, y)
+        e0.record(stream)
+        for _ in range(reps):
+            alt.apply_level(lmax, 0, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_apply_family = e0.elapsed_time(e1) / reps * 1e-3
+        alt.close()
+        log(f"  level {lmax} operator: family {t_apply * 1e6:.1f} us, per-cell {t_apply_family * 1e6:.1f} us")
         esz = 8 if prec == 64 else 4
         alg_bytes = 2 * esz * nl
         results[prec] = dict(N=N, levels=info.n_levels, its=its, res=float(h[-1]), status=st,
                              ms=wall / args.steps * 1e3, dev_ms=dev_t / args.steps * 1e3,
                              vcycle_ms=vc_t / max(n_vc, 1) * 1e3, lmax=lmax, level_dofs=nl,
-                             level_cells=int(info.level_cells[lmax]), t_apply=t_apply,
+                             level_cells=int(info.level_cells[lmax]), t_apply=t_apply, t_apply_family=t_apply_family,
                              alg_bytes=alg_bytes, maps_s=t_maps, bind_s=t_bind, u=u.cpu().numpy())
         P.close()
         del f, x, y
@@ -233,7 +253,8 @@ def main():
                        "frac": a / HBM_PEAK_GBS, "traffic": None,
                        "kernel": f"level operator FP64, level {r64['lmax']} ({r64['level_dofs']} DoFs, "
                                  f"{r64['level_cells']} cells), 16 B/DoF algorithmic",
-                       "t_launch_us": r64["t_apply"] * 1e6}
+                       "t_launch_us": r64["t_apply"] * 1e6,
+                       "t_launch_per_cell_variant_us": r64["t_apply_family"] * 1e6}
     if 32 in results:
         r32 = results[32]
         a32 = r32["alg_bytes"] / r32["t_apply"] / 1e9

@@ -77,6 +77,8 @@ typedef struct {
   double rtol;           /* stop when ||b - A u||_2 <= rtol ||b||_2 */
   int32_t max_iter;      /* CG iteration cap */
   int32_t use_graph;     /* 1: replay the V-cycle as a captured HIP graph */
+  int32_t op_variant;    /* level operator pass 1: 0 auto, 1 one lane per cell, 2 sibling-family
+                            patches in LDS (levels >= 1) */
 } gmg_options;
 
 void gmg_options_default(gmg_options* opts);
@@ -108,6 +110,11 @@ int gmg_mesh_destroy(gmg_mesh m);
  * The mesh is only read; it may be destroyed afterwards. */
 int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* cell_coeff,
                        gmg_problem* out);
+
+/* New problem with the host set-up of `src` (same mesh, degree and
+ * coefficient) and other options (precision, smoother, tolerances); the
+ * degree must match.  Not bound. */
+int gmg_problem_clone(gmg_problem src, const gmg_options* opts, gmg_problem* out);
 
 typedef struct {
   int32_t dim, degree, n_levels, mg_precision;

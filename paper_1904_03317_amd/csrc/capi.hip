@@ -65,6 +65,7 @@ void gmg_options_default(gmg_options* o) {
   o->rtol = 1e-10;
   o->max_iter = 100;
   o->use_graph = 1;
+  o->op_variant = 0;
 }
 
 const char* gmg_last_error(void) { return gmg::g_last_error.c_str(); }
@@ -133,6 +134,7 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
     REQUIRE(opts->eig_iters >= 1 && opts->eig_iters <= 100, "eig_iters must be 1..100");
     REQUIRE(opts->rtol > 0 && opts->max_iter >= 1, "rtol > 0 and max_iter >= 1 required");
     REQUIRE(m->f->max_level() < 24, "too many levels");
+    REQUIRE(opts->op_variant >= 0 && opts->op_variant <= 2, "op_variant must be 0, 1 or 2");
     auto p = std::make_unique<gmg_problem_s>();
     gmg::Problem& P = p->P;
     P.opt = *opts;
@@ -150,6 +152,28 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
       P.m64.E[i] = fe.E[i];
       P.m32.E[i] = (float)fe.E[i];
     }
+    P.ws_need = gmg::plan_workspace(P, nullptr);
+    *out = p.release();
+    return 0;
+  });
+}
+
+int gmg_problem_clone(gmg_problem src, const gmg_options* opts, gmg_problem* out) {
+  return guard([&] {
+    REQUIRE(src && opts && out, "null argument");
+    REQUIRE(opts->degree == src->P.maps.k, "clone must keep the degree");
+    REQUIRE(opts->mg_precision == 32 || opts->mg_precision == 64, "mg_precision must be 32 or 64");
+    REQUIRE(opts->cheb_degree >= 1 && opts->cheb_degree <= 64, "cheb_degree must be 1..64");
+    REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "0 < cheb_lo < cheb_hi required");
+    REQUIRE(opts->eig_iters >= 1 && opts->eig_iters <= 100, "eig_iters must be 1..100");
+    REQUIRE(opts->rtol > 0 && opts->max_iter >= 1, "rtol > 0 and max_iter >= 1 required");
+    auto p = std::make_unique<gmg_problem_s>();
+    gmg::Problem& P = p->P;
+    P.opt = *opts;
+    P.kt = src->P.kt;
+    P.maps = src->P.maps;
+    P.m32 = src->P.m32;
+    P.m64 = src->P.m64;
     P.ws_need = gmg::plan_workspace(P, nullptr);
     *out = p.release();
     return 0;

@@ -20,7 +20,8 @@ struct LevelView {
   const int32_t* parent = nullptr;
   // two-pass operator: slot of (cell, local node) in the node-major buffer,
   // and per-node slot ranges
-  const int32_t* slot = nullptr;    // SoA [npc][n_cells]
+  const int32_t* slot = nullptr;    // SoA [npc][n_cells] (level 0: per-cell slots)
+  const int32_t* fslot = nullptr;   // SoA [mf][n_fam] (levels >= 1: per-family patch slots)
   const int32_t* soff = nullptr;    // [n_dofs + 1]
   // restriction into the next coarser level: slot of (family, parent node)
   const int32_t* rslot = nullptr;   // SoA [npc][n_fam]

@@ -1,6 +1,10 @@
 #include "maps.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -195,12 +199,132 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
       fail(-1, "cell coefficients must be positive and finite");
   }
 
+  // ---------------------------------------------------------- levels (cores)
+  // Level meshes depend only on the forest: number them on worker threads
+  // while this thread numbers the leaf mesh.
+  const int L = f.max_level();
+  M.levels.resize(L + 1);
+  std::vector<KeyMap> lmaps(L + 1, KeyMap(16));
+  std::exception_ptr level_error;
+  std::mutex level_mu;
+  auto parallel_levels = [&](auto&& fn) {
+    std::atomic<int> next_level{0};
+    const int nthreads = std::max(1, std::min<int>(L + 1, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t)
+      th.emplace_back([&] {
+        for (int l = next_level++; l <= L; l = next_level++) {
+          try {
+            fn(l);
+          } catch (...) {
+            std::lock_guard<std::mutex> lk(level_mu);
+            if (!level_error) level_error = std::current_exception();
+          }
+        }
+      });
+    for (auto& x : th) x.join();
+    if (level_error) std::rethrow_exception(level_error);
+  };
+  std::vector<std::thread> level_threads;
+  level_threads.emplace_back([&] {
+    try {
+      parallel_levels([&](int l) {
+        KeyMap& lmap = lmaps[l];
+    LevelData& D = M.levels[l];
+    D.level = l;
+    {
+      int64_t s = side_of(l);
+      uint64_t last = ~0ull;
+      for (int64_t li = 0; li < nl; ++li) {
+        const Cell& c = leaves[li].c;
+        if (c.level < l) continue;
+        Cell a = c;
+        a.level = (int8_t)l;
+        for (int i = 0; i < dim; ++i) a.a[i] = (int32_t)floor_to(c.a[i], s);
+        uint64_t kk = f.key(a);
+        if (kk == last) continue;
+        last = kk;
+        D.cells.push_back(a);
+        D.keys.push_back(kk);
+        D.leaf_index.push_back(c.level == l ? (int32_t)li : -1);
+      }
+    }
+    D.n_cells = (int64_t)D.cells.size();
+    lmap.reset(size_t(D.n_cells) * (dim == 3 ? k * k * k : k * k) + 64);
+    D.cellmap.resize(size_t(D.n_cells) * npc);
+    int32_t next = 0;
+    std::vector<u128> lkeys;
+    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+      uint32_t kc[3][5];
+      C.cell_codes(D.cells[ci], kc);
+      for (int li = 0; li < npc; ++li) {
+        u128 key = C.node_key(kc, li);
+        int32_t id = lmap.get_or_insert(key, next);
+        if (id == next) {
+          ++next;
+          lkeys.push_back(key);
+        }
+        D.cellmap[size_t(ci) * npc + li] = id;
+      }
+    }
+    D.n_dofs = next;
+    D.flags.assign(D.n_dofs, kFlagS);
+    if (l >= 1) {
+      std::array<int, 3> offs[26];
+      uint64_t last_parent = ~0ull;
+      int nn = 0;
+      for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+        const Cell& K = D.cells[ci];
+        Cell P = C.parent_of(K);
+        uint64_t pk = f.key(P);
+        if (pk != last_parent) {
+          nn = C.leaf_neighbours(P, offs);
+          last_parent = pk;
+        }
+        for (int q = 0; q < nn; ++q) {
+          int lists[3][5], cnt[3];
+          if (!C.touch(K, P, offs[q], lists, cnt)) continue;
+          for (int jz = 0; jz < cnt[2]; ++jz)
+            for (int jy = 0; jy < cnt[1]; ++jy)
+              for (int jx = 0; jx < cnt[0]; ++jx) {
+                int li = lists[0][jx] + n * (lists[1][jy] + n * lists[2][jz]);
+                D.flags[D.cellmap[size_t(ci) * npc + li]] = kFlagI;
+              }
+        }
+      }
+    }
+    for (int64_t i = 0; i < D.n_dofs; ++i)
+      if (C.on_boundary(lkeys[i])) D.flags[i] = kFlagD;
+    for (int64_t i = 0; i < D.n_dofs; ++i)
+      if (D.flags[i] == kFlagI) D.ilist.push_back((int32_t)i);
+    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
+      for (int li = 0; li < npc; ++li)
+        if (D.flags[D.cellmap[size_t(ci) * npc + li]] == kFlagI) {
+          D.edge_cells.push_back((int32_t)ci);
+          break;
+        }
+    }
+      });
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(level_mu);
+      if (!level_error) level_error = std::current_exception();
+    }
+  });
+  struct JoinGuard {
+    std::vector<std::thread>& t;
+    ~JoinGuard() {
+      for (auto& x : t)
+        if (x.joinable()) x.join();
+    }
+  } join_guard{level_threads};
+
   // ---------------------------------------------------------- hanging nodes
   // a node of leaf K (level l) is hanging iff it lies in the closure of a
   // level-(l-1) leaf N (a neighbour of K's parent) and is not a node of N;
   // masters: N's nodes on the smallest entity holding it with nonzero
   // weight, z-major order; weights: N's tensor Lagrange basis at the node.
   KeyMap hang(1024);
+  std::vector<uint8_t> maybe_hang(nl, 0);   // leaf touches a coarser leaf
   std::vector<HangRec> hrec;
   std::vector<u128> hpool_m;
   std::vector<double> hpool_w;
@@ -224,6 +348,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
         const auto& off = offs[q];
         int lists[3][5], cnt[3];
         if (!C.touch(K, P, off, lists, cnt)) continue;
+        maybe_hang[ci] = 1;
         Cell N = P;
         int64_t S = side_of(P.level), s = side_of(K.level);
         for (int i = 0; i < dim; ++i) N.a[i] = (int32_t)(P.a[i] + off[i] * S);
@@ -304,7 +429,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
       C.cell_codes(K, kc);
       for (int li = 0; li < npc; ++li) {
         u128 key = C.node_key(kc, li);
-        int32_t h = hrec.empty() ? -1 : hang.get(key);
+        int32_t h = (hrec.empty() || !maybe_hang[ci]) ? -1 : hang.get(key);
         if (h >= 0) {
           if (hrec[h].id < 0) {
             hrec[h].id = (int32_t)hang_order.size();
@@ -347,9 +472,10 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
   dofs = KeyMap(16);
   T.mark("dirichlet+constraints");
 
-  // ---------------------------------------------------------- levels
-  const int L = f.max_level();
-  M.levels.resize(L + 1);
+  // ---------------------------------------------------------- levels (rest)
+  for (auto& t : level_threads) t.join();
+  if (level_error) std::rethrow_exception(level_error);
+  T.mark("level numbering");
   // bucket leaf DoFs by the level that owns them in the hierarchy
   std::vector<int64_t> bstart(L + 2, 0);
   for (int64_t i = 0; i < M.n_dofs; ++i) ++bstart[dof_minlevel[i] + 1];
@@ -361,82 +487,9 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
   }
   M.copy_level.resize(M.n_dofs);
   M.copy_index.resize(M.n_dofs);
-  KeyMap lmap(16);
-  for (int l = 0; l <= L; ++l) {
+  parallel_levels([&](int l) {
     LevelData& D = M.levels[l];
-    D.level = l;
-    {
-      int64_t s = side_of(l);
-      uint64_t last = ~0ull;
-      for (int64_t li = 0; li < nl; ++li) {
-        const Cell& c = leaves[li].c;
-        if (c.level < l) continue;
-        Cell a = c;
-        a.level = (int8_t)l;
-        for (int i = 0; i < dim; ++i) a.a[i] = (int32_t)floor_to(c.a[i], s);
-        uint64_t kk = f.key(a);
-        if (kk == last) continue;
-        last = kk;
-        D.cells.push_back(a);
-        D.keys.push_back(kk);
-        D.leaf_index.push_back(c.level == l ? (int32_t)li : -1);
-      }
-    }
-    D.n_cells = (int64_t)D.cells.size();
-    lmap.reset(size_t(D.n_cells) * (dim == 3 ? k * k * k : k * k) + 64);
-    D.cellmap.resize(size_t(D.n_cells) * npc);
-    int32_t next = 0;
-    std::vector<u128> lkeys;
-    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
-      uint32_t kc[3][5];
-      C.cell_codes(D.cells[ci], kc);
-      for (int li = 0; li < npc; ++li) {
-        u128 key = C.node_key(kc, li);
-        int32_t id = lmap.get_or_insert(key, next);
-        if (id == next) {
-          ++next;
-          lkeys.push_back(key);
-        }
-        D.cellmap[size_t(ci) * npc + li] = id;
-      }
-    }
-    D.n_dofs = next;
-    D.flags.assign(D.n_dofs, kFlagS);
-    if (l >= 1) {
-      std::array<int, 3> offs[26];
-      uint64_t last_parent = ~0ull;
-      int nn = 0;
-      for (int64_t ci = 0; ci < D.n_cells; ++ci) {
-        const Cell& K = D.cells[ci];
-        Cell P = C.parent_of(K);
-        uint64_t pk = f.key(P);
-        if (pk != last_parent) {
-          nn = C.leaf_neighbours(P, offs);
-          last_parent = pk;
-        }
-        for (int q = 0; q < nn; ++q) {
-          int lists[3][5], cnt[3];
-          if (!C.touch(K, P, offs[q], lists, cnt)) continue;
-          for (int jz = 0; jz < cnt[2]; ++jz)
-            for (int jy = 0; jy < cnt[1]; ++jy)
-              for (int jx = 0; jx < cnt[0]; ++jx) {
-                int li = lists[0][jx] + n * (lists[1][jy] + n * lists[2][jz]);
-                D.flags[D.cellmap[size_t(ci) * npc + li]] = kFlagI;
-              }
-        }
-      }
-    }
-    for (int64_t i = 0; i < D.n_dofs; ++i)
-      if (C.on_boundary(lkeys[i])) D.flags[i] = kFlagD;
-    for (int64_t i = 0; i < D.n_dofs; ++i)
-      if (D.flags[i] == kFlagI) D.ilist.push_back((int32_t)i);
-    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
-      for (int li = 0; li < npc; ++li)
-        if (D.flags[D.cellmap[size_t(ci) * npc + li]] == kFlagI) {
-          D.edge_cells.push_back((int32_t)ci);
-          break;
-        }
-    }
+    KeyMap& lmap = lmaps[l];
     // copy map for the leaf DoFs owned by this level
     for (int64_t b = bstart[l]; b < bstart[l + 1]; ++b) {
       int64_t i = bucket[b];
@@ -445,7 +498,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
       M.copy_level[i] = (int8_t)l;
       M.copy_index[i] = id;
     }
-    T.mark("level numbering");
+    lmap = KeyMap(16);
     // families and transfer maps
     if (l >= 1) {
       const LevelData& Pl = M.levels[l - 1];
@@ -492,7 +545,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
             fail(-8, "complete-layer rule violated");
       }
     }
-  }
+    });
   T.mark("levels done");
   // cell coefficients: leaves from the input, other cells the mean of their
   // children (Sec. 4.3 coefficient, applied on every level)

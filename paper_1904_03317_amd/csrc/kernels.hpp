@@ -257,6 +257,97 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
 }
 
+// Families per workgroup for the family-patch operator: one lane per cell,
+// the input and output patches of all families in LDS (<= 64 KB).
+template <int DIM, int K, typename T>
+struct FamilyShape {
+  static constexpr int M2 = 2 * K + 1;
+  static constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
+  static constexpr int CPF = 1 << DIM;
+  // padded row length: odd in 4-byte words so that the families of a wave
+  // fall on different LDS banks
+  static constexpr int MFP = sizeof(T) == 4 ? (MF % 2 ? MF + 2 : MF + 1) : MF + 1;
+  static constexpr int fb_lds = 65536 / (2 * MFP * (int)sizeof(T));
+  static constexpr int fb_cap = 256 / CPF;
+  static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
+  static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
+  static constexpr int THREADS = FB * CPF;
+};
+
+// Level operator, pass 1, by sibling families: the workgroup gathers the
+// (2k+1)^d node patch of each of its families once into LDS (index reads
+// coalesced over families), every lane computes one cell from LDS,
+// contributions of the 2^d siblings are combined with LDS atomics, and each
+// family writes its patch once into its node-major slots (pass 2 sums the
+// slots of a node over the families that contain it).
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamilyShape<DIM, K, T>::THREADS)) family_to_slots(
+    int64_t n_fam, const int32_t* __restrict__ famap, const int32_t* __restrict__ fslot,
+    const double* __restrict__ scale, double scale0, const T* __restrict__ x, T* __restrict__ E, Mats<T> m) {
+  using S = FamilyShape<DIM, K, T>;
+  constexpr int N = K + 1, M2 = S::M2, MF = S::MF, MFP = S::MFP, FB = S::FB, CPF = S::CPF;
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  __shared__ T sin[FB * MFP];
+  __shared__ T sout[FB * MFP];
+  const int64_t f0 = xcd_block() * FB;
+  const int tid = threadIdx.x;
+  // all index loads first, then all gathers, so the loads are in flight together
+  constexpr int ITER = (MF * FB + S::THREADS - 1) / S::THREADS;
+  int32_t gid[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int e = tid + it * S::THREADS;
+    const int q = e / FB, fl = e % FB;
+    gid[it] = (e < MF * FB && f0 + fl < n_fam) ? famap[(int64_t)q * n_fam + f0 + fl] : -1;
+  }
+  T val[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) val[it] = gid[it] >= 0 ? x[gid[it]] : T(0);
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int e = tid + it * S::THREADS;
+    if (e < MF * FB) {
+      const int q = e / FB, fl = e % FB;
+      sin[fl * MFP + q] = val[it];
+      sout[fl * MFP + q] = T(0);
+    }
+  }
+  __syncthreads();
+  const int fl = tid / CPF, cid = tid % CPF;
+  const int64_t f = f0 + fl;
+  if (f < n_fam) {
+    const int bx = (cid & 1) * K, by = ((cid >> 1) & 1) * K, bz = DIM == 3 ? ((cid >> 2) & 1) * K : 0;
+    T u[NP], v[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+      u[j] = sin[fl * MFP + ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx)];
+    }
+    if (DIM == 3)
+      laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(v));
+    else
+      laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
+    const T sc = T(scale ? scale[f * CPF + cid] : scale0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+      atomicAdd(&sout[fl * MFP + ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx)], sc * v[j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int e = tid + it * S::THREADS;
+    const int q = e / FB, fl2 = e % FB;
+    gid[it] = (e < MF * FB && f0 + fl2 < n_fam) ? fslot[(int64_t)q * n_fam + f0 + fl2] : -1;
+  }
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const int e = tid + it * S::THREADS;
+    if (gid[it] >= 0) E[gid[it]] = sout[(e % FB) * MFP + e / FB];
+  }
+}
+
 // diagonal of the cell Laplacian, accumulated per node (FP64)
 template <int DIM, int N>
 __global__ void __launch_bounds__(kBlock) cell_diag(int64_t n_cells, const int32_t* __restrict__ cmap,
@@ -495,11 +586,17 @@ __global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, cons
 }
 
 // ------------------------------------------------------------------ pass 2
+// sum of the slots of node i, four independent loads at a time (fixed order)
 template <typename T>
 __device__ __forceinline__ T seg_sum(const int32_t* __restrict__ off, const T* __restrict__ E, int64_t i) {
   T y = 0;
+  int32_t p = off[i];
   const int32_t e = off[i + 1];
-  for (int32_t p = off[i]; p < e; ++p) y += E[p];
+  for (; p + 4 <= e; p += 4) {
+    const T a0 = E[p], a1 = E[p + 1], a2 = E[p + 2], a3 = E[p + 3];
+    y += (a0 + a1) + (a2 + a3);
+  }
+  for (; p < e; ++p) y += E[p];
   return y;
 }
 

@@ -23,7 +23,8 @@ _ARR_DTYPE = {1: np.int32, 2: np.uint8, 3: np.int64, 4: np.int32, 5: np.float64,
 class gmg_options(C.Structure):
     _fields_ = [("degree", C.c_int32), ("mg_precision", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("eig_iters", C.c_int32),
-                ("rtol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32)]
+                ("rtol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32),
+                ("op_variant", C.c_int32)]
 
 
 class gmg_info(C.Structure):
@@ -80,6 +81,7 @@ def lib():
         "gmg_mesh_destroy": (C.c_int, [vp]),
         "gmg_problem_create": (C.c_int, [vp, C.POINTER(gmg_options), vp, C.POINTER(vp)]),
         "gmg_problem_info": (C.c_int, [vp, C.POINTER(gmg_info)]),
+        "gmg_problem_clone": (C.c_int, [vp, C.POINTER(gmg_options), C.POINTER(vp)]),
         "gmg_problem_array": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(vp), C.POINTER(i64)]),
         "gmg_problem_workspace_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "gmg_problem_bind": (C.c_int, [vp, vp, C.c_size_t, vp]),
@@ -113,7 +115,7 @@ def exported_symbols():
     """Names the library must export (every function of include/gmg.h)."""
     return ["gmg_options_default", "gmg_last_error", "gmg_mesh_create", "gmg_mesh_refine",
             "gmg_mesh_num_leaves", "gmg_mesh_leaves", "gmg_mesh_dim", "gmg_mesh_destroy",
-            "gmg_problem_create", "gmg_problem_info", "gmg_problem_array",
+            "gmg_problem_create", "gmg_problem_clone", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
             "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle",
             "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_poll",
@@ -195,13 +197,22 @@ class Mesh:
 class Problem:
     """Discretisation + multigrid hierarchy of one mesh (gmg_problem_*)."""
 
-    def __init__(self, mesh: Mesh, opts=None, coeff=None):
+    def __init__(self, mesh: Mesh, opts=None, coeff=None, _handle=None):
         self.opts = opts if opts is not None else options()
+        self.ws = None
+        if _handle is not None:
+            self.h = _handle
+            return
         c = None if coeff is None else np.ascontiguousarray(np.asarray(coeff, np.float64))
         h = C.c_void_p()
         _check(lib().gmg_problem_create(mesh.h, C.byref(self.opts), _ptr(c), C.byref(h)))
         self.h = h
-        self.ws = None
+
+    def clone(self, opts):
+        """Same host set-up, other options (gmg_problem_clone)."""
+        h = C.c_void_p()
+        _check(lib().gmg_problem_clone(self.h, C.byref(opts), C.byref(h)))
+        return Problem(None, opts, _handle=h)
 
     def info(self):
         i = gmg_info()

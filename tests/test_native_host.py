@@ -114,3 +114,14 @@ def test_workspace_accounts_for_precision():
     _, P32, _ = library_problem(rec, k, mg_precision=32)
     _, P64, _ = library_problem(rec, k, mg_precision=64)
     assert P64.workspace_bytes() > P32.workspace_bytes() > 0
+
+
+def test_clone_keeps_maps():
+    rec, k = CASES["fichera-q2"]
+    _, P64, _ = library_problem(rec, k, mg_precision=64)
+    P32 = P64.clone(gmg.options(degree=k, mg_precision=32, cheb_degree=5))
+    for name in ("LEAF_CELLMAP", "CON_MASTERS", "COPY_INDEX"):
+        assert np.array_equal(P32.array(name), P64.array(name))
+    assert P32.info().mg_precision == 32 and P32.workspace_bytes() < P64.workspace_bytes()
+    with pytest.raises(gmg.GMGError):
+        P64.clone(gmg.options(degree=k + 1))
