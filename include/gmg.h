@@ -140,7 +140,12 @@ int gmg_problem_info(gmg_problem p, gmg_info* out);
  *   GMG_ARR_COPY_INDEX    int32  n_dofs            its index on that level
  *   GMG_ARR_LEVEL_CELLMAP int32  level_cells*(k+1)^d (level given)
  *   GMG_ARR_LEVEL_FLAGS   uint8  level_dofs        0 S, 1 I, 2 D
- *   GMG_ARR_LEVEL_PARENT  int32  level_cells/2^d   parent index in level-1 cells */
+ *   GMG_ARR_LEVEL_PARENT  int32  level_cells/2^d   parent index in level-1 cells
+ *   GMG_ARR_LEAF_CELLMAP_PARENT int32 n_leaves*(k+1)^d  in-cell constraint form: on a face or
+ *                         edge shared with a coarser leaf, the DoF of the parent's node at the
+ *                         same local position (interpolated in the cell by the 1D embedding)
+ *   GMG_ARR_LEAF_MASK     uint16 n_leaves         bits 0-2 child position, 3-5 hanging face
+ *                         normal to x/y/z, 6-8 hanging edge along x/y/z */
 enum {
   GMG_ARR_LEAF_CELLMAP = 1,
   GMG_ARR_LEAF_DIRICHLET = 2,
@@ -151,7 +156,9 @@ enum {
   GMG_ARR_COPY_INDEX = 7,
   GMG_ARR_LEVEL_CELLMAP = 8,
   GMG_ARR_LEVEL_FLAGS = 9,
-  GMG_ARR_LEVEL_PARENT = 10
+  GMG_ARR_LEVEL_PARENT = 10,
+  GMG_ARR_LEAF_CELLMAP_PARENT = 11,
+  GMG_ARR_LEAF_MASK = 12
 };
 int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int64_t* count);
 

@@ -224,6 +224,11 @@ int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int
       case GMG_ARR_LEVEL_CELLMAP: *ptr = lev().cellmap.data(); *count = (int64_t)lev().cellmap.size(); break;
       case GMG_ARR_LEVEL_FLAGS: *ptr = lev().flags.data(); *count = (int64_t)lev().flags.size(); break;
       case GMG_ARR_LEVEL_PARENT: *ptr = lev().parent.data(); *count = (int64_t)lev().parent.size(); break;
+      case GMG_ARR_LEAF_CELLMAP_PARENT:
+        *ptr = M.leaf_cellmap_parent.data();
+        *count = (int64_t)M.leaf_cellmap_parent.size();
+        break;
+      case GMG_ARR_LEAF_MASK: *ptr = M.leaf_mask.data(); *count = (int64_t)M.leaf_mask.size(); break;
       default: gmg::fail(GMG_E_INVAL, "unknown array");
     }
     return 0;

@@ -31,16 +31,13 @@ struct LevelView {
 
 struct LeafView {
   int64_t n_cells = 0, n_dofs = 0;
-  const int32_t* cmap = nullptr;    // SoA [npc][n_cells], hanging h as n_dofs + h
+  const int32_t* cmap = nullptr;    // SoA [npc][n_cells], parent-arranged DoFs on refinement edges
+  const uint16_t* mask = nullptr;   // [n_cells] in-cell constraint mask
   const double* scale = nullptr;    // a_K h^{d-2}
   const double* mscale = nullptr;   // h^d
   const int32_t* slot = nullptr;    // SoA [npc][n_cells] slot in the node-major buffer
-  const int32_t* soff = nullptr;    // [n_dofs + n_hanging + 1]
-  const int64_t* toff = nullptr;    // transposed constraints: per DoF, its hanging nodes
-  const int32_t* th = nullptr;
-  const double* tw = nullptr;
+  const int32_t* soff = nullptr;    // [n_dofs + 1]
   const uint8_t* dir = nullptr;     // [n_dofs] Dirichlet flag
-  int64_t n_hang = 0;
 };
 
 template <typename T>
@@ -65,8 +62,7 @@ struct KernelTable {
   LevelOps<float> f32;
   LevelOps<double> f64;
   // pass 1 of the leaf operator (or mass matrix): cell results into slots
-  void (*leaf_e)(const LeafView&, const double* x, const double* xh, double* E, bool mass,
-                 const MatsH<double>&, hipStream_t);
+  void (*leaf_e)(const LeafView&, const double* x, double* E, bool mass, const MatsH<double>&, hipStream_t);
   void (*diag)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
 };
 

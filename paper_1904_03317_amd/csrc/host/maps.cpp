@@ -469,6 +469,74 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
     if (std::fabs(sw - 1.0) > 1e-12) fail(-8, "constraint weights do not sum to one");
     M.con_off.push_back((int64_t)M.con_mas.size());
   }
+  // in-cell constraints: masks and parent-arranged DoF ids
+  M.leaf_mask.assign(nl, 0);
+  M.leaf_cellmap_parent = M.leaf_cellmap;
+  {
+    std::array<int, 3> offs[26];
+    for (int64_t ci = 0; ci < nl; ++ci) {
+      if (!maybe_hang[ci]) continue;
+      const Cell& K = leaves[ci].c;
+      const Cell P = C.parent_of(K);
+      const int nn = C.leaf_neighbours(P, offs);
+      int bit[3] = {0, 0, 0};
+      for (int i = 0; i < dim; ++i) bit[i] = (int)((K.a[i] - P.a[i]) / side_of(K.level));
+      bool face[3] = {false, false, false}, edge[3] = {false, false, false};
+      for (int q = 0; q < nn; ++q) {
+        const auto& o = offs[q];
+        int nz = 0, touches = 1;
+        for (int i = 0; i < dim; ++i)
+          if (o[i]) {
+            ++nz;
+            if ((o[i] > 0 ? 1 : 0) != bit[i]) touches = 0;
+          }
+        if (!touches) continue;
+        if (nz == 1) {
+          for (int i = 0; i < dim; ++i)
+            if (o[i]) face[i] = true;
+        } else if (nz == 2 && dim == 3) {
+          for (int i = 0; i < 3; ++i)
+            if (!o[i]) edge[i] = true;
+        }
+      }
+      // an edge of two hanging faces is part of them
+      for (int a = 0; a < dim; ++a)
+        if (edge[a])
+          for (int b = 0; b < dim; ++b)
+            if (b != a && face[b]) edge[a] = false;
+      uint16_t mk = 0;
+      for (int i = 0; i < dim; ++i) {
+        mk |= (uint16_t)(bit[i] << i);
+        if (face[i]) mk |= (uint16_t)(1u << (3 + i));
+        if (edge[i]) mk |= (uint16_t)(1u << (6 + i));
+      }
+      if (!(mk >> 3)) continue;
+      M.leaf_mask[ci] = mk;
+      uint32_t pc[3][5];
+      C.cell_codes(P, pc);
+      for (int li = 0; li < npc; ++li) {
+        int j[3] = {li % n, (li / n) % n, dim == 3 ? li / (n * n) : 0};
+        bool hang_pos = false;
+        for (int a = 0; a < dim; ++a) {
+          if (face[a] && j[a] == bit[a] * k) hang_pos = true;
+          if (edge[a]) {
+            bool on = true;
+            for (int b = 0; b < dim; ++b)
+              if (b != a && j[b] != bit[b] * k) on = false;
+            if (on) hang_pos = true;
+          }
+        }
+        if (!hang_pos) continue;
+        // parent node at the same local position
+        uint32_t c3[3] = {pc[0][j[0]], pc[1][j[1]], dim == 3 ? pc[2][j[2]] : 0};
+        int32_t id = dofs.get(make_key(c3, dim));
+        if (id < 0) fail(-8, "parent node on a refinement edge is not a DoF");
+        M.leaf_cellmap_parent[size_t(ci) * npc + li] = id;
+      }
+    }
+    for (auto v : M.leaf_cellmap_parent)
+      if (v < 0) fail(-8, "hanging node outside an in-cell constraint");
+  }
   dofs = KeyMap(16);
   T.mark("dirichlet+constraints");
 

@@ -34,6 +34,15 @@ struct Maps {
   FE1D fe;
   int64_t n_leaves = 0, n_dofs = 0, n_hanging = 0;
   std::vector<int32_t> leaf_cellmap;  // [n_leaves * npc] DoF id or -(h+1)
+  // In-cell form of the hanging-node constraints: on a face or edge of a
+  // leaf shared with a coarser leaf, the cell holds the DoFs of its parent's
+  // nodes at the same local positions and interpolates them with the 1D
+  // embedding rows of its child position.
+  std::vector<int32_t> leaf_cellmap_parent;  // [n_leaves * npc] DoF ids only
+  // bits 0..2 child position (x, y, z) in the parent, 3..5 hanging face
+  // normal to x / y / z (on the child's side of the parent), 6..8 hanging
+  // edge along x / y / z (at the child's corner edge of the parent)
+  std::vector<uint16_t> leaf_mask;
   std::vector<int8_t> leaf_level;
   std::vector<double> leaf_coeff;
   std::vector<uint8_t> dirichlet;     // [n_dofs]

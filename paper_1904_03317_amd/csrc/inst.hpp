@@ -1,6 +1,8 @@
 // Instantiation of the kernel table for one (dim, k); included by inst_*.hip.
 #pragma once
 #include "dispatch.hpp"
+#include "gmg.h"
+#include "host/common.hpp"
 #include "kernels.hpp"
 
 namespace gmg {
@@ -25,8 +27,16 @@ struct Inst {
   template <typename T>
   static void apply_e(const LevelView& v, const T* x, T* E, const MatsH<T>& m, hipStream_t s) {
     if (!v.n_cells) return;
+    if (v.n_fam > 0 && v.fslot) {
+      using S = dev::FamilyShape<DIM, K, T>;
+      const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::family_to_slots<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, v.n_fam, v.famap,
+                         v.fslot, v.scale, v.scale0, x, E, to_dev(m));
+      return;
+    }
+    if (!v.slot) fail(GMG_E_STATE, "level operator has neither cell nor family slots");
     hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, T, false, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
-                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const T*)nullptr, (int64_t)0, E,
+                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const uint16_t*)nullptr, E,
                        to_dev(m));
   }
   template <typename T>
@@ -49,17 +59,15 @@ struct Inst {
     hipLaunchKernelGGL((dev::restrict_to_slots<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s,
                        f.n_fam, f.famap, f.own, r, f.rslot, E, to_dev(m));
   }
-  static void leaf_e(const LeafView& v, const double* x, const double* xh, double* E, bool mass,
-                     const MatsH<double>& m, hipStream_t s) {
+  static void leaf_e(const LeafView& v, const double* x, double* E, bool mass, const MatsH<double>& m,
+                     hipStream_t s) {
     if (!v.n_cells) return;
     if (mass)
       hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(v.n_cells)),
-                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.mscale, 1.0, x, xh, v.n_dofs, E,
-                         to_dev(m));
+                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.mscale, 1.0, x, v.mask, E, to_dev(m));
     else
       hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(v.n_cells)),
-                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, xh, v.n_dofs, E,
-                         to_dev(m));
+                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, v.mask, E, to_dev(m));
   }
   static void diag(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;

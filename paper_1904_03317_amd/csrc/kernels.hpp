@@ -167,6 +167,200 @@ __device__ __forceinline__ void mass_nd(const Mats<T>& m, T* u, T* out) {
   }
 }
 
+// ------------------------------------------------------------------ in-cell constraints
+// A leaf on the fine side of a refinement face or edge holds, at the
+// positions of that face/edge, the values of its parent's nodes at the same
+// local indices; the child's values there are the parent's polynomial at the
+// child's nodes: per tangential axis the 1D embedding rows of the child
+// position b (rows b*k .. b*k+k of E).  The transpose applies the columns,
+// each fine position counted once.
+template <int N, typename T>
+__device__ __forceinline__ T emb(const Mats<T>& m, int b, int j, int J) {
+  return b ? m.E[(N - 1 + j) * N + J] : m.E[j * N + J];
+}
+
+template <int DIM, int N>
+__device__ constexpr int lidx(int jx, int jy, int jz) {
+  return DIM == 3 ? jx + N * (jy + N * jz) : jx + N * jy;
+}
+
+// position with j_A = JA, j_P = p, j_Q = q (3D) or j_A = JA, j_P = p (2D)
+template <int DIM, int N, int A, int JA>
+__device__ constexpr int fpos(int p, int q) {
+  if (DIM == 2) return A == 0 ? lidx<2, N>(JA, p, 0) : lidx<2, N>(p, JA, 0);
+  return A == 0 ? lidx<3, N>(JA, p, q) : (A == 1 ? lidx<3, N>(p, JA, q) : lidx<3, N>(p, q, JA));
+}
+
+template <int DIM, int N, int A, int JA, typename T>
+__device__ __forceinline__ void face_fwd(const Mats<T>& m, const int* bb, const T* uc, T* u) {
+  constexpr int P = A == 0 ? 1 : 0;
+  constexpr int Q = A == 2 ? 1 : 2;
+  if (DIM == 2) {
+#pragma unroll
+    for (int jp = 0; jp < N; ++jp) {
+      T s = 0;
+#pragma unroll
+      for (int J = 0; J < N; ++J) s += emb<N>(m, bb[P], jp, J) * uc[fpos<DIM, N, A, JA>(J, 0)];
+      u[fpos<DIM, N, A, JA>(jp, 0)] = s;
+    }
+    return;
+  }
+  T t[N * N];
+#pragma unroll
+  for (int jp = 0; jp < N; ++jp)
+#pragma unroll
+    for (int Jq = 0; Jq < N; ++Jq) {
+      T s = 0;
+#pragma unroll
+      for (int Jp = 0; Jp < N; ++Jp) s += emb<N>(m, bb[P], jp, Jp) * uc[fpos<DIM, N, A, JA>(Jp, Jq)];
+      t[jp * N + Jq] = s;
+    }
+#pragma unroll
+  for (int jp = 0; jp < N; ++jp)
+#pragma unroll
+    for (int jq = 0; jq < N; ++jq) {
+      T s = 0;
+#pragma unroll
+      for (int Jq = 0; Jq < N; ++Jq) s += emb<N>(m, bb[Q], jq, Jq) * t[jp * N + Jq];
+      u[fpos<DIM, N, A, JA>(jp, jq)] = s;
+    }
+}
+
+template <int DIM, int N, int A, int JA, typename T>
+__device__ __forceinline__ void face_bwd(const Mats<T>& m, const int* bb, const T* t, T* v, uint32_t* used) {
+  constexpr int P = A == 0 ? 1 : 0;
+  constexpr int Q = A == 2 ? 1 : 2;
+  constexpr int NQ = DIM == 3 ? N : 1;
+  T w[N * NQ];
+#pragma unroll
+  for (int jp = 0; jp < N; ++jp)
+#pragma unroll
+    for (int jq = 0; jq < NQ; ++jq) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int p = fpos<DIM, N, A, JA>(jp, jq);
+      const bool u = (used[p >> 5] >> (p & 31)) & 1u;
+      w[jp * NQ + jq] = u ? T(0) : t[p];
+      if (!u) v[p] -= t[p];
+      used[p >> 5] |= 1u << (p & 31);
+    }
+  T c[N * NQ];
+#pragma unroll
+  for (int Jp = 0; Jp < N; ++Jp)
+#pragma unroll
+    for (int jq = 0; jq < NQ; ++jq) {
+      T s = 0;
+#pragma unroll
+      for (int jp = 0; jp < N; ++jp) s += emb<N>(m, bb[P], jp, Jp) * w[jp * NQ + jq];
+      c[Jp * NQ + jq] = s;
+    }
+  if (DIM == 2) {
+#pragma unroll
+    for (int Jp = 0; Jp < N; ++Jp) v[fpos<DIM, N, A, JA>(Jp, 0)] += c[Jp];
+    return;
+  }
+#pragma unroll
+  for (int Jp = 0; Jp < N; ++Jp)
+#pragma unroll
+    for (int Jq = 0; Jq < N; ++Jq) {
+      T s = 0;
+#pragma unroll
+      for (int jq = 0; jq < N; ++jq) s += emb<N>(m, bb[Q], jq, Jq) * c[Jp * NQ + jq];
+      v[fpos<DIM, N, A, JA>(Jp, Jq)] += s;
+    }
+}
+
+// edge along axis A at j_P = JP, j_Q = JQ (3D)
+template <int N, int A, int JP, int JQ>
+__device__ constexpr int epos(int ja) {
+  return A == 0 ? lidx<3, N>(ja, JP, JQ) : (A == 1 ? lidx<3, N>(JP, ja, JQ) : lidx<3, N>(JP, JQ, ja));
+}
+
+template <int N, int A, int JP, int JQ, typename T>
+__device__ __forceinline__ void edge_fwd(const Mats<T>& m, int b, const T* uc, T* u) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T s = 0;
+#pragma unroll
+    for (int J = 0; J < N; ++J) s += emb<N>(m, b, j, J) * uc[epos<N, A, JP, JQ>(J)];
+    u[epos<N, A, JP, JQ>(j)] = s;
+  }
+}
+
+template <int N, int A, int JP, int JQ, typename T>
+__device__ __forceinline__ void edge_bwd(const Mats<T>& m, int b, const T* t, T* v, uint32_t* used) {
+  T w[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int p = epos<N, A, JP, JQ>(j);
+    const bool u = (used[p >> 5] >> (p & 31)) & 1u;
+    w[j] = u ? T(0) : t[p];
+    if (!u) v[p] -= t[p];
+    used[p >> 5] |= 1u << (p & 31);
+  }
+#pragma unroll
+  for (int J = 0; J < N; ++J) {
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += emb<N>(m, b, j, J) * w[j];
+    v[epos<N, A, JP, JQ>(J)] += s;
+  }
+}
+
+template <int N, int A, typename T>
+__device__ __forceinline__ void edge_dispatch(const Mats<T>& m, const int* bb, const T* in, T* out, uint32_t* used,
+                                              bool fwd) {
+  constexpr int P = A == 0 ? 1 : 0;
+  constexpr int Q = A == 2 ? 1 : 2;
+  constexpr int K = N - 1;
+  const int sel = bb[P] + 2 * bb[Q];
+  if (fwd) {
+    if (sel == 0) edge_fwd<N, A, 0, 0>(m, bb[A], in, out);
+    else if (sel == 1) edge_fwd<N, A, K, 0>(m, bb[A], in, out);
+    else if (sel == 2) edge_fwd<N, A, 0, K>(m, bb[A], in, out);
+    else edge_fwd<N, A, K, K>(m, bb[A], in, out);
+  } else {
+    if (sel == 0) edge_bwd<N, A, 0, 0>(m, bb[A], in, out, used);
+    else if (sel == 1) edge_bwd<N, A, K, 0>(m, bb[A], in, out, used);
+    else if (sel == 2) edge_bwd<N, A, 0, K>(m, bb[A], in, out, used);
+    else edge_bwd<N, A, K, K>(m, bb[A], in, out, used);
+  }
+}
+
+template <int DIM, int N, int A, typename T>
+__device__ __forceinline__ void face_dispatch(const Mats<T>& m, const int* bb, const T* in, T* out, uint32_t* used,
+                                              bool fwd) {
+  constexpr int K = N - 1;
+  if (fwd) {
+    if (bb[A]) face_fwd<DIM, N, A, K>(m, bb, in, out);
+    else face_fwd<DIM, N, A, 0>(m, bb, in, out);
+  } else {
+    if (bb[A]) face_bwd<DIM, N, A, K>(m, bb, in, out, used);
+    else face_bwd<DIM, N, A, 0>(m, bb, in, out, used);
+  }
+}
+
+// u <- C_K u (fwd) or v <- C_K^T v (bwd) for the mask of a leaf
+template <int DIM, int N, typename T>
+__device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u, bool fwd) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  T c[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) c[j] = u[j];
+  const int bb[3] = {(int)(mask & 1u), (int)((mask >> 1) & 1u), (int)((mask >> 2) & 1u)};
+  uint32_t used[(NP + 31) / 32];
+#pragma unroll
+  for (int w = 0; w < (NP + 31) / 32; ++w) used[w] = 0u;
+  if ((mask >> 3) & 1u) face_dispatch<DIM, N, 0>(m, bb, c, u, used, fwd);
+  if ((mask >> 4) & 1u) face_dispatch<DIM, N, 1>(m, bb, c, u, used, fwd);
+  if (DIM == 3) {
+    if ((mask >> 5) & 1u) face_dispatch<DIM, N, 2>(m, bb, c, u, used, fwd);
+    if ((mask >> 6) & 1u) edge_dispatch<N, 0>(m, bb, c, u, used, fwd);
+    if ((mask >> 7) & 1u) edge_dispatch<N, 1>(m, bb, c, u, used, fwd);
+    if ((mask >> 8) & 1u) edge_dispatch<N, 2>(m, bb, c, u, used, fwd);
+  }
+}
+
 // ------------------------------------------------------------------ cell operator
 // MODE 0: plain gather/scatter (level operator, smoother and residual).
 // MODE 1: leaf operator: ids >= n_main address the hanging-node buffers.
@@ -231,20 +425,16 @@ __global__ void __launch_bounds__(kBlock) cell_apply(
 template <int DIM, int N, typename T, bool LEAF, bool MASS>
 __global__ void __launch_bounds__(kBlock) cell_to_slots(
     int64_t n_cells, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
-    const double* __restrict__ scale, double scale0, const T* __restrict__ x, const T* __restrict__ xh,
-    int64_t n_main, T* __restrict__ E, Mats<T> m) {
+    const double* __restrict__ scale, double scale0, const T* __restrict__ x,
+    const uint16_t* __restrict__ mask, T* __restrict__ E, Mats<T> m) {
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   const int64_t c = xcd_tid();
   if (c >= n_cells) return;
   T u[NP], v[NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int32_t g = cmap[(int64_t)j * n_cells + c];
-    if (LEAF)
-      u[j] = g < n_main ? x[g] : xh[g - n_main];
-    else
-      u[j] = x[g];
-  }
+  for (int j = 0; j < NP; ++j) u[j] = x[cmap[(int64_t)j * n_cells + c]];
+  const uint32_t mk = LEAF ? (uint32_t)mask[c] : 0u;
+  if (LEAF && (mk >> 3)) constrain<DIM, N, T>(m, mk, u, true);
   if (MASS) {
     mass_nd<DIM, N, T>(m, u, v);
   } else if (DIM == 3) {
@@ -252,6 +442,7 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   } else {
     laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
   }
+  if (LEAF && (mk >> 3)) constrain<DIM, N, T>(m, mk, v, false);
   const T s = T(scale ? scale[c] : scale0);
 #pragma unroll
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
@@ -574,7 +765,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, const double* __restrict__ ainv,
                                                        const int32_t* __restrict__ idx, const T* __restrict__ d0,
                                                        T* __restrict__ x0) {
-  extern __shared__ double sd[];
+  HIP_DYNAMIC_SHARED(double, sd)
   for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) x0[i] = T(0);
   for (int i = threadIdx.x; i < n0; i += blockDim.x) sd[i] = double(d0[idx[i]]);
   __syncthreads();
@@ -649,40 +840,13 @@ __global__ void seg_restrict_start(int64_t n, const int32_t* __restrict__ off, c
 
 #ifdef GMG_SOLVER_TU
 // Non-template kernels: compiled in the solver translation unit only.
-// hanging nodes: xh[h] = sum_j w_hj x[m_hj]; condensation y[m_hj] += w_hj yh[h]
-__global__ void hang_fill(int64_t H, const int64_t* __restrict__ off, const int32_t* __restrict__ mas,
-                          const double* __restrict__ w, const double* __restrict__ x, double* __restrict__ xh) {
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= H) return;
-  double s = 0.0;
-  for (int64_t p = off[h]; p < off[h + 1]; ++p) s += w[p] * x[mas[p]];
-  xh[h] = s;
-}
 
-__global__ void hang_condense(int64_t H, const int64_t* __restrict__ off, const int32_t* __restrict__ mas,
-                              const double* __restrict__ w, const double* __restrict__ yh, double* __restrict__ y) {
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= H) return;
-  const double v = yh[h];
-  for (int64_t p = off[h]; p < off[h + 1]; ++p) atomic_add(&y[mas[p]], w[p] * v);
-}
-
-// leaf operator, pass 2: hanging-node sums, then DoF sums plus the
-// condensation y_m += sum_h w_hm y_h (transposed constraints, gathered)
-__global__ void seg_hang(int64_t H, const int32_t* __restrict__ off, const double* __restrict__ E,
-                         double* __restrict__ yh) {
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < H) yh[h] = seg_sum(off, E, h);
-}
-
-__global__ void seg_leaf(int64_t n, const int32_t* __restrict__ off, const double* __restrict__ E,
-                         const int64_t* __restrict__ toff, const int32_t* __restrict__ th,
-                         const double* __restrict__ tw, const double* __restrict__ yh,
-                         const uint8_t* __restrict__ dir, double* __restrict__ y) {
+// leaf operator, pass 2: per-DoF sums, Dirichlet rows zero
+__global__ void seg_dir(int64_t n, const int32_t* __restrict__ off, const double* __restrict__ E,
+                        const uint8_t* __restrict__ dir, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = seg_sum(off, E, i);
-  for (int64_t p = toff[i]; p < toff[i + 1]; ++p) s += tw[p] * yh[th[p]];
+  const double s = seg_sum(off, E, i);
   y[i] = dir[i] ? 0.0 : s;
 }
 

@@ -47,14 +47,9 @@ struct Problem {
   LeafView leaf;
   int64_t n_total = 0;   // sum of level DoFs
   int64_t n_dir = 0;
-  const int32_t* dir = nullptr;
-  const int64_t* con_off = nullptr;
-  const int32_t* con_mas = nullptr;
-  const double* con_w = nullptr;
   const int32_t* copy = nullptr;
   void *lx = nullptr, *lg = nullptr, *lt = nullptr, *ld = nullptr, *ldinv = nullptr;
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
-  double *xh = nullptr, *yh = nullptr;
   double* E = nullptr;     // node-major slots of the two-pass operator (used as float or double)
   double *scal = nullptr, *part = nullptr;
   double* ainv = nullptr;

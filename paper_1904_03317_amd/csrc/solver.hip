@@ -127,28 +127,18 @@ size_t plan_workspace(Problem& P, char* base) {
   P.lt = pl.take<char>(size_t(off) * esz);
   P.ld = pl.take<char>(size_t(off) * esz);
   P.ldinv = pl.take<char>(size_t(off) * esz);
-  const int64_t N = M.n_dofs, H = M.n_hanging;
+  const int64_t N = M.n_dofs;
   P.leaf.n_cells = M.n_leaves;
   P.leaf.n_dofs = N;
   P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
+  P.leaf.mask = pl.take<uint16_t>(M.n_leaves);
   P.leaf.scale = pl.take<double>(M.n_leaves);
   P.leaf.mscale = pl.take<double>(M.n_leaves);
   P.leaf.slot = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
-  P.leaf.soff = pl.take<int32_t>(N + H + 1);
-  P.leaf.toff = pl.take<int64_t>(N + 1);
-  P.leaf.th = pl.take<int32_t>(M.con_mas.size());
-  P.leaf.tw = pl.take<double>(M.con_mas.size());
+  P.leaf.soff = pl.take<int32_t>(N + 1);
   P.leaf.dir = pl.take<uint8_t>(N);
-  P.leaf.n_hang = H;
-  e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
-  if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
-  P.E = pl.take<double>(e_max);
   P.n_dir = 0;
   for (auto d : M.dirichlet) P.n_dir += d;
-  P.dir = pl.take<int32_t>(P.n_dir);
-  P.con_off = pl.take<int64_t>(H + 1);
-  P.con_mas = pl.take<int32_t>(M.con_mas.size());
-  P.con_w = pl.take<double>(M.con_w.size());
   P.copy = pl.take<int32_t>(N);
   P.cx = pl.take<double>(N);
   P.cr = pl.take<double>(N);
@@ -156,8 +146,9 @@ size_t plan_workspace(Problem& P, char* base) {
   P.cp = pl.take<double>(N);
   P.cq = pl.take<double>(N);
   P.cb = pl.take<double>(N);
-  P.xh = pl.take<double>(H);
-  P.yh = pl.take<double>(H);
+  e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
+  if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
+  P.E = pl.take<double>(e_max);
   P.scal = pl.take<double>(dev::kNumScalars + 8);
   P.part = pl.take<double>(dev::kDotBlocks);
   int n0 = 0;
@@ -416,36 +407,14 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     HIPCHECK(hipStreamSynchronize(s));
   }
   {
-    std::vector<int32_t> cm(M.leaf_cellmap.size());
-    for (size_t i = 0; i < cm.size(); ++i) {
-      int32_t v = M.leaf_cellmap[i];
-      cm[i] = v >= 0 ? v : (int32_t)(M.n_dofs + (-v - 1));
-    }
+    const std::vector<int32_t>& cm = M.leaf_cellmap_parent;
     h2d(P.leaf.cmap, soa(cm, M.n_leaves, M.npc), s);
+    h2d(P.leaf.mask, M.leaf_mask, s);
     {
       std::vector<int32_t> off, sl;
-      build_slots(cm, M.n_leaves, M.npc, M.n_dofs + M.n_hanging, off, sl);
+      build_slots(cm, M.n_leaves, M.npc, M.n_dofs, off, sl);
       h2d(P.leaf.slot, sl, s);
       h2d(P.leaf.soff, off, s);
-      HIPCHECK(hipStreamSynchronize(s));
-    }
-    {
-      // transposed constraints: for each master DoF, its hanging nodes
-      std::vector<int64_t> toff(M.n_dofs + 1, 0);
-      for (auto m : M.con_mas) ++toff[m + 1];
-      for (int64_t i = 0; i < M.n_dofs; ++i) toff[i + 1] += toff[i];
-      std::vector<int64_t> pos(toff.begin(), toff.end() - 1);
-      std::vector<int32_t> th(M.con_mas.size());
-      std::vector<double> tw(M.con_mas.size());
-      for (int64_t h = 0; h < M.n_hanging; ++h)
-        for (int64_t q = M.con_off[h]; q < M.con_off[h + 1]; ++q) {
-          int64_t at = pos[M.con_mas[q]]++;
-          th[at] = (int32_t)h;
-          tw[at] = M.con_w[q];
-        }
-      h2d(P.leaf.toff, toff, s);
-      h2d(P.leaf.th, th, s);
-      h2d(P.leaf.tw, tw, s);
       h2d(P.leaf.dir, M.dirichlet, s);
       HIPCHECK(hipStreamSynchronize(s));
     }
@@ -457,13 +426,6 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     }
     h2d(P.leaf.scale, sc, s);
     h2d(P.leaf.mscale, ms, s);
-    std::vector<int32_t> dl;
-    for (int64_t i = 0; i < M.n_dofs; ++i)
-      if (M.dirichlet[i]) dl.push_back((int32_t)i);
-    h2d(P.dir, dl, s);
-    h2d(P.con_off, M.con_off, s);
-    h2d(P.con_mas, M.con_mas, s);
-    h2d(P.con_w, M.con_w, s);
     std::vector<int32_t> cp(M.n_dofs);
     for (int64_t i = 0; i < M.n_dofs; ++i) {
       int64_t g = P.lv[M.copy_level[i]].off + M.copy_index[i];
@@ -508,14 +470,13 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- operators
+// leaf operator q = C^T A C p with Dirichlet rows zero (or the mass matrix):
+// hanging-node constraints applied inside the cells (pass 1), per-DoF sums
+// (pass 2)
 void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s) {
-  const Maps& M = P.maps;
-  const int64_t N = M.n_dofs, H = M.n_hanging;
-  if (H) hipLaunchKernelGGL(dev::hang_fill, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.con_off, P.con_mas, P.con_w, x, P.xh);
-  P.kt->leaf_e(P.leaf, x, P.xh, P.E, mass, P.m64, s);
-  if (H) hipLaunchKernelGGL(dev::seg_hang, dim3(grid1(H)), dim3(dev::kBlock), 0, s, H, P.leaf.soff + N, P.E, P.yh);
-  hipLaunchKernelGGL(dev::seg_leaf, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.toff,
-                     P.leaf.th, P.leaf.tw, P.yh, P.leaf.dir, y);
+  const int64_t N = P.maps.n_dofs;
+  P.kt->leaf_e(P.leaf, x, P.E, mass, P.m64, s);
+  hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.dir, y);
 }
 
 template <typename T>

@@ -15,9 +15,10 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgmg.so")
 
 GMG_OK, GMG_NOT_CONVERGED = 0, 1
 ARR = dict(LEAF_CELLMAP=1, LEAF_DIRICHLET=2, CON_OFFSETS=3, CON_MASTERS=4, CON_WEIGHTS=5,
-           COPY_LEVEL=6, COPY_INDEX=7, LEVEL_CELLMAP=8, LEVEL_FLAGS=9, LEVEL_PARENT=10)
+           COPY_LEVEL=6, COPY_INDEX=7, LEVEL_CELLMAP=8, LEVEL_FLAGS=9, LEVEL_PARENT=10,
+           LEAF_CELLMAP_PARENT=11, LEAF_MASK=12)
 _ARR_DTYPE = {1: np.int32, 2: np.uint8, 3: np.int64, 4: np.int32, 5: np.float64, 6: np.int8,
-              7: np.int32, 8: np.int32, 9: np.uint8, 10: np.int32}
+              7: np.int32, 8: np.int32, 9: np.uint8, 10: np.int32, 11: np.int32, 12: np.uint16}
 
 
 class gmg_options(C.Structure):
@@ -58,17 +59,8 @@ class GMGError(RuntimeError):
 _lib = None
 
 
-def lib():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_1904_03317_amd.build)")
-    try:  # share torch's HIP runtime when torch is present
-        import torch  # noqa: F401
-    except Exception:
-        pass
-    L = C.CDLL(LIB_PATH)
+def configure(L):
+    """Set the ctypes signatures of every exported function on a loaded library."""
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
         "gmg_options_default": (None, [C.POINTER(gmg_options)]),
@@ -107,6 +99,21 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_1904_03317_amd.build)")
+    try:  # share torch's HIP runtime when torch is present
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    L = C.CDLL(LIB_PATH)
+    configure(L)
     _lib = L
     return L
 

@@ -1,0 +1,121 @@
+"""Run the library's kernels in the CPU emulation (AddressSanitizer build)
+on a small seeded case and compare with the oracle.  Invoked by
+tests/test_cpu_emulation.py in a subprocess with libasan preloaded; prints
+one JSON line.  Usage: run_emu.py <case> <precision> [checks]"""
+import ctypes as C
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import gmg_inputs as gi  # noqa: E402
+from helpers import CASES, oracle_problem  # noqa: E402
+from paper_1904_03317_amd import gmg  # noqa: E402
+
+L = gmg.configure(C.CDLL(os.path.join(HERE, "_build", "libgmg_emu.so")))
+
+
+def check(code):
+    if code < 0:
+        raise RuntimeError(f"error {code}: {L.gmg_last_error().decode()}")
+    return code
+
+
+def ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def aligned(nbytes):
+    raw = np.zeros(nbytes + 512, np.uint8)
+    off = (-raw.ctypes.data) % 256
+    return raw, raw[off:off + nbytes]
+
+
+def main():
+    case, prec = sys.argv[1], int(sys.argv[2])
+    checks = sys.argv[3].split(",") if len(sys.argv) > 3 else ["leaf", "level", "vcycle", "solve"]
+    rec, k = CASES[case]
+    coeff_kind = "checker" if rec.coarse == "fichera" else "one"
+    op, coeff = oracle_problem(rec, k, coeff_kind=coeff_kind)
+    dim, origins = gi.coarse_mesh(rec.coarse)
+    m = C.c_void_p()
+    o = np.ascontiguousarray(origins, dtype=np.int32)
+    check(L.gmg_mesh_create(dim, len(o), ptr(o), C.byref(m)))
+    for step in range(rec.steps):
+        n = C.c_int64()
+        check(L.gmg_mesh_num_leaves(m, C.byref(n)))
+        lv = np.zeros(n.value, np.int8)
+        an = np.zeros((n.value, dim), np.int64)
+        check(L.gmg_mesh_leaves(m, ptr(lv), ptr(an)))
+        f = np.ascontiguousarray(rec.flags(step, lv, an), dtype=np.uint8)
+        check(L.gmg_mesh_refine(m, ptr(f), None))
+    opts = gmg.gmg_options()
+    L.gmg_options_default(C.byref(opts))
+    opts.degree, opts.mg_precision = k, prec
+    P = C.c_void_p()
+    c = None if coeff is None else np.ascontiguousarray(coeff, np.float64)
+    check(L.gmg_problem_create(m, C.byref(opts), None if c is None else ptr(c), C.byref(P)))
+    nb = C.c_size_t()
+    check(L.gmg_problem_workspace_bytes(P, C.byref(nb)))
+    raw, ws = aligned(nb.value)
+    check(L.gmg_problem_bind(P, ptr(ws), nb.value, None))
+    out = {"case": case, "prec": prec, "N": op.n_dofs}
+    info = gmg.gmg_info()
+    check(L.gmg_problem_info(P, C.byref(info)))
+    out["lam_rel"] = max(abs(info.lambda_max[l] - op.mg.lam[l]) / op.mg.lam[l] for l in range(1, info.n_levels))
+    rng = np.random.default_rng(5)
+    N = op.n_dofs
+    if "leaf" in checks:
+        x = rng.standard_normal(N)
+        x[~op.free] = 0
+        y = np.zeros(N)
+        check(L.gmg_apply_leaf(P, ptr(x), ptr(y), None))
+        ref = op.A @ x
+        out["leaf_rel"] = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+        fn = 1.0 + rng.standard_normal(N)
+        b = np.zeros(N)
+        check(L.gmg_rhs(P, ptr(fn), ptr(b), None))
+        rb = op.rhs(fn)
+        out["rhs_rel"] = float(np.linalg.norm(b - rb) / np.linalg.norm(rb))
+    if "level" in checks:
+        from oracle.assemble import level_coefficients, level_matrix
+        lc = level_coefficients(op.disc, op.coeff)
+        worst = 0.0
+        dt = np.float64 if prec == 64 else np.float32
+        for l, lev in enumerate(op.disc.levels):
+            A = level_matrix(op.disc, l, lc[l]).tocsr()
+            x = rng.standard_normal(lev.n_dofs).astype(dt)
+            y = np.zeros(lev.n_dofs, dt)
+            check(L.gmg_apply_level(P, l, 0, ptr(x), ptr(y), None))
+            ref = A @ x.astype(np.float64)
+            worst = max(worst, float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300)))
+        out["level_rel"] = worst
+    if "vcycle" in checks:
+        r = rng.standard_normal(N)
+        r[~op.free] = 0
+        z = np.zeros(N)
+        check(L.gmg_vcycle(P, ptr(r), ptr(z), None))
+        zr = op.mg.vcycle(r)
+        out["vcycle_rel"] = float(np.linalg.norm(z - zr) / np.linalg.norm(zr))
+    if "solve" in checks:
+        fn = gi.rhs_nodal("noise", N)
+        x, it, hist, ok = op.solve(fn)
+        u = np.zeros(N)
+        its = C.c_int32()
+        h = np.zeros(opts.max_iter + 1)
+        st = check(L.gmg_solve(P, ptr(fn), ptr(u), C.byref(its), ptr(h), None))
+        out.update(status=st, its=its.value, its_oracle=it,
+                   solve_rel=float(np.linalg.norm(u - x) / np.linalg.norm(x)))
+    L.gmg_problem_destroy(P)
+    L.gmg_mesh_destroy(m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,11 +24,11 @@ CASES = {
     # name: (recipe, degree)
     "lshape-q1": (recipe("lshape", 3, 3, "corner"), 1),
     "lshape-q2": (recipe("lshape", 2, 3, "corner"), 2),
-    "lshape-q4": (recipe("lshape", 1, 3, "corner"), 4),
+    "lshape-q4": (recipe("lshape", 2, 3, "corner"), 4),
     "fichera-q1": (recipe("fichera", 1, 2, "corner+random"), 1),
     "fichera-q2": (recipe("fichera", 1, 2, "corner+random"), 2),
-    "fichera-q3": (recipe("fichera", 0, 2, "corner+random"), 3),
-    "fichera-q4": (recipe("fichera", 0, 2, "corner+random"), 4),
+    "fichera-q3": (recipe("fichera", 1, 2, "corner+random"), 3),
+    "fichera-q4": (recipe("fichera", 1, 1, "corner+random"), 4),
     "cube-q2": (recipe("cube", 2, 2, "corner"), 2),
 }
 
