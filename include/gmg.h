@@ -77,8 +77,8 @@ typedef struct {
   double rtol;           /* stop when ||b - A u||_2 <= rtol ||b||_2 */
   int32_t max_iter;      /* CG iteration cap */
   int32_t use_graph;     /* 1: replay the V-cycle as a captured HIP graph */
-  int32_t op_variant;    /* level operator pass 1: 0 auto, 1 one lane per cell, 2 sibling-family
-                            patches in LDS (levels >= 1) */
+  int32_t op_variant;    /* level operator form; 0 (the only value): sibling-family patches on
+                            levels >= 1 in the entity layout (GMG_ARR_LEVEL_PERM) */
 } gmg_options;
 
 void gmg_options_default(gmg_options* opts);
@@ -145,7 +145,11 @@ int gmg_problem_info(gmg_problem p, gmg_info* out);
  *                         edge shared with a coarser leaf, the DoF of the parent's node at the
  *                         same local position (interpolated in the cell by the 1D embedding)
  *   GMG_ARR_LEAF_MASK     uint16 n_leaves         bits 0-2 child position, 3-5 hanging face
- *                         normal to x/y/z, 6-8 hanging edge along x/y/z */
+ *                         normal to x/y/z, 6-8 hanging edge along x/y/z
+ *   GMG_ARR_LEVEL_PERM    int32  level_dofs        device index of each level DoF (level given):
+ *                         levels >= 1 store their vectors in the entity layout of their sibling
+ *                         families (interiors, then facets, edges, vertices of the family
+ *                         lattice); level 0 keeps its numbering */
 enum {
   GMG_ARR_LEAF_CELLMAP = 1,
   GMG_ARR_LEAF_DIRICHLET = 2,
@@ -158,7 +162,8 @@ enum {
   GMG_ARR_LEVEL_FLAGS = 9,
   GMG_ARR_LEVEL_PARENT = 10,
   GMG_ARR_LEAF_CELLMAP_PARENT = 11,
-  GMG_ARR_LEAF_MASK = 12
+  GMG_ARR_LEAF_MASK = 12,
+  GMG_ARR_LEVEL_PERM = 13
 };
 int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int64_t* count);
 
@@ -195,7 +200,8 @@ int gmg_solve_rhs(gmg_problem p, const double* d_b, double* d_u, int32_t* iterat
 
 /* Test hooks (stream-ordered, no synchronisation):
  * leaf operator q = C^T A C p with Dirichlet rows zeroed (FP64, [n_dofs]);
- * level operator on level l (element type = mg precision, [level_dofs[l]]):
+ * level operator on level l (element type = mg precision, [level_dofs[l]],
+ * vectors in the device layout of the level, see GMG_ARR_LEVEL_PERM):
  *   variant 0 (smoother): y = A_l x over all level cells, every row written
  *     (rows of S nodes give A^S x^S when x is zero on I and D nodes);
  *   variant 1 (edge): y^S = A^{SI} x^I: input restricted to I nodes, output

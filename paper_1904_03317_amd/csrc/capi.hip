@@ -134,7 +134,7 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
     REQUIRE(opts->eig_iters >= 1 && opts->eig_iters <= 100, "eig_iters must be 1..100");
     REQUIRE(opts->rtol > 0 && opts->max_iter >= 1, "rtol > 0 and max_iter >= 1 required");
     REQUIRE(m->f->max_level() < 24, "too many levels");
-    REQUIRE(opts->op_variant >= 0 && opts->op_variant <= 2, "op_variant must be 0, 1 or 2");
+    REQUIRE(opts->op_variant == 0, "op_variant must be 0");
     auto p = std::make_unique<gmg_problem_s>();
     gmg::Problem& P = p->P;
     P.opt = *opts;
@@ -229,6 +229,11 @@ int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int
         *count = (int64_t)M.leaf_cellmap_parent.size();
         break;
       case GMG_ARR_LEAF_MASK: *ptr = M.leaf_mask.data(); *count = (int64_t)M.leaf_mask.size(); break;
+      case GMG_ARR_LEVEL_PERM:
+        lev();
+        *ptr = M.layouts[level].perm.data();
+        *count = (int64_t)M.layouts[level].perm.size();
+        break;
       default: gmg::fail(GMG_E_INVAL, "unknown array");
     }
     return 0;

@@ -8,25 +8,33 @@
 
 namespace gmg {
 
+// Device view of one level, passed to the kernels by value.  Level 0 keeps
+// its own numbering and per-cell maps; levels >= 1 use the entity layout of
+// their families (host/layout.hpp) and hold no per-node or per-cell maps.
 struct LevelView {
-  int64_t n_cells = 0, n_dofs = 0, n_fam = 0, n_edge = 0;
-  const int32_t* cmap = nullptr;    // SoA [npc][n_cells]
+  int64_t n_cells = 0, n_dofs = 0, n_fam = 0;
   const double* scale = nullptr;    // per-cell a_K h^{d-2}, or null
   double scale0 = 1.0;              // uniform value when scale is null
-  const uint8_t* flags = nullptr;
-  const int32_t* edge = nullptr;
-  const int32_t* famap = nullptr;   // SoA [mf][n_fam]
-  const uint32_t* own = nullptr;    // SoA [own_words][n_fam]
-  const int32_t* parent = nullptr;
-  // two-pass operator: slot of (cell, local node) in the node-major buffer,
-  // and per-node slot ranges
-  const int32_t* slot = nullptr;    // SoA [npc][n_cells] (level 0: per-cell slots)
-  const int32_t* fslot = nullptr;   // SoA [mf][n_fam] (levels >= 1: per-family patch slots)
+  const uint8_t* flags = nullptr;   // [n_dofs] 0 S, 1 I, 2 D
+  // level 0: per-cell node map, operator slots of (cell, local node) in a
+  // node-major buffer with per-node ranges, and the ranges of the
+  // contributions restricted from level 1
+  const int32_t* cmap = nullptr;    // SoA [npc][n_cells]
+  const int32_t* slot = nullptr;    // SoA [npc][n_cells]
   const int32_t* soff = nullptr;    // [n_dofs + 1]
-  // restriction into the next coarser level: slot of (family, parent node)
-  const int32_t* rslot = nullptr;   // SoA [npc][n_fam]
-  // slot ranges of the contributions restricted from the next finer level
   const int32_t* roff = nullptr;    // [n_dofs + 1]
+  // levels >= 1: entity layout
+  const int32_t* gbase = nullptr;   // SoA [3^d][n_fam] device index of each entity's first node
+  const uint32_t* own = nullptr;    // [n_fam] bit j: the family owns entity j
+  const uint32_t* excl = nullptr;   // [n_fam] bit j: no other family touches entity j
+  const uint8_t* pmask = nullptr;   // [entities] present positions
+  const int32_t* parent = nullptr;  // [n_fam] parent cell on the next coarser level
+  const int32_t* child = nullptr;   // SoA [2^d][n_fam] family of each cell on the next finer level, or -1
+  const int32_t* rslot = nullptr;   // level 1: SoA [npc][n_fam] level-0 slots of the parent nodes
+  int64_t sec[5] = {0, 0, 0, 0, 0};     // first node of section r (r = boundary axes)
+  int64_t shn[5] = {0, 0, 0, 0, 0};     // prefix sums of the shared nodes of the sections
+  int64_t entoff[5] = {0, 0, 0, 0, 0};  // first shared entity of section r
+  int64_t eoff[5] = {0, 0, 0, 0, 0};    // first slot of section r (2^r slots per shared node)
 };
 
 struct LeafView {
@@ -45,17 +53,29 @@ struct MatsH {
   T M[25], K[25], E[45];
 };
 
+namespace dev {
+template <typename T>
+struct Epi;
+}
+
 template <typename T>
 struct LevelOps {
-  // pass 1 of y = A x over all cells: cell results into the slots E
-  void (*apply_e)(const LevelView&, const T* x, T* E, const MatsH<T>&, hipStream_t);
-  // y[S] += sign * A^{SI} x^I on the edge cells (atomic scatter; test hook)
-  void (*edge)(const LevelView&, const T* x, T* y, T sign, const MatsH<T>&, hipStream_t);
-  // x_f += P x_c on owned fine nodes
+  // levels >= 1, pass 1 of the operator: interior values through the
+  // epilogue epi (dev::kEpi*), shared-entity values into the slots E
+  void (*op)(const LevelView&, int epi, const T* x, const dev::Epi<T>&, T* E, const MatsH<T>&, hipStream_t);
+  // levels >= 1, pass 2: shared nodes, same epilogue
+  void (*sum)(const LevelView&, int epi, const T* E, const dev::Epi<T>&, hipStream_t);
+  // restriction of the fine residual r into coarse level >= 1 (rstart
+  // epilogue on the coarse interiors, coarse slots for the rest)
+  void (*restrict_fc)(const LevelView& fine, const LevelView& coarse, const T* r, const dev::Epi<T>& coarse_ep,
+                      T* E, const MatsH<T>&, hipStream_t);
+  // restriction from level 1 into the level-0 slots
+  void (*restrict0)(const LevelView& fine, const T* r, T* E, const MatsH<T>&, hipStream_t);
+  // x_f += P x_c
   void (*prolong)(const LevelView& fine, const LevelView& coarse, const T* xc, T* xf, const MatsH<T>&,
                   hipStream_t);
-  // family contributions of R r to the parent-node slots E
-  void (*restrict_e)(const LevelView& fine, const T* r, T* E, const MatsH<T>&, hipStream_t);
+  // level 0, pass 1 of the operator: cell results into the node-major slots
+  void (*cell_e)(const LevelView&, const T* x, T* E, const MatsH<T>&, hipStream_t);
 };
 
 struct KernelTable {
@@ -63,7 +83,8 @@ struct KernelTable {
   LevelOps<double> f64;
   // pass 1 of the leaf operator (or mass matrix): cell results into slots
   void (*leaf_e)(const LeafView&, const double* x, double* E, bool mass, const MatsH<double>&, hipStream_t);
-  void (*diag)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
+  // level 0: diagonal of the operator accumulated per node
+  void (*diag0)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
 };
 
 const KernelTable* kernel_table(int dim, int k);

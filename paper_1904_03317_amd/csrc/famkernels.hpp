@@ -1,0 +1,661 @@
+// Level kernels on the entity layout of levels >= 1 (families of 2^d
+// siblings; the layout is described in host/layout.hpp).  Operator, smoother
+// update, residual and transfers (Sec. 2.2, 2.3, 4.1) without stored node
+// maps: a family holds the base index of each of its 3^d entities, and the
+// node index and operator slot of every patch position follow from the
+// position's entity and its offset inside it.
+//
+// Operator, two passes.  Pass 1 (fam_op): a workgroup stages the node
+// patches of FB families in LDS (interiors, contiguous in memory, by
+// coalesced loads; entity nodes through the entity bases), one lane computes
+// one cell, siblings combine in LDS.  Values at nodes no other family
+// touches (the family interior, and level-boundary entities) are final and
+// go straight through the epilogue (Chebyshev update, residual, or plain
+// output); values at shared entities go to the entity's slot for this
+// family's position.  Pass 2 (fam_sum) runs over the shared nodes only:
+// each sums its present position slots in a fixed order and applies the
+// same epilogue.  No atomics in global memory, no index arrays per node;
+// all loads of an epilogue are issued before their values are used.
+#pragma once
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace gmg {
+namespace dev {
+
+enum { kEpiPlain = 0, kEpiCheb = 1, kEpiResid = 2, kEpiDiag = 3, kEpiRStart = 4 };
+
+// Vectors of one level for the epilogues (pointers already offset to the level).
+//   plain / diag: y = A x (or diag A)
+//   cheb:  d = c1 d + c2 D^{-1} (g - A x), x += d    (Sec. 4.1 smoother step)
+//   resid: y = g - A x, 0 on Dirichlet rows
+//   rstart: g += restricted contribution; if smooth: d = c2 D^{-1} g, x = d
+template <typename T>
+struct Epi {
+  T* x = nullptr;
+  T* d = nullptr;
+  T* y = nullptr;
+  T* g = nullptr;
+  const T* dinv = nullptr;
+  const uint8_t* flags = nullptr;
+  T c1 = 0, c2 = 0;
+  int smooth = 0;
+};
+
+// Patch geometry of a family: (2k+1)^d positions, 3^d entities.
+template <int DIM, int K>
+struct Geo {
+  static constexpr int N = K + 1, M2 = 2 * K + 1, S1 = 2 * K - 1;
+  static constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
+  static constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  static constexpr int NJ = DIM == 3 ? 27 : 9;
+  static constexpr int CPF = 1 << DIM;
+  static constexpr int NI = DIM == 3 ? S1 * S1 * S1 : S1 * S1;  // interior positions
+  static constexpr int NB = MF - NI;                             // entity positions
+  static constexpr int INTERIOR = DIM == 3 ? 13 : 4;             // entity index of the interior
+  // patch position of interior offset loc
+  __host__ __device__ static constexpr int iq(int loc) {
+    const int lx = loc % S1, ly = (loc / S1) % S1, lz = DIM == 3 ? loc / (S1 * S1) : 0;
+    return (lx + 1) + M2 * ((ly + 1) + M2 * (DIM == 3 ? lz + 1 : 0));
+  }
+  // index of an entity position among the entity positions (ascending q)
+  __host__ __device__ static constexpr int bidx(int q) {
+    const int qx = q % M2, qy = (q / M2) % M2, qz = DIM == 3 ? q / (M2 * M2) : 0;
+    auto cnt = [](int a) { return a <= 0 ? 0 : a - 1 > S1 ? S1 : a - 1; };
+    auto in = [](int a) { return a >= 1 && a <= S1; };
+    int before = DIM == 3 ? cnt(qz) * S1 * S1 : 0;
+    if (DIM == 2 || in(qz)) {
+      before += cnt(qy) * S1;
+      if (in(qy)) before += cnt(qx);
+    }
+    return q - before;
+  }
+  // code of position q: entity j (bits 0-4), offset in the entity (5-19),
+  // boundary axes r (20-21), position around the entity (23-25)
+  __host__ __device__ static constexpr uint32_t code(int q) {
+    int j = 0, loc = 0, r = 0, pos = 0, mul = 1, st = 1, t = q;
+    for (int a = 0; a < DIM; ++a) {
+      const int qa = t % M2;
+      t /= M2;
+      const int c = qa == 0 ? 0 : qa == 2 * K ? 2 : 1;
+      j += c * mul;
+      mul *= 3;
+      if (c == 1) {
+        loc += (qa - 1) * st;
+        st *= S1;
+      } else {
+        pos |= (c == 2 ? 1 : 0) << r;
+        ++r;
+      }
+    }
+    return (uint32_t)j | ((uint32_t)loc << 5) | ((uint32_t)r << 20) | ((uint32_t)pos << 23);
+  }
+  __host__ __device__ static constexpr int size_r(int r) {
+    int s = 1;
+    for (int i = 0; i < DIM - r; ++i) s *= S1;
+    return s;
+  }
+  static __device__ __forceinline__ int cj(uint32_t c) { return (int)(c & 31u); }
+  static __device__ __forceinline__ int cloc(uint32_t c) { return (int)((c >> 5) & 0x7fffu); }
+  static __device__ __forceinline__ int cr(uint32_t c) { return (int)((c >> 20) & 3u); }
+  static __device__ __forceinline__ int cpos(uint32_t c) { return (int)((c >> 23) & 7u); }
+};
+
+// Families per workgroup: LDS holds the input and output patches, the
+// entity bases of FB families and the position codes (80 KB, or 160 KB for
+// k >= 3, of the 160 KB of a gfx950 CU).
+template <int DIM, int K, typename T>
+struct FamShape {
+  using G = Geo<DIM, K>;
+  static constexpr int MF = G::MF, CPF = G::CPF, NJ = G::NJ;
+  // padded patch length: odd in 4-byte words so that families fall on
+  // different LDS banks
+  static constexpr int MFP = sizeof(T) == 4 ? (MF % 2 ? MF + 2 : MF + 1) : MF + 1;
+  static constexpr int budget = K >= 3 ? 163840 : 81920;
+  static constexpr int fixed = G::NB * 6 + 256;
+  static constexpr int fb_lds = (budget - fixed) / (2 * MFP * (int)sizeof(T) + NJ * 4 + 4);
+  static constexpr int fb_cap = 256 / CPF;
+  static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
+  static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
+  static constexpr int THREADS = FB * CPF;
+  static constexpr int ITI = (G::NI * FB + THREADS - 1) / THREADS;
+  static constexpr int ITB = (G::NB * FB + THREADS - 1) / THREADS;
+};
+
+// operator slot of a shared-entity position (r >= 1)
+template <int DIM, int K>
+__device__ __forceinline__ int64_t ent_slot(const LevelView& v, int32_t gb, uint32_t c) {
+  using G = Geo<DIM, K>;
+  const int r = G::cr(c);
+  const int sz = r == 1 ? G::size_r(1) : r == 2 ? G::size_r(2) : G::size_r(3);
+  return v.eoff[r] + ((int64_t)(gb - v.sec[r]) << r) + (int64_t)G::cpos(c) * sz + G::cloc(c);
+}
+
+// Epilogue on IT nodes (node < 0: nothing).  All loads first, at a valid
+// index (node 0 of the level when the node is skipped), then the updates.
+// FLAGS: the nodes may be interface or Dirichlet nodes (residual rows of D
+// nodes are zero); family-interior nodes are always smoothed nodes.
+// xo: the node's x before this operator application (Chebyshev update).
+template <typename T, int EPI, int IT, bool FLAGS>
+__device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int64_t (&node)[IT], const T (&ax)[IT],
+                                          const T (&xo)[IT]) {
+  int64_t ii[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) ii[it] = node[it] >= 0 ? node[it] : 0;
+  if (EPI == kEpiPlain || EPI == kEpiDiag) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (node[it] >= 0) ep.y[ii[it]] = ax[it];
+  } else if (EPI == kEpiCheb) {
+    T dv[IT], gv[IT], iv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      dv[it] = ep.d[ii[it]];
+      gv[it] = ep.g[ii[it]];
+      iv[it] = ep.dinv[ii[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (node[it] >= 0) {
+        const T dn = ep.c1 * dv[it] + ep.c2 * iv[it] * (gv[it] - ax[it]);
+        ep.d[ii[it]] = dn;
+        ep.x[ii[it]] = xo[it] + dn;
+      }
+  } else if (EPI == kEpiResid) {
+    T gv[IT];
+    uint8_t fv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      gv[it] = ep.g[ii[it]];
+      fv[it] = FLAGS ? ep.flags[ii[it]] : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (node[it] >= 0) ep.y[ii[it]] = fv[it] == 2 ? T(0) : gv[it] - ax[it];
+  } else {  // kEpiRStart
+    T gv[IT], iv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      gv[it] = ep.g[ii[it]];
+      iv[it] = ep.smooth ? ep.dinv[ii[it]] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (node[it] >= 0) {
+        const T gi = gv[it] + ax[it];
+        ep.g[ii[it]] = gi;
+        if (ep.smooth) {
+          const T dn = ep.c2 * iv[it] * gi;
+          ep.d[ii[it]] = dn;
+          ep.x[ii[it]] = dn;
+        }
+      }
+  }
+}
+
+// single shared node (pass 2)
+template <typename T, int EPI>
+__device__ __forceinline__ void epi_shared(const Epi<T>& ep, int64_t i, T ax) {
+  if (EPI == kEpiPlain || EPI == kEpiDiag) {
+    ep.y[i] = ax;
+  } else if (EPI == kEpiCheb) {
+    const T dn = ep.c1 * ep.d[i] + ep.c2 * ep.dinv[i] * (ep.g[i] - ax);
+    ep.d[i] = dn;
+    ep.x[i] += dn;
+  } else if (EPI == kEpiResid) {
+    ep.y[i] = ep.flags[i] == 2 ? T(0) : ep.g[i] - ax;
+  } else {
+    const T gi = ep.g[i] + ax;
+    ep.g[i] = gi;
+    if (ep.smooth) {
+      const T dn = ep.c2 * ep.dinv[i] * gi;
+      ep.d[i] = dn;
+      ep.x[i] = dn;
+    }
+  }
+}
+
+// stage the entity bases and exclusivity bits of the workgroup's families
+// and the table of entity positions (position, code)
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void stage_bases(const LevelView& v, int64_t f0, int32_t* sgb, uint32_t* sex,
+                                            uint16_t* bq, uint32_t* bc) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  for (int e = threadIdx.x; e < S::FB * G::NJ; e += S::THREADS) {
+    const int j = e / S::FB, fl = e % S::FB;
+    sgb[fl * G::NJ + j] = f0 + fl < v.n_fam ? v.gbase[(int64_t)j * v.n_fam + f0 + fl] : 0;
+  }
+  for (int fl = threadIdx.x; fl < S::FB; fl += S::THREADS) sex[fl] = f0 + fl < v.n_fam ? v.excl[f0 + fl] : 0u;
+  for (int q = threadIdx.x; q < G::MF; q += S::THREADS) {
+    const uint32_t c = G::code(q);
+    if (G::cr(c) != 0) {
+      const int b = G::bidx(q);
+      bq[b] = (uint16_t)q;
+      bc[b] = c;
+    }
+  }
+}
+
+// cell k of a family (child position bits x, y, z): offset of its node
+// (jx, jy, jz) in the family patch
+template <int DIM, int K>
+__device__ __forceinline__ int cell_patch_pos(int cid, int j) {
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2;
+  const int bx = (cid & 1) * K, by = ((cid >> 1) & 1) * K, bz = DIM == 3 ? ((cid >> 2) & 1) * K : 0;
+  const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+  return ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx);
+}
+
+// ------------------------------------------------------------------ pass 1
+// Output of a family patch held in LDS (sout): interior nodes and nodes of
+// exclusive entities through the epilogue, shared entities to their slots.
+// xo from sin (CHEB only).
+template <int DIM, int K, typename T, int EPI>
+__device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf, const T* sout, const T* sin,
+                                          const int32_t* sgb, const uint32_t* sex, const uint16_t* bq,
+                                          const uint32_t* bc, const Epi<T>& ep, T* __restrict__ E) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
+  const int tid = threadIdx.x;
+  {
+    int64_t node[S::ITI];
+    T ax[S::ITI], xo[S::ITI];
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) {
+      const int e = tid + it * S::THREADS;
+      node[it] = -1;
+      ax[it] = xo[it] = T(0);
+      if (e < nf * NI) {
+        const int fl = e / NI, q = G::iq(e % NI);
+        node[it] = f0 * NI + e;
+        ax[it] = sout[fl * MFP + q];
+        if (EPI == kEpiCheb) xo[it] = sin[fl * MFP + q];
+      }
+    }
+    epi_batch<T, EPI, S::ITI, false>(ep, node, ax, xo);
+  }
+  {
+    int64_t node[S::ITB];
+    T ax[S::ITB], xo[S::ITB];
+#pragma unroll
+    for (int it = 0; it < S::ITB; ++it) {
+      const int e = tid + it * S::THREADS;
+      node[it] = -1;
+      ax[it] = xo[it] = T(0);
+      if (e < nf * NB) {
+        const int fl = e / NB, b = e % NB;
+        const int q = bq[b];
+        const uint32_t c = bc[b];
+        const int j = G::cj(c);
+        const int32_t gb = sgb[fl * NJ + j];
+        const T val = sout[fl * MFP + q];
+        if ((sex[fl] >> j) & 1u) {
+          node[it] = (int64_t)gb + G::cloc(c);
+          ax[it] = val;
+          if (EPI == kEpiCheb) xo[it] = sin[fl * MFP + q];
+        } else {
+          E[ent_slot<DIM, K>(v, gb, c)] = val;
+        }
+      }
+    }
+    epi_batch<T, EPI, S::ITB, true>(ep, node, ax, xo);
+  }
+}
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelView v, const T* __restrict__ xin,
+                                                                          Epi<T> ep, T* __restrict__ E, Mats<T> m) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP;
+  constexpr int NI = G::NI, NB = G::NB;
+  __shared__ T sin[FB * MFP];
+  __shared__ T sout[FB * MFP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(v.n_fam - f0 < FB ? v.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  stage_bases<DIM, K, T>(v, f0, sgb, sex, bq, bc);
+  for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
+  __syncthreads();
+  if (EPI != kEpiDiag) {
+    T vi[S::ITI], vb[S::ITB];
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) {
+      const int e = tid + it * S::THREADS;
+      vi[it] = e < nf * NI ? xin[f0 * NI + e] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITB; ++it) {
+      const int e = tid + it * S::THREADS;
+      vb[it] = T(0);
+      if (e < nf * NB) {
+        const int fl = e / NB;
+        const uint32_t c = bc[e % NB];
+        vb[it] = xin[sgb[fl * NJ + G::cj(c)] + G::cloc(c)];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) {
+      const int e = tid + it * S::THREADS;
+      if (e < nf * NI) sin[(e / NI) * MFP + G::iq(e % NI)] = vi[it];
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITB; ++it) {
+      const int e = tid + it * S::THREADS;
+      if (e < nf * NB) sin[(e / NB) * MFP + bq[e % NB]] = vb[it];
+    }
+    __syncthreads();
+  }
+  {
+    const int fl = tid / CPF, cid = tid % CPF;
+    const int64_t f = f0 + fl;
+    if (fl < nf) {
+      T w[NP];
+      if (EPI == kEpiDiag) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+          const T mx = m.M[jx * N + jx], my = m.M[jy * N + jy], kx = m.K[jx * N + jx], ky = m.K[jy * N + jy];
+          if (DIM == 3) {
+            const T mz = m.M[jz * N + jz], kz = m.K[jz * N + jz];
+            w[j] = kx * my * mz + mx * ky * mz + mx * my * kz;
+          } else {
+            w[j] = kx * my + mx * ky;
+          }
+        }
+      } else {
+        T u[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) u[j] = sin[fl * MFP + cell_patch_pos<DIM, K>(cid, j)];
+        if (DIM == 3)
+          laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(w));
+        else
+          laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(w));
+      }
+      const T sc = T(v.scale ? v.scale[f * CPF + cid] : v.scale0);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], sc * w[j]);
+    }
+  }
+  __syncthreads();
+  patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, ep, E);
+}
+
+// ------------------------------------------------------------------ pass 2
+// shared nodes: sum of the present position slots (fixed order), epilogue
+template <int DIM, int K, int R, typename T>
+__device__ __forceinline__ T sum_slots(const LevelView& v, const T* __restrict__ E, int64_t i) {
+  using G = Geo<DIM, K>;
+  constexpr int SZ = G::size_r(R);
+  const int64_t t = i - v.sec[R];
+  const int64_t e = t / SZ;
+  const int loc = (int)(t - e * SZ);
+  const uint32_t pm = v.pmask[v.entoff[R] + e];
+  const T* p = E + v.eoff[R] + ((e << R) * SZ) + loc;
+  T s = T(0);
+#pragma unroll
+  for (int pos = 0; pos < (1 << R); ++pos)
+    if ((pm >> pos) & 1u) s += p[pos * SZ];
+  return s;
+}
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__(kBlock) fam_sum(LevelView v, const T* __restrict__ E, Epi<T> ep) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= v.shn[DIM + 1]) return;
+  T s;
+  int64_t i;
+  if (t < v.shn[2]) {
+    i = v.sec[1] + t;
+    s = sum_slots<DIM, K, 1, T>(v, E, i);
+  } else if (DIM == 2 || t < v.shn[3]) {
+    i = v.sec[2] + (t - v.shn[2]);
+    s = sum_slots<DIM, K, 2, T>(v, E, i);
+  } else {
+    i = v.sec[3] + (t - v.shn[3]);
+    s = sum_slots<DIM, K, DIM == 3 ? 3 : 2, T>(v, E, i);
+  }
+  epi_shared<T, EPI>(ep, i, s);
+}
+
+// ------------------------------------------------------------------ transfers
+// Fine-family values at patch position q (compile-time), read through the
+// fine family's entity bases; positions of entities the family does not own
+// read as zero when MASK is set.
+template <int DIM, int K>
+__device__ __forceinline__ int64_t fam_node(const int32_t (&gb)[Geo<DIM, K>::NJ], int q) {
+  using G = Geo<DIM, K>;
+  const uint32_t c = G::code(q);
+  return (int64_t)gb[G::cj(c)] + G::cloc(c);
+}
+
+// Restriction R = P^T of the fine residual r on the nodes the fine family
+// owns, contracted to the (k+1)^d values of its parent cell (row by row
+// while loading).
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void restrict_family(const LevelView& fine, int64_t f, const T* __restrict__ r,
+                                                const Mats<T>& m, T (&out)[Geo<DIM, K>::NP]) {
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2, NJ = G::NJ;
+  constexpr int NZ = DIM == 3 ? M2 : 1;
+  int32_t gb[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) gb[j] = fine.gbase[(int64_t)j * fine.n_fam + f];
+  const uint32_t ow = fine.own[f];
+  T a[NZ * M2 * N];
+#pragma unroll
+  for (int zy = 0; zy < NZ * M2; ++zy) {
+    T rv[M2];
+#pragma unroll
+    for (int i = 0; i < M2; ++i) rv[i] = r[fam_node<DIM, K>(gb, zy * M2 + i)];
+#pragma unroll
+    for (int i = 0; i < M2; ++i)
+      if (!((ow >> G::cj(G::code(zy * M2 + i))) & 1u)) rv[i] = T(0);
+#pragma unroll
+    for (int J = 0; J < N; ++J) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * rv[i];
+      a[zy * N + J] = s;
+    }
+  }
+  T b[NZ * N * N];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x)
+#pragma unroll
+      for (int J = 0; J < N; ++J) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * a[(z * M2 + i) * N + x];
+        b[(z * N + J) * N + x] = s;
+      }
+  if (DIM == 2) {
+#pragma unroll
+    for (int j = 0; j < N * N; ++j) out[j] = b[j];
+  } else {
+#pragma unroll
+    for (int J = 0; J < N; ++J)
+#pragma unroll
+      for (int yx = 0; yx < N * N; ++yx) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * b[i * N * N + yx];
+        out[J * N * N + yx] = s;
+      }
+  }
+}
+
+// Restriction into a level with families: one workgroup per FB coarse
+// families, one lane per coarse cell restricting the residual of the cell's
+// fine family (if the cell is refined); the coarse patch is summed in LDS
+// and leaves like an operator result with the rstart epilogue (every coarse
+// node of the level passes through it, restricted contribution or not;
+// pass 2 of the coarse level finishes the shared nodes).
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(LevelView fine, LevelView coarse,
+                                                                                const T* __restrict__ r, Epi<T> ep,
+                                                                                T* __restrict__ E, Mats<T> m) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
+  __shared__ T sout[FB * MFP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(coarse.n_fam - f0 < FB ? coarse.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  stage_bases<DIM, K, T>(coarse, f0, sgb, sex, bq, bc);
+  for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
+  __syncthreads();
+  {
+    const int fl = tid / CPF, cid = tid % CPF;
+    const int64_t f = fl < nf ? coarse.child[(int64_t)cid * coarse.n_fam + f0 + fl] : -1;
+    if (f >= 0) {
+      T out[NP];
+      restrict_family<DIM, K, T>(fine, f, r, m, out);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], out[j]);
+    }
+  }
+  __syncthreads();
+  patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, ep, E);
+}
+
+// Restriction from level 1 into level 0 (no families there): one lane per
+// level-1 family, parent-node values to the level-0 node-major slots
+// (summed by seg_restrict_start).
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) fam_restrict0(LevelView fine, const T* __restrict__ r,
+                                                        T* __restrict__ E, Mats<T> m) {
+  using G = Geo<DIM, K>;
+  const int64_t f = xcd_tid();
+  if (f >= fine.n_fam) return;
+  T out[G::NP];
+  restrict_family<DIM, K, T>(fine, f, r, m, out);
+#pragma unroll
+  for (int j = 0; j < G::NP; ++j) E[fine.rslot[(int64_t)j * fine.n_fam + f]] = out[j];
+}
+
+// Prolongation x_f += P x_c of one fine family from its parent cell's
+// (k+1)^d values u: the family's (2k+1)^d patch, written on the entities it
+// owns (each fine node is owned by exactly one family).
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void prolong_family(const LevelView& fine, int64_t f, const T (&u)[Geo<DIM, K>::NP],
+                                               T* __restrict__ xf, const Mats<T>& m) {
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2, NJ = G::NJ;
+  constexpr int NZ = DIM == 3 ? N : 1;
+  int32_t gb[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) gb[j] = fine.gbase[(int64_t)j * fine.n_fam + f];
+  const uint32_t ow = fine.own[f];
+  T a[NZ * N * M2];
+#pragma unroll
+  for (int rr = 0; rr < NZ * N; ++rr)
+#pragma unroll
+    for (int i = 0; i < M2; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += m.E[i * N + j] * u[rr * N + j];
+      a[rr * M2 + i] = s;
+    }
+  T b[NZ * M2 * M2];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < M2; ++x)
+#pragma unroll
+      for (int i = 0; i < M2; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.E[i * N + j] * a[(z * N + j) * M2 + x];
+        b[(z * M2 + i) * M2 + x] = s;
+      }
+  constexpr int NZF = DIM == 3 ? M2 : 1;
+#pragma unroll
+  for (int iz = 0; iz < NZF; ++iz) {
+    T old[M2 * M2];
+#pragma unroll
+    for (int yx = 0; yx < M2 * M2; ++yx) old[yx] = xf[fam_node<DIM, K>(gb, iz * M2 * M2 + yx)];
+#pragma unroll
+    for (int yx = 0; yx < M2 * M2; ++yx) {
+      const int q = iz * M2 * M2 + yx;
+      T s;
+      if (DIM == 3) {
+        s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += m.E[iz * N + j] * b[j * M2 * M2 + yx];
+      } else {
+        s = b[yx];
+      }
+      if ((ow >> G::cj(G::code(q))) & 1u) xf[fam_node<DIM, K>(gb, q)] = old[yx] + s;
+    }
+  }
+}
+
+// Prolongation from a level with families: one lane per fine family; the
+// parent cell's nodes are positions of the coarse family's patch, whose
+// entity bases the lane keeps in its own LDS row (indexed at run time).
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) fam_prolong(LevelView fine, LevelView coarse, const T* __restrict__ xc,
+                                                      T* __restrict__ xf, Mats<T> m) {
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, NJ = G::NJ, NP = G::NP;
+  __shared__ int32_t cg[kBlock * NJ];
+  const int64_t f = xcd_tid();
+  if (f >= fine.n_fam) return;
+  const int64_t p = fine.parent[f];
+  const int64_t F = p >> DIM;
+  const int cid = (int)(p & (G::CPF - 1));
+  int32_t* row = cg + threadIdx.x * NJ;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) row[j] = coarse.gbase[(int64_t)j * coarse.n_fam + F];
+  int b[3] = {(cid & 1) * K, ((cid >> 1) & 1) * K, DIM == 3 ? ((cid >> 2) & 1) * K : 0};
+  T u[NP];
+#pragma unroll
+  for (int jn = 0; jn < NP; ++jn) {
+    const int jc[3] = {jn % N, (jn / N) % N, DIM == 3 ? jn / (N * N) : 0};
+    int j = 0, loc = 0, mul = 1, st = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int qa = b[a] + jc[a];
+      const int c = qa == 0 ? 0 : qa == 2 * K ? 2 : 1;
+      j += c * mul;
+      mul *= 3;
+      if (c == 1) {
+        loc += (qa - 1) * st;
+        st *= G::S1;
+      }
+    }
+    u[jn] = xc[row[j] + loc];
+  }
+  prolong_family<DIM, K, T>(fine, f, u, xf, m);
+}
+
+// Prolongation from level 0 (per-cell node map): one lane per level-1 family.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) fam_prolong0(LevelView fine, LevelView coarse, const T* __restrict__ xc,
+                                                       T* __restrict__ xf, Mats<T> m) {
+  using G = Geo<DIM, K>;
+  const int64_t f = xcd_tid();
+  if (f >= fine.n_fam) return;
+  const int64_t p = fine.parent[f];
+  T u[G::NP];
+#pragma unroll
+  for (int j = 0; j < G::NP; ++j) u[j] = xc[coarse.cmap[(int64_t)j * coarse.n_cells + p]];
+  prolong_family<DIM, K, T>(fine, f, u, xf, m);
+}
+
+}  // namespace dev
+}  // namespace gmg

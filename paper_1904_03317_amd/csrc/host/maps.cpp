@@ -632,6 +632,8 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
       }
     }
   }
+  build_layouts(M);
+  T.mark("layouts");
   return M;
 }
 

@@ -8,6 +8,7 @@
 
 #include "fe1d.hpp"
 #include "forest.hpp"
+#include "layout.hpp"
 
 namespace gmg {
 
@@ -52,6 +53,7 @@ struct Maps {
   std::vector<int8_t> copy_level;     // [n_dofs]
   std::vector<int32_t> copy_index;    // [n_dofs]
   std::vector<LevelData> levels;
+  std::vector<LevelLayout> layouts;  // device layout of levels >= 1
 };
 
 Maps build_maps(const Forest& f, int k, const double* coeff);

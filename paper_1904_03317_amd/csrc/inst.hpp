@@ -3,6 +3,7 @@
 #include "dispatch.hpp"
 #include "gmg.h"
 #include "host/common.hpp"
+#include "famkernels.hpp"
 #include "kernels.hpp"
 
 namespace gmg {
@@ -24,40 +25,90 @@ template <int DIM, int K>
 struct Inst {
   static constexpr int N = K + 1;
 
-  template <typename T>
-  static void apply_e(const LevelView& v, const T* x, T* E, const MatsH<T>& m, hipStream_t s) {
-    if (!v.n_cells) return;
-    if (v.n_fam > 0 && v.fslot) {
-      using S = dev::FamilyShape<DIM, K, T>;
-      const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
-      hipLaunchKernelGGL((dev::family_to_slots<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, v.n_fam, v.famap,
-                         v.fslot, v.scale, v.scale0, x, E, to_dev(m));
-      return;
-    }
-    if (!v.slot) fail(GMG_E_STATE, "level operator has neither cell nor family slots");
-    hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, T, false, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
-                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const uint16_t*)nullptr, E,
-                       to_dev(m));
+  template <typename T, int EPI>
+  static void op_launch(const LevelView& v, const T* x, const dev::Epi<T>& ep, T* E, const MatsH<T>& m,
+                        hipStream_t s) {
+    using S = dev::FamShape<DIM, K, T>;
+    const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
+    hipLaunchKernelGGL((dev::fam_op<DIM, K, T, EPI>), dim3(g), dim3(S::THREADS), 0, s, v, x, ep, E, to_dev(m));
   }
   template <typename T>
-  static void edge(const LevelView& v, const T* x, T* y, T sign, const MatsH<T>& m, hipStream_t s) {
-    if (!v.n_edge) return;
-    hipLaunchKernelGGL((dev::cell_apply<DIM, N, T, 2, false>), dim3(grid_for(v.n_edge)), dim3(dev::kBlock), 0, s,
-                       v.n_edge, v.edge, v.n_cells, v.cmap, v.scale, v.scale0, x, (const T*)nullptr, y,
-                       (T*)nullptr, (int64_t)0, v.flags, sign, to_dev(m));
+  static void op(const LevelView& v, int epi, const T* x, const dev::Epi<T>& ep, T* E, const MatsH<T>& m,
+                 hipStream_t s) {
+    if (!v.n_fam) return;
+    if (!v.gbase) fail(GMG_E_STATE, "level operator called on a level without families");
+    switch (epi) {
+      case dev::kEpiPlain:
+        return op_launch<T, dev::kEpiPlain>(v, x, ep, E, m, s);
+      case dev::kEpiCheb:
+        return op_launch<T, dev::kEpiCheb>(v, x, ep, E, m, s);
+      case dev::kEpiResid:
+        return op_launch<T, dev::kEpiResid>(v, x, ep, E, m, s);
+      case dev::kEpiDiag:
+        if constexpr (sizeof(T) == 8) return op_launch<T, dev::kEpiDiag>(v, x, ep, E, m, s);
+        break;
+      default:
+        break;
+    }
+    fail(GMG_E_INVAL, "unsupported operator epilogue");
+  }
+  template <typename T>
+  static void sum(const LevelView& v, int epi, const T* E, const dev::Epi<T>& ep, hipStream_t s) {
+    const int64_t nb = v.shn[DIM + 1];
+    if (nb <= 0) return;
+    const dim3 g(grid_for(nb)), b(dev::kBlock);
+    switch (epi) {
+      case dev::kEpiPlain:
+      case dev::kEpiDiag:
+        hipLaunchKernelGGL((dev::fam_sum<DIM, K, T, dev::kEpiPlain>), g, b, 0, s, v, E, ep);
+        return;
+      case dev::kEpiCheb:
+        hipLaunchKernelGGL((dev::fam_sum<DIM, K, T, dev::kEpiCheb>), g, b, 0, s, v, E, ep);
+        return;
+      case dev::kEpiResid:
+        hipLaunchKernelGGL((dev::fam_sum<DIM, K, T, dev::kEpiResid>), g, b, 0, s, v, E, ep);
+        return;
+      case dev::kEpiRStart:
+        hipLaunchKernelGGL((dev::fam_sum<DIM, K, T, dev::kEpiRStart>), g, b, 0, s, v, E, ep);
+        return;
+      default:
+        break;
+    }
+    fail(GMG_E_INVAL, "unsupported operator epilogue");
+  }
+  template <typename T>
+  static void restrict_fc(const LevelView& f, const LevelView& c, const T* r, const dev::Epi<T>& ep, T* E,
+                          const MatsH<T>& m, hipStream_t s) {
+    if (!c.n_fam) return;
+    using S = dev::FamShape<DIM, K, T>;
+    const unsigned g = (unsigned)((c.n_fam + S::FB - 1) / S::FB);
+    hipLaunchKernelGGL((dev::fam_restrict<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, c, r, ep, E, to_dev(m));
+  }
+  template <typename T>
+  static void restrict0(const LevelView& f, const T* r, T* E, const MatsH<T>& m, hipStream_t s) {
+    if (!f.n_fam) return;
+    hipLaunchKernelGGL((dev::fam_restrict0<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s, f, r, E,
+                       to_dev(m));
   }
   template <typename T>
   static void prolong(const LevelView& f, const LevelView& c, const T* xc, T* xf, const MatsH<T>& m,
                       hipStream_t s) {
     if (!f.n_fam) return;
-    hipLaunchKernelGGL((dev::prolongate<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s, f.n_fam,
-                       f.famap, f.own, f.parent, c.n_cells, c.cmap, xc, xf, to_dev(m));
+    if (c.gbase) {
+      hipLaunchKernelGGL((dev::fam_prolong<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s, f, c, xc,
+                         xf, to_dev(m));
+    } else {
+      hipLaunchKernelGGL((dev::fam_prolong0<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s, f, c, xc,
+                         xf, to_dev(m));
+    }
   }
   template <typename T>
-  static void restrict_e(const LevelView& f, const T* r, T* E, const MatsH<T>& m, hipStream_t s) {
-    if (!f.n_fam) return;
-    hipLaunchKernelGGL((dev::restrict_to_slots<DIM, K, T>), dim3(grid_for(f.n_fam)), dim3(dev::kBlock), 0, s,
-                       f.n_fam, f.famap, f.own, r, f.rslot, E, to_dev(m));
+  static void cell_e(const LevelView& v, const T* x, T* E, const MatsH<T>& m, hipStream_t s) {
+    if (!v.n_cells) return;
+    if (!v.slot || !v.cmap) fail(GMG_E_STATE, "per-cell operator called on a level without cell maps");
+    hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, T, false, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
+                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const uint16_t*)nullptr, E,
+                       to_dev(m));
   }
   static void leaf_e(const LeafView& v, const double* x, double* E, bool mass, const MatsH<double>& m,
                      hipStream_t s) {
@@ -69,19 +120,18 @@ struct Inst {
       hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(v.n_cells)),
                          dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, v.mask, E, to_dev(m));
   }
-  static void diag(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
+  static void diag0(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;
     hipLaunchKernelGGL((dev::cell_diag<DIM, N>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock), 0, s, v.n_cells,
                        v.cmap, v.scale, v.scale0, d, to_dev(m));
   }
 
+  template <typename T>
+  static constexpr LevelOps<T> ops() {
+    return LevelOps<T>{&op<T>, &sum<T>, &restrict_fc<T>, &restrict0<T>, &prolong<T>, &cell_e<T>};
+  }
   static const KernelTable* table() {
-    static KernelTable t = {
-        {&apply_e<float>, &edge<float>, &prolong<float>, &restrict_e<float>},
-        {&apply_e<double>, &edge<double>, &prolong<double>, &restrict_e<double>},
-        &leaf_e,
-        &diag,
-    };
+    static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &diag0};
     return &t;
   }
 };

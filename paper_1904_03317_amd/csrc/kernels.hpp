@@ -1,9 +1,9 @@
 // HIP kernels for gfx950 (MI355X).  Matrix-free tensor-product operators on
 // axis-aligned cells (Sec. 3.2 matrix-free evaluation, here re-designed for
-// 64-wide wavefronts: one lane per cell, the whole cell tensor in registers,
-// coalesced structure-of-arrays index maps, scatter by hardware float
-// atomics), Chebyshev-Jacobi update (Sec. 4.1), family transfer operators
-// (Sec. 2.2) and CG vector kernels (FP64).
+// 64-wide wavefronts: one lane per cell, the whole cell tensor in registers),
+// the leaf operator with in-cell hanging-node constraints, level-0 kernels,
+// vector kernels of the smoother and the V-cycle (Sec. 4.1) and the FP64 CG.
+// The level kernels of levels >= 1 are in famkernels.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -361,61 +361,6 @@ __device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u,
   }
 }
 
-// ------------------------------------------------------------------ cell operator
-// MODE 0: plain gather/scatter (level operator, smoother and residual).
-// MODE 1: leaf operator: ids >= n_main address the hanging-node buffers.
-// MODE 2: edge operator on a cell subset: input restricted to I nodes,
-//         output to S nodes (y += sign * A^{SI} x^I).
-// MASS: mass matrix instead of the Laplacian.
-template <int DIM, int N, typename T, int MODE, bool MASS>
-__global__ void __launch_bounds__(kBlock) cell_apply(
-    int64_t n_items, const int32_t* __restrict__ list, int64_t n_cells,
-    const int32_t* __restrict__ cmap, const double* __restrict__ scale, double scale0,
-    const T* __restrict__ x, const T* __restrict__ xh, T* __restrict__ y, T* __restrict__ yh,
-    int64_t n_main, const uint8_t* __restrict__ flags, T sign, Mats<T> m) {
-  constexpr int NP = DIM == 3 ? N * N * N : N * N;
-  const int64_t t = xcd_tid();
-  if (t >= n_items) return;
-  const int64_t c = MODE == 2 ? (int64_t)list[t] : t;
-  int32_t id[NP];
-  T u[NP], v[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) id[j] = cmap[(int64_t)j * n_cells + c];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int32_t g = id[j];
-    if (MODE == 1) {
-      u[j] = g < n_main ? x[g] : xh[g - n_main];
-    } else if (MODE == 2) {
-      u[j] = flags[g] == 1 ? x[g] : T(0);
-    } else {
-      u[j] = x[g];
-    }
-  }
-  if (MASS) {
-    mass_nd<DIM, N, T>(m, u, v);
-  } else if (DIM == 3) {
-    laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(v));
-  } else {
-    laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
-  }
-  const T s = T(scale ? scale[c] : scale0) * sign;
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int32_t g = id[j];
-    if (MODE == 1) {
-      if (g < n_main)
-        atomic_add(&y[g], s * v[j]);
-      else
-        atomic_add(&yh[g - n_main], s * v[j]);
-    } else if (MODE == 2) {
-      if (flags[g] == 0) atomic_add(&y[g], s * v[j]);
-    } else {
-      atomic_add(&y[g], s * v[j]);
-    }
-  }
-}
-
 // Two-pass operator, pass 1: every (cell, local node) owns one slot of the
 // node-major buffer E (the slots of a node are contiguous), so the cell
 // results are written with plain stores and no two lanes ever write the same
@@ -446,97 +391,6 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   const T s = T(scale ? scale[c] : scale0);
 #pragma unroll
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
-}
-
-// Families per workgroup for the family-patch operator: one lane per cell,
-// the input and output patches of all families in LDS (<= 64 KB).
-template <int DIM, int K, typename T>
-struct FamilyShape {
-  static constexpr int M2 = 2 * K + 1;
-  static constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
-  static constexpr int CPF = 1 << DIM;
-  // padded row length: odd in 4-byte words so that the families of a wave
-  // fall on different LDS banks
-  static constexpr int MFP = sizeof(T) == 4 ? (MF % 2 ? MF + 2 : MF + 1) : MF + 1;
-  static constexpr int fb_lds = 65536 / (2 * MFP * (int)sizeof(T));
-  static constexpr int fb_cap = 256 / CPF;
-  static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
-  static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
-  static constexpr int THREADS = FB * CPF;
-};
-
-// Level operator, pass 1, by sibling families: the workgroup gathers the
-// (2k+1)^d node patch of each of its families once into LDS (index reads
-// coalesced over families), every lane computes one cell from LDS,
-// contributions of the 2^d siblings are combined with LDS atomics, and each
-// family writes its patch once into its node-major slots (pass 2 sums the
-// slots of a node over the families that contain it).
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamilyShape<DIM, K, T>::THREADS)) family_to_slots(
-    int64_t n_fam, const int32_t* __restrict__ famap, const int32_t* __restrict__ fslot,
-    const double* __restrict__ scale, double scale0, const T* __restrict__ x, T* __restrict__ E, Mats<T> m) {
-  using S = FamilyShape<DIM, K, T>;
-  constexpr int N = K + 1, M2 = S::M2, MF = S::MF, MFP = S::MFP, FB = S::FB, CPF = S::CPF;
-  constexpr int NP = DIM == 3 ? N * N * N : N * N;
-  __shared__ T sin[FB * MFP];
-  __shared__ T sout[FB * MFP];
-  const int64_t f0 = xcd_block() * FB;
-  const int tid = threadIdx.x;
-  // all index loads first, then all gathers, so the loads are in flight together
-  constexpr int ITER = (MF * FB + S::THREADS - 1) / S::THREADS;
-  int32_t gid[ITER];
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const int e = tid + it * S::THREADS;
-    const int q = e / FB, fl = e % FB;
-    gid[it] = (e < MF * FB && f0 + fl < n_fam) ? famap[(int64_t)q * n_fam + f0 + fl] : -1;
-  }
-  T val[ITER];
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) val[it] = gid[it] >= 0 ? x[gid[it]] : T(0);
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const int e = tid + it * S::THREADS;
-    if (e < MF * FB) {
-      const int q = e / FB, fl = e % FB;
-      sin[fl * MFP + q] = val[it];
-      sout[fl * MFP + q] = T(0);
-    }
-  }
-  __syncthreads();
-  const int fl = tid / CPF, cid = tid % CPF;
-  const int64_t f = f0 + fl;
-  if (f < n_fam) {
-    const int bx = (cid & 1) * K, by = ((cid >> 1) & 1) * K, bz = DIM == 3 ? ((cid >> 2) & 1) * K : 0;
-    T u[NP], v[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
-      u[j] = sin[fl * MFP + ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx)];
-    }
-    if (DIM == 3)
-      laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(v));
-    else
-      laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(v));
-    const T sc = T(scale ? scale[f * CPF + cid] : scale0);
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
-      atomicAdd(&sout[fl * MFP + ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx)], sc * v[j]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const int e = tid + it * S::THREADS;
-    const int q = e / FB, fl2 = e % FB;
-    gid[it] = (e < MF * FB && f0 + fl2 < n_fam) ? fslot[(int64_t)q * n_fam + f0 + fl2] : -1;
-  }
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const int e = tid + it * S::THREADS;
-    if (gid[it] >= 0) E[gid[it]] = sout[(e % FB) * MFP + e / FB];
-  }
 }
 
 // diagonal of the cell Laplacian, accumulated per node (FP64)
@@ -570,148 +424,6 @@ __global__ void make_dinv(int64_t n, const double* __restrict__ diag, const uint
   if (i < n) dinv[i] = flags[i] == 0 ? T(1.0 / diag[i]) : T(0);
 }
 
-// ------------------------------------------------------------------ transfer
-// Family of 2^d siblings: (2k+1)^d fine nodes, parent (k+1)^d nodes.
-// Prolongation x_f += E^{x d} x_c on the nodes this family owns; each fine
-// node is owned by exactly one family, so the global operator is applied
-// once per node without atomics.  All loads are unconditional (the family
-// map is valid for every node) so that they are issued together.
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) prolongate(
-    int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
-    const int32_t* __restrict__ parent, int64_t n_pcells, const int32_t* __restrict__ pmap,
-    const T* __restrict__ xc, T* __restrict__ xf, Mats<T> m) {
-  constexpr int N = K + 1, M2 = 2 * K + 1;
-  constexpr int NP = DIM == 3 ? N * N * N : N * N;
-  constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
-  constexpr int NW = (MF + 31) / 32;
-  constexpr int NZ = DIM == 3 ? N : 1;
-  const int64_t f = xcd_tid();
-  if (f >= n_fam) return;
-  const int64_t p = parent[f];
-  T u[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) u[j] = xc[pmap[(int64_t)j * n_pcells + p]];
-  // x: N -> M2
-  T a[NZ * N * M2];
-#pragma unroll
-  for (int r = 0; r < NZ * N; ++r)
-#pragma unroll
-    for (int i = 0; i < M2; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) s += m.E[i * N + j] * u[r * N + j];
-      a[r * M2 + i] = s;
-    }
-  // y: N -> M2 over rows (z, x)
-  T b[NZ * M2 * M2];
-#pragma unroll
-  for (int z = 0; z < NZ; ++z)
-#pragma unroll
-    for (int x = 0; x < M2; ++x)
-#pragma unroll
-      for (int i = 0; i < M2; ++i) {
-        T s = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) s += m.E[i * N + j] * a[(z * N + j) * M2 + x];
-        b[(z * M2 + i) * M2 + x] = s;
-      }
-  uint32_t ow[NW];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) ow[w] = own[(int64_t)w * n_fam + f];
-  constexpr int NZF = DIM == 3 ? M2 : 1;
-#pragma unroll
-  for (int iz = 0; iz < NZF; ++iz) {
-    int32_t gid[M2 * M2];
-    T old[M2 * M2];
-#pragma unroll
-    for (int yx = 0; yx < M2 * M2; ++yx) gid[yx] = famap[(int64_t)(iz * M2 * M2 + yx) * n_fam + f];
-#pragma unroll
-    for (int yx = 0; yx < M2 * M2; ++yx) old[yx] = xf[gid[yx]];
-#pragma unroll
-    for (int yx = 0; yx < M2 * M2; ++yx) {
-      const int q = iz * M2 * M2 + yx;
-      T s;
-      if (DIM == 3) {
-        s = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) s += m.E[iz * N + j] * b[j * M2 * M2 + yx];
-      } else {
-        s = b[yx];
-      }
-      if ((ow[q / 32] >> (q % 32)) & 1u) xf[gid[yx]] = old[yx] + s;
-    }
-  }
-}
-
-// Restriction (R = P^T) of the residual r (zero on Dirichlet rows) on the
-// nodes this family owns, contracted to the parent's nodes and written to
-// the parent-node slots of the coarse level (summed by a seg_* kernel).
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) restrict_to_slots(
-    int64_t n_fam, const int32_t* __restrict__ famap, const uint32_t* __restrict__ own,
-    const T* __restrict__ r, const int32_t* __restrict__ rslot, T* __restrict__ E, Mats<T> m) {
-  constexpr int N = K + 1, M2 = 2 * K + 1;
-  constexpr int MF = DIM == 3 ? M2 * M2 * M2 : M2 * M2;
-  constexpr int NW = (MF + 31) / 32;
-  constexpr int NZ = DIM == 3 ? M2 : 1;
-  const int64_t f = xcd_tid();
-  if (f >= n_fam) return;
-  uint32_t ow[NW];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) ow[w] = own[(int64_t)w * n_fam + f];
-  // x contraction while loading: a[(z, y), J] = sum_i E[i][J] r[z, y, i]
-  T a[NZ * M2 * N];
-#pragma unroll
-  for (int zy = 0; zy < NZ * M2; ++zy) {
-    int32_t gid[M2];
-    T rv[M2];
-#pragma unroll
-    for (int i = 0; i < M2; ++i) gid[i] = famap[(int64_t)(zy * M2 + i) * n_fam + f];
-#pragma unroll
-    for (int i = 0; i < M2; ++i) rv[i] = r[gid[i]];
-#pragma unroll
-    for (int i = 0; i < M2; ++i) {
-      const int q = zy * M2 + i;
-      if (!((ow[q / 32] >> (q % 32)) & 1u)) rv[i] = T(0);
-    }
-#pragma unroll
-    for (int J = 0; J < N; ++J) {
-      T s = 0;
-#pragma unroll
-      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * rv[i];
-      a[zy * N + J] = s;
-    }
-  }
-  // y contraction
-  T b[NZ * N * N];
-#pragma unroll
-  for (int z = 0; z < NZ; ++z)
-#pragma unroll
-    for (int x = 0; x < N; ++x)
-#pragma unroll
-      for (int J = 0; J < N; ++J) {
-        T s = 0;
-#pragma unroll
-        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * a[(z * M2 + i) * N + x];
-        b[(z * N + J) * N + x] = s;
-      }
-  if (DIM == 2) {
-#pragma unroll
-    for (int j = 0; j < N * N; ++j) E[rslot[(int64_t)j * n_fam + f]] = b[j];
-  } else {
-#pragma unroll
-    for (int J = 0; J < N; ++J)
-#pragma unroll
-      for (int yx = 0; yx < N * N; ++yx) {
-        T s = 0;
-#pragma unroll
-        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * b[i * N * N + yx];
-        E[rslot[(int64_t)(J * N * N + yx) * n_fam + f]] = s;
-      }
-  }
-}
-
 // ------------------------------------------------------------------ vectors
 template <typename T>
 __global__ void fill(int64_t n, T* __restrict__ p, T v) {
@@ -719,10 +431,11 @@ __global__ void fill(int64_t n, T* __restrict__ p, T v) {
     p[i] = v;
 }
 
+// t = x on the rows whose flag is want, 0 elsewhere (t may alias x)
 template <typename T>
-__global__ void zero_list(int64_t n, const int32_t* __restrict__ list, T* __restrict__ p) {
+__global__ void mask_rows(int64_t n, const uint8_t* __restrict__ flags, int want, const T* x, T* t) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[list[i]] = T(0);
+  if (i < n) t[i] = flags[i] == want ? x[i] : T(0);
 }
 
 // Chebyshev step (Sec. 4.1 smoother): d = c1 d + c2 D^{-1} (g - t); x += d;
@@ -789,19 +502,6 @@ __device__ __forceinline__ T seg_sum(const int32_t* __restrict__ off, const T* _
   }
   for (; p < e; ++p) y += E[p];
   return y;
-}
-
-// Chebyshev step on the operator result: d = c1 d + c2 D^{-1} (g - A x);
-// x += d.  Rows that are not smoothed have D^{-1} = 0.
-template <typename T>
-__global__ void seg_cheb(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E, T* __restrict__ x,
-                         T* __restrict__ d, const T* __restrict__ g, const T* __restrict__ dinv, T c1, T c2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const T y = seg_sum(off, E, i);
-  const T v = c1 * d[i] + c2 * dinv[i] * (g[i] - y);
-  d[i] = v;
-  x[i] += v;
 }
 
 // residual r = g - A x on free rows, 0 on Dirichlet rows (use_e = 0: A x = 0)
@@ -928,12 +628,12 @@ __global__ void copy_vec(int64_t n, const double* __restrict__ a, double* __rest
 }
 
 // eigenvalue-estimate helpers (FP64, level vectors)
-__global__ void eig_init(int64_t n, const uint8_t* __restrict__ flags, const double* __restrict__ dinv,
-                         double* __restrict__ r, double* __restrict__ z, double* __restrict__ p) {
+// start vector r (set on the host, zero off the S rows): z = p = D^{-1} r
+__global__ void eig_init(int64_t n, const double* __restrict__ dinv, const double* __restrict__ r,
+                         double* __restrict__ z, double* __restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double v = flags[i] == 0 ? double(i % 12) - 5.5 : 0.0;
-  r[i] = v;
+  const double v = r[i];
   z[i] = dinv[i] * v;
   p[i] = dinv[i] * v;
 }

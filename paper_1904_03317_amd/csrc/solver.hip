@@ -6,6 +6,7 @@
 #include <mutex>
 
 #define GMG_SOLVER_TU
+#include "famkernels.hpp"
 #include "kernels.hpp"
 #include "problem.hpp"
 
@@ -50,11 +51,50 @@ static void fill_dev(T* p, int64_t n, T v, hipStream_t s) {
 
 void set_constant(double* p, int64_t n, double v, hipStream_t s) { fill_dev(p, n, v, s); }
 
-// Pass 1 of the level operator: one lane per cell (variant 1) or sibling
-// family patches staged in LDS (variant 2, auto): on the 1.2M-cell finest
-// level of the 2e7-DoF Fichera Q2 mesh the family form measured 2.3x faster
-// in FP64.
-static bool family_variant(const Problem& P) { return P.opt.op_variant != 1; }
+template <typename T>
+static const LevelOps<T>& ops(Problem& P);
+template <>
+const LevelOps<float>& ops<float>(Problem& P) { return P.kt->f32; }
+template <>
+const LevelOps<double>& ops<double>(Problem& P) { return P.kt->f64; }
+template <typename T>
+static const MatsH<T>& mats(Problem& P);
+template <>
+const MatsH<float>& mats<float>(Problem& P) { return P.m32; }
+template <>
+const MatsH<double>& mats<double>(Problem& P) { return P.m64; }
+
+// y = A_l x on every row of level l (device layout of the level)
+template <typename T>
+static void level_apply(Problem& P, int l, const T* x, T* y, hipStream_t s) {
+  DevLevel& V = P.lv[l];
+  const int64_t n = V.v.n_dofs;
+  const LevelOps<T>& op = ops<T>(P);
+  T* E = (T*)P.E;
+  if (l == 0) {
+    op.cell_e(V.v, x, E, mats<T>(P), s);
+    hipLaunchKernelGGL(dev::seg_plain<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, (const T*)E, y);
+  } else {
+    dev::Epi<T> ep;
+    ep.y = y;
+    op.op(V.v, dev::kEpiPlain, x, ep, E, mats<T>(P), s);
+    op.sum(V.v, dev::kEpiPlain, E, ep, s);
+  }
+}
+
+// diagonal of A_l (FP64, device layout)
+static void level_diag(Problem& P, int l, double* diag, hipStream_t s) {
+  DevLevel& V = P.lv[l];
+  if (l == 0) {
+    fill_dev(diag, V.v.n_dofs, 0.0, s);
+    P.kt->diag0(V.v, diag, P.m64, s);
+  } else {
+    dev::Epi<double> ep;
+    ep.y = diag;
+    P.kt->f64.op(V.v, dev::kEpiDiag, nullptr, ep, P.E, P.m64, s);
+    P.kt->f64.sum(V.v, dev::kEpiDiag, P.E, ep, s);
+  }
+}
 
 // ---------------------------------------------------------------- workspace
 namespace {
@@ -80,31 +120,22 @@ size_t plan_workspace(Problem& P, char* base) {
   int64_t off = 0;
   int64_t e_max = 0;
   P.max_level_dofs = 0;
+  const int nj = M.dim == 3 ? 27 : 9, cpf = 1 << M.dim;
   for (int l = 0; l <= L; ++l) {
     LevelData& D = M.levels[l];
     DevLevel& V = P.lv[l];
     V.v.n_cells = D.n_cells;
     V.v.n_dofs = D.n_dofs;
     V.v.n_fam = D.n_fam;
-    V.v.n_edge = (int64_t)D.edge_cells.size();
     V.off = off;
     off += D.n_dofs;
     V.n_I = (int64_t)D.ilist.size();
     V.n_S = 0;
     for (auto f : D.flags) V.n_S += f == kFlagS;
     P.max_level_dofs = std::max(P.max_level_dofs, D.n_dofs);
-    V.v.cmap = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
-    const bool fam = l >= 1 && family_variant(P);
-    V.v.slot = fam ? nullptr : pl.take<int32_t>(size_t(D.n_cells) * M.npc);
-    V.v.fslot = fam ? pl.take<int32_t>(size_t(D.n_fam) * M.mf) : nullptr;
-    V.v.soff = pl.take<int32_t>(D.n_dofs + 1);
-    V.v.roff = l < L ? pl.take<int32_t>(D.n_dofs + 1) : nullptr;
-    e_max = std::max<int64_t>(e_max, D.n_cells * M.npc);
-    e_max = std::max<int64_t>(e_max, D.n_fam * M.npc);
     bool uniform = true;
     for (auto c : D.coeff) uniform = uniform && (c == D.coeff[0]);
-    double h = std::ldexp(1.0, -l);
-    double hd = M.dim == 3 ? h : 1.0;
+    const double hd = M.dim == 3 ? std::ldexp(1.0, -l) : 1.0;
     if (uniform) {
       V.v.scale = nullptr;
       V.v.scale0 = (D.coeff.empty() ? 1.0 : D.coeff[0]) * hd;
@@ -112,13 +143,30 @@ size_t plan_workspace(Problem& P, char* base) {
       V.v.scale = pl.take<double>(D.n_cells);
     }
     V.v.flags = pl.take<uint8_t>(D.n_dofs);
-    V.v.edge = pl.take<int32_t>(D.edge_cells.size());
     V.ilist = pl.take<int32_t>(D.ilist.size());
-    if (l >= 1) {
-      V.v.famap = pl.take<int32_t>(size_t(D.n_fam) * M.mf);
-      V.v.own = pl.take<uint32_t>(size_t(D.n_fam) * M.own_words);
+    if (l == 0) {
+      V.v.cmap = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
+      V.v.slot = pl.take<int32_t>(size_t(D.n_cells) * M.npc);
+      V.v.soff = pl.take<int32_t>(D.n_dofs + 1);
+      V.v.roff = L >= 1 ? pl.take<int32_t>(D.n_dofs + 1) : nullptr;
+      e_max = std::max<int64_t>(e_max, D.n_cells * M.npc);
+    } else {
+      const LevelLayout& Y = M.layouts[l];
+      for (int r = 0; r < 5; ++r) {
+        V.v.sec[r] = Y.sec[r];
+        V.v.shn[r] = Y.shn[r];
+        V.v.entoff[r] = Y.entoff[r];
+        V.v.eoff[r] = Y.eoff[r];
+      }
+      V.v.gbase = pl.take<int32_t>(size_t(D.n_fam) * nj);
+      V.v.own = pl.take<uint32_t>(D.n_fam);
+      V.v.excl = pl.take<uint32_t>(D.n_fam);
+      V.v.pmask = pl.take<uint8_t>(Y.n_ent);
       V.v.parent = pl.take<int32_t>(D.n_fam);
-      V.v.rslot = pl.take<int32_t>(size_t(D.n_fam) * M.npc);
+      V.v.child = l < L ? pl.take<int32_t>(size_t(D.n_fam) * cpf) : nullptr;
+      V.v.rslot = l == 1 ? pl.take<int32_t>(size_t(D.n_fam) * M.npc) : nullptr;
+      e_max = std::max<int64_t>(e_max, Y.n_slots);
+      if (l == 1) e_max = std::max<int64_t>(e_max, D.n_fam * M.npc);
     }
   }
   P.n_total = off;
@@ -246,16 +294,25 @@ double estimate_lambda(Problem& P, int l, hipStream_t s) {
   double* p = P.eig + 3 * n;
   double* q = P.eig + 4 * n;
   double* diag = P.eig + 5 * n;
-  fill_dev(diag, n, 0.0, s);
-  P.kt->diag(V.v, diag, P.m64, s);
+  level_diag(P, l, diag, s);
   hipLaunchKernelGGL(dev::make_dinv<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags, dinv);
-  hipLaunchKernelGGL(dev::eig_init, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.flags, dinv, r, z, p);
+  {
+    // start vector (i mod 12) - 5.5 on the S rows, i the level DoF id
+    const LevelData& D = P.maps.levels[l];
+    const std::vector<int32_t>& perm = P.maps.layouts[l].perm;
+    std::vector<double> r0(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      if (D.flags[i] == kFlagS) r0[perm[i]] = double(i % 12) - 5.5;
+    h2d(r, r0, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  hipLaunchKernelGGL(dev::eig_init, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, (const double*)dinv,
+                     (const double*)r, z, p);
   double rho = dot_host(P, r, z, n, s);
   std::vector<double> alphas, betas;
   for (int j = 0; j < iters; ++j) {
     if (!(rho > 0.0)) break;
-    P.kt->f64.apply_e(V.v, p, P.E, P.m64, s);
-    hipLaunchKernelGGL(dev::seg_plain<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, P.E, q);
+    level_apply<double>(P, l, p, q, s);
     double pq = dot_host(P, p, q, n, s);
     if (!(pq > 0.0)) break;
     double alpha = rho / pq;
@@ -361,50 +418,56 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
   }
   const int L = (int)M.levels.size() - 1;
   const bool f32 = P.opt.mg_precision == 32;
+  const int nj = M.dim == 3 ? 27 : 9, cpf = 1 << M.dim;
   for (int l = 0; l <= L; ++l) {
     LevelData& D = M.levels[l];
     DevLevel& V = P.lv[l];
-    h2d(V.v.cmap, soa(D.cellmap, D.n_cells, M.npc), s);
-    {
-      // operator slots: per cell on level 0, per (family, patch node) above
-      std::vector<int32_t> off, sl;
-      if (!V.v.fslot) {
-        build_slots(D.cellmap, D.n_cells, M.npc, D.n_dofs, off, sl);
-        h2d(V.v.slot, sl, s);
-      } else {
-        build_slots(D.famap, D.n_fam, M.mf, D.n_dofs, off, sl);
-        h2d(V.v.fslot, sl, s);
-      }
-      h2d(V.v.soff, off, s);
-      HIPCHECK(hipStreamSynchronize(s));
-    }
-    if (l >= 1) {
-      // restriction slots: (family, parent node) -> coarse node-major entries
-      const LevelData& Pl = M.levels[l - 1];
-      std::vector<int32_t> pm(size_t(D.n_fam) * M.npc);
-      for (int64_t f = 0; f < D.n_fam; ++f)
-        for (int j = 0; j < M.npc; ++j) pm[size_t(f) * M.npc + j] = Pl.cellmap[size_t(D.parent[f]) * M.npc + j];
-      std::vector<int32_t> off, sl;
-      build_slots(pm, D.n_fam, M.npc, Pl.n_dofs, off, sl);
-      h2d(V.v.rslot, sl, s);
-      h2d(P.lv[l - 1].v.roff, off, s);
-      HIPCHECK(hipStreamSynchronize(s));
-    }
     if (V.v.scale) {
       std::vector<double> sc(D.n_cells);
       double hd = M.dim == 3 ? std::ldexp(1.0, -l) : 1.0;
       for (int64_t c = 0; c < D.n_cells; ++c) sc[c] = D.coeff[c] * hd;
       h2d(V.v.scale, sc, s);
     }
-    h2d(V.v.flags, D.flags, s);
-    h2d(V.v.edge, D.edge_cells, s);
-    h2d(V.ilist, D.ilist, s);
-    if (l >= 1) {
-      h2d(V.v.famap, soa(D.famap, D.n_fam, M.mf), s);
-      h2d(V.v.own, soa(D.own, D.n_fam, M.own_words), s);
-      h2d(V.v.parent, D.parent, s);
+    if (l == 0) {
+      h2d(V.v.cmap, soa(D.cellmap, D.n_cells, M.npc), s);
+      std::vector<int32_t> off, sl;
+      build_slots(D.cellmap, D.n_cells, M.npc, D.n_dofs, off, sl);
+      h2d(V.v.slot, sl, s);
+      h2d(V.v.soff, off, s);
+      h2d(V.v.flags, D.flags, s);
+      h2d(V.ilist, D.ilist, s);
+      HIPCHECK(hipStreamSynchronize(s));
+      continue;
     }
-    HIPCHECK(hipStreamSynchronize(s));
+    // entity layout: flags and I-node list in device numbering
+    const LevelLayout& Y = M.layouts[l];
+    {
+      std::vector<uint8_t> fl(D.n_dofs);
+      for (int64_t i = 0; i < D.n_dofs; ++i) fl[Y.perm[i]] = D.flags[i];
+      std::vector<int32_t> il(D.ilist.size());
+      for (size_t i = 0; i < il.size(); ++i) il[i] = Y.perm[D.ilist[i]];
+      h2d(V.v.flags, fl, s);
+      h2d(V.ilist, il, s);
+      h2d(V.v.gbase, soa(Y.gbase, D.n_fam, nj), s);
+      h2d(V.v.own, Y.own, s);
+      h2d(V.v.excl, Y.excl, s);
+      h2d(V.v.pmask, Y.pmask, s);
+      h2d(V.v.parent, D.parent, s);
+      if (V.v.child) h2d(V.v.child, soa(Y.child, D.n_fam, cpf), s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    if (l == 1) {
+      // restriction into level 0: (family, parent node) -> level-0 node-major slots
+      const LevelData& Pl = M.levels[0];
+      std::vector<int32_t> pm(size_t(D.n_fam) * M.npc);
+      for (int64_t f = 0; f < D.n_fam; ++f)
+        for (int j = 0; j < M.npc; ++j) pm[size_t(f) * M.npc + j] = Pl.cellmap[size_t(D.parent[f]) * M.npc + j];
+      std::vector<int32_t> off, sl;
+      build_slots(pm, D.n_fam, M.npc, Pl.n_dofs, off, sl);
+      h2d(V.v.rslot, sl, s);
+      h2d(P.lv[0].v.roff, off, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
   }
   {
     const std::vector<int32_t>& cm = M.leaf_cellmap_parent;
@@ -428,7 +491,9 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     h2d(P.leaf.mscale, ms, s);
     std::vector<int32_t> cp(M.n_dofs);
     for (int64_t i = 0; i < M.n_dofs; ++i) {
-      int64_t g = P.lv[M.copy_level[i]].off + M.copy_index[i];
+      const int l = M.copy_level[i];
+      const int32_t li = l >= 1 ? M.layouts[l].perm[M.copy_index[i]] : M.copy_index[i];
+      int64_t g = P.lv[l].off + li;
       if (g > INT32_MAX) fail(GMG_E_INVAL, "level vectors exceed 2^31 entries");
       cp[i] = (int32_t)g;
     }
@@ -450,8 +515,7 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     DevLevel& V = P.lv[l];
     const int64_t n = V.v.n_dofs;
     double* diag = P.eig + 5 * n;
-    fill_dev(diag, n, 0.0, s);
-    P.kt->diag(V.v, diag, P.m64, s);
+    level_diag(P, l, diag, s);
     if (f32)
       hipLaunchKernelGGL(dev::make_dinv<float>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags,
                          (float*)P.ldinv + V.off);
@@ -479,18 +543,6 @@ void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s
   hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.dir, y);
 }
 
-template <typename T>
-static const LevelOps<T>& ops(Problem& P);
-template <>
-const LevelOps<float>& ops<float>(Problem& P) { return P.kt->f32; }
-template <>
-const LevelOps<double>& ops<double>(Problem& P) { return P.kt->f64; }
-template <typename T>
-static const MatsH<T>& mats(Problem& P);
-template <>
-const MatsH<float>& mats<float>(Problem& P) { return P.m32; }
-template <>
-const MatsH<double>& mats<double>(Problem& P) { return P.m64; }
 
 struct Cheb {
   double theta, delta, sigma;
@@ -504,18 +556,24 @@ static Cheb cheb_of(const Problem& P, int l) {
   return c;
 }
 
-// Chebyshev smoothing steps on level l (Sec. 4.1 smoother): steps
+// Chebyshev smoothing steps on level l >= 1 (Sec. 4.1 smoother): steps
 // first..m of the semi-iteration on D^{-1} A^S, each an operator application
-// (two passes) whose second pass performs the vector update.  Pre-smoothing
-// enters with step 1 already done (from x = 0, no operator needed);
-// post-smoothing starts at step 1 from the prolongated x, whose interface
-// values stay fixed so that every residual includes A^{SI} x^I.
+// whose two passes perform the vector update as their epilogue.
+// Pre-smoothing enters with step 1 already done (from x = 0, no operator
+// needed); post-smoothing starts at step 1 from the prolongated x, whose
+// interface values stay fixed (D^{-1} = 0 there) so that every residual
+// includes A^{SI} x^I.
 template <typename T>
 static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
   DevLevel& V = P.lv[l];
-  const int64_t n = V.v.n_dofs, o = V.off;
-  T *X = (T*)P.lx + o, *G = (T*)P.lg + o, *Dd = (T*)P.ld + o, *Di = (T*)P.ldinv + o;
+  const int64_t o = V.off;
   T* E = (T*)P.E;
+  dev::Epi<T> ep;
+  ep.x = (T*)P.lx + o;
+  ep.d = (T*)P.ld + o;
+  ep.g = (T*)P.lg + o;
+  ep.dinv = (const T*)P.ldinv + o;
+  ep.flags = V.v.flags;
   const Cheb c = cheb_of(P, l);
   double rho_old = 1.0 / c.sigma;
   const LevelOps<T>& op = ops<T>(P);
@@ -528,9 +586,10 @@ static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
       rho_old = rho;
     }
     if (j < first) continue;
-    op.apply_e(V.v, X, E, mats<T>(P), s);
-    hipLaunchKernelGGL(dev::seg_cheb<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, E, X, Dd, G, Di,
-                       T(c1), T(c2));
+    ep.c1 = T(c1);
+    ep.c2 = T(c2);
+    op.op(V.v, dev::kEpiCheb, ep.x, ep, E, mats<T>(P), s);
+    op.sum(V.v, dev::kEpiCheb, E, ep, s);
   }
 }
 
@@ -558,17 +617,37 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
   for (int l = L; l >= 1; --l) {
     DevLevel& V = P.lv[l];
     const int64_t n = V.v.n_dofs;
+    // residual r = g - A x on S and I rows (0 on D rows)
     if (V.n_S > 0) {
       smooth_steps<T>(P, l, 2, s);
-      op.apply_e(V.v, X + V.off, E, mats<T>(P), s);
+      dev::Epi<T> ep;
+      ep.y = R + V.off;
+      ep.g = G + V.off;
+      ep.flags = V.v.flags;
+      op.op(V.v, dev::kEpiResid, X + V.off, ep, E, mats<T>(P), s);
+      op.sum(V.v, dev::kEpiResid, E, ep, s);
+    } else {
+      hipLaunchKernelGGL(dev::seg_residual<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, (const int32_t*)nullptr,
+                         (const T*)E, G + V.off, V.v.flags, R + V.off, 0);
     }
-    hipLaunchKernelGGL(dev::seg_residual<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, E, G + V.off,
-                       V.v.flags, R + V.off, V.n_S > 0 ? 1 : 0);
-    op.restrict_e(V.v, R + V.off, E, mats<T>(P), s);
+    // restriction into level l-1 and its first smoothing step from x = 0
     DevLevel& W = P.lv[l - 1];
-    const double c2 = l - 1 >= 1 ? 1.0 / cheb_of(P, l - 1).theta : 0.0;
-    hipLaunchKernelGGL(dev::seg_restrict_start<T>, dim3(grid1(W.v.n_dofs)), dim3(dev::kBlock), 0, s, W.v.n_dofs,
-                       W.v.roff, E, G + W.off, X + W.off, Dd + W.off, Di + W.off, T(c2), l - 1 >= 1 ? 1 : 0);
+    if (l - 1 >= 1) {
+      dev::Epi<T> ep;
+      ep.x = X + W.off;
+      ep.d = Dd + W.off;
+      ep.g = G + W.off;
+      ep.dinv = Di + W.off;
+      ep.flags = W.v.flags;
+      ep.c2 = T(1.0 / cheb_of(P, l - 1).theta);
+      ep.smooth = 1;
+      op.restrict_fc(V.v, W.v, R + V.off, ep, E, mats<T>(P), s);
+      op.sum(W.v, dev::kEpiRStart, E, ep, s);
+    } else {
+      op.restrict0(V.v, R + V.off, E, mats<T>(P), s);
+      hipLaunchKernelGGL(dev::seg_restrict_start<T>, dim3(grid1(W.v.n_dofs)), dim3(dev::kBlock), 0, s, W.v.n_dofs,
+                         W.v.roff, (const T*)E, G + W.off, X + W.off, Dd + W.off, Di + W.off, T(0), 0);
+    }
   }
   hipLaunchKernelGGL(dev::coarse_solve<T>, dim3(1), dim3(dev::kBlock), P.n0 * sizeof(double), s,
                      (int)P.lv[0].v.n_dofs, P.n0, P.ainv, P.cidx, G + P.lv[0].off, X + P.lv[0].off);
@@ -614,29 +693,32 @@ static void precondition(Problem& P, hipStream_t s) {
   HIPCHECK(hipGraphLaunch(P.graph, s));
 }
 
+// level operator test hook in the device layout of the level: variant 0
+// y = A_l x; variant 1 y = A^{SI} x^I on S rows, 0 elsewhere (the input
+// restricted to I rows through the level's temporary vector)
+template <typename T>
+static void level_hook(Problem& P, int l, int variant, const T* x, T* y, hipStream_t s) {
+  DevLevel& V = P.lv[l];
+  const int64_t n = V.v.n_dofs;
+  if (variant == 0) {
+    level_apply<T>(P, l, x, y, s);
+    return;
+  }
+  T* t = (T*)P.lt + V.off;
+  hipLaunchKernelGGL(dev::mask_rows<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.flags, 1, x, t);
+  level_apply<T>(P, l, (const T*)t, y, s);
+  hipLaunchKernelGGL(dev::mask_rows<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.flags, 0, (const T*)y, y);
+  fill_dev(t, n, T(0), s);
+}
+
 void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hipStream_t s) {
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
   if (l < 0 || l >= (int)P.lv.size()) fail(GMG_E_INVAL, "level out of range");
-  DevLevel& V = P.lv[l];
-  const int64_t n = V.v.n_dofs;
-  if (P.opt.mg_precision == 32) {
-    if (variant == 0) {
-      P.kt->f32.apply_e(V.v, (const float*)x, (float*)P.E, P.m32, s);
-      hipLaunchKernelGGL(dev::seg_plain<float>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, (const float*)P.E,
-                         (float*)y);
-    } else {
-      fill_dev((float*)y, n, 0.0f, s);
-      P.kt->f32.edge(V.v, (const float*)x, (float*)y, 1.0f, P.m32, s);
-    }
-  } else {
-    if (variant == 0) {
-      P.kt->f64.apply_e(V.v, (const double*)x, P.E, P.m64, s);
-      hipLaunchKernelGGL(dev::seg_plain<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, V.v.soff, P.E, (double*)y);
-    } else {
-      fill_dev((double*)y, n, 0.0, s);
-      P.kt->f64.edge(V.v, (const double*)x, (double*)y, 1.0, P.m64, s);
-    }
-  }
+  if (variant != 0 && variant != 1) fail(GMG_E_INVAL, "variant must be 0 or 1");
+  if (P.opt.mg_precision == 32)
+    level_hook<float>(P, l, variant, (const float*)x, (float*)y, s);
+  else
+    level_hook<double>(P, l, variant, (const double*)x, (double*)y, s);
   HIPCHECK(hipGetLastError());
 }
 

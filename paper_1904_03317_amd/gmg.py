@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgmg.so")
 GMG_OK, GMG_NOT_CONVERGED = 0, 1
 ARR = dict(LEAF_CELLMAP=1, LEAF_DIRICHLET=2, CON_OFFSETS=3, CON_MASTERS=4, CON_WEIGHTS=5,
            COPY_LEVEL=6, COPY_INDEX=7, LEVEL_CELLMAP=8, LEVEL_FLAGS=9, LEVEL_PARENT=10,
-           LEAF_CELLMAP_PARENT=11, LEAF_MASK=12)
+           LEAF_CELLMAP_PARENT=11, LEAF_MASK=12, LEVEL_PERM=13)
 _ARR_DTYPE = {1: np.int32, 2: np.uint8, 3: np.int64, 4: np.int32, 5: np.float64, 6: np.int8,
-              7: np.int32, 8: np.int32, 9: np.uint8, 10: np.int32, 11: np.int32, 12: np.uint16}
+              7: np.int32, 8: np.int32, 9: np.uint8, 10: np.int32, 11: np.int32, 12: np.uint16,
+              13: np.int32}
 
 
 class gmg_options(C.Structure):
@@ -273,6 +274,8 @@ class Problem:
         _check(lib().gmg_apply_leaf(self.h, _ptr(x), _ptr(y), _stream(stream)))
 
     def apply_level(self, level, variant, x, y, stream=None):
+        """Level operator on level vectors in the device layout of the level
+        (x_dev[perm[i]] = x[i] with perm = array("LEVEL_PERM", level))."""
         _check(lib().gmg_apply_level(self.h, level, variant, _ptr(x), _ptr(y), _stream(stream)))
 
     def vcycle(self, r, z, stream=None):

@@ -31,6 +31,15 @@ def ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def array(P, which, level, dtype):
+    p, n = C.c_void_p(), C.c_int64()
+    check(L.gmg_problem_array(P, which, level, C.byref(p), C.byref(n)))
+    if n.value == 0:
+        return np.zeros(0, dtype)
+    buf = (C.c_char * (n.value * np.dtype(dtype).itemsize)).from_address(p.value)
+    return np.frombuffer(buf, dtype=dtype).copy()
+
+
 def aligned(nbytes):
     raw = np.zeros(nbytes + 512, np.uint8)
     off = (-raw.ctypes.data) % 256
@@ -86,16 +95,30 @@ def main():
     if "level" in checks:
         from oracle.assemble import level_coefficients, level_matrix
         lc = level_coefficients(op.disc, op.coeff)
-        worst = 0.0
+        worst = worst_edge = 0.0
         dt = np.float64 if prec == 64 else np.float32
         for l, lev in enumerate(op.disc.levels):
             A = level_matrix(op.disc, l, lc[l]).tocsr()
+            perm = array(P, gmg.ARR["LEVEL_PERM"], l, np.int32)
+            assert np.array_equal(np.sort(perm), np.arange(lev.n_dofs))
             x = rng.standard_normal(lev.n_dofs).astype(dt)
-            y = np.zeros(lev.n_dofs, dt)
-            check(L.gmg_apply_level(P, l, 0, ptr(x), ptr(y), None))
+            xd = np.zeros_like(x)
+            xd[perm] = x
+            yd = np.zeros(lev.n_dofs, dt)
+            check(L.gmg_apply_level(P, l, 0, ptr(xd), ptr(yd), None))
             ref = A @ x.astype(np.float64)
-            worst = max(worst, float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300)))
+            worst = max(worst, float(np.linalg.norm(yd[perm] - ref) / max(np.linalg.norm(ref), 1e-300)))
+            S, I = lev.flags == 0, lev.flags == 1
+            want = np.zeros(lev.n_dofs)
+            want[S] = A[S][:, I] @ x.astype(np.float64)[I]
+            check(L.gmg_apply_level(P, l, 1, ptr(xd), ptr(yd), None))
+            got = yd[perm].astype(np.float64)
+            if np.linalg.norm(want) > 0:
+                worst_edge = max(worst_edge, float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+            else:
+                worst_edge = max(worst_edge, float(np.abs(got).max()))
         out["level_rel"] = worst
+        out["edge_rel"] = worst_edge
     if "vcycle" in checks:
         r = rng.standard_normal(N)
         r[~op.free] = 0

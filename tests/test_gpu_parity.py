@@ -62,17 +62,22 @@ def test_level_operators(case, prec, tol):
     tdt = torch.float64 if prec == 64 else torch.float32
     for l, lev in enumerate(d.levels):
         A = level_matrix(d, l, lc[l]).tocsr()
+        # level vectors live in the device layout of the level
+        perm = P.array("LEVEL_PERM", l)
+        assert np.array_equal(np.sort(perm), np.arange(lev.n_dofs))
         x = rng.standard_normal(lev.n_dofs)
+        xd = np.zeros_like(x)
+        xd[perm] = x
         y = torch.zeros(lev.n_dofs, dtype=tdt, device="cuda")
-        P.apply_level(l, 0, dev(x, tdt), y)
+        P.apply_level(l, 0, dev(xd, tdt), y)
         xr = x.astype(np.float32).astype(np.float64) if prec == 32 else x
-        assert rel(host(y).astype(np.float64), A @ xr) <= tol, l
+        assert rel(host(y).astype(np.float64)[perm], A @ xr) <= tol, l
         # edge coupling A^{SI} x^I on S rows
         S, I = lev.flags == 0, lev.flags == 1
         want = np.zeros(lev.n_dofs)
         want[S] = A[S][:, I] @ xr[I]
-        P.apply_level(l, 1, dev(x, tdt), y)
-        got = host(y).astype(np.float64)
+        P.apply_level(l, 1, dev(xd, tdt), y)
+        got = host(y).astype(np.float64)[perm]
         if np.linalg.norm(want) > 0:
             assert rel(got, want) <= tol, l
         else:
