@@ -28,6 +28,42 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_03317_amd", "csrc",
+                             "famkernels.hpp")
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "level_kernels_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the level kernels from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy of known
+    size); empty when the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return {}
+    return rec if rec.get("kernel_source_sha256") == sha else {}
+
+
+def roofline(r, traffic):
+    """Dominant unit of the solve: one Chebyshev step on the largest level
+    (pass 1 + pass 2), algorithmic bytes = read x, d, g, D^-1 and write x, d;
+    beside it the operator apply y = A x (read x, write y)."""
+    nl, esz = r["level_dofs"], r["esz"]
+    a = 6 * esz * nl / r["t_cheb"] / 1e9
+    a_apply = 2 * esz * nl / r["t_apply"] / 1e9
+    t_bytes = traffic.get("cheb_bytes_per_launch") if traffic else None
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+            "traffic": t_bytes,
+            "kernel": f"Chebyshev step on level {r['lmax']} ({nl} DoFs, {r['level_cells']} cells): "
+                      f"fam_op + fam_sum, {6 * esz} B/DoF algorithmic",
+            "t_launch_us": r["t_cheb"] * 1e6,
+            "apply": {"achieved": a_apply, "frac": a_apply / HBM_PEAK_GBS, "t_launch_us": r["t_apply"] * 1e6,
+                      "bytes_per_dof": 2 * esz,
+                      "traffic": traffic.get("apply_bytes_per_launch") if traffic else None}}
+
+
 def cpu_baseline(g_sample=2, min_seconds=12.0):
     """The oracle (plain numpy/scipy, FP64, one thread) on the same recipe
     at a reduced number of global refinements: DoFs/s of its CG solve,
@@ -199,24 +235,29 @@ def main():
         x = torch.randn(nl, dtype=tdt, device="cuda")
         y = torch.zeros(nl, dtype=tdt, device="cuda")
         stream = torch.cuda.current_stream()
-        for _ in range(3):
-            P.apply_level(lmax, 0, x, y)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record(stream)
-        for _ in range(reps):
-            P.apply_level(lmax, 0, x, y)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_apply = e0.elapsed_time(e1) / reps * 1e-3
-        log(f"  level {lmax} operator: {t_apply * 1e6:.1f} us ({nl} DoFs)")
+
+        def timed(variant, reps=20):
+            for _ in range(3):
+                P.apply_level(lmax, variant, x, y)
+            e0.record(stream)
+            for _ in range(reps):
+                P.apply_level(lmax, variant, x, y)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps * 1e-3
+
+        # y = A x (operator apply) and one Chebyshev step of the smoother
+        # (the solve's dominant unit), each = pass 1 fam_op + pass 2 fam_sum
+        t_apply = timed(0)
+        t_cheb = timed(2)
+        log(f"  level {lmax} ({nl} DoFs): operator {t_apply * 1e6:.1f} us, Chebyshev step {t_cheb * 1e6:.1f} us")
         esz = 8 if prec == 64 else 4
-        alg_bytes = 2 * esz * nl
         results[prec] = dict(N=N, levels=info.n_levels, its=its, res=float(h[-1]), status=st,
                              ms=wall / args.steps * 1e3, dev_ms=dev_t / args.steps * 1e3,
                              vcycle_ms=vc_t / max(n_vc, 1) * 1e3, lmax=lmax, level_dofs=nl,
-                             level_cells=int(info.level_cells[lmax]), t_apply=t_apply,
-                             alg_bytes=alg_bytes, maps_s=t_maps, bind_s=t_bind, u=u.cpu().numpy())
+                             level_cells=int(info.level_cells[lmax]), t_apply=t_apply, t_cheb=t_cheb,
+                             esz=esz, maps_s=t_maps, bind_s=t_bind, u=u.cpu().numpy())
         P.close()
         del f, x, y
         torch.cuda.empty_cache()
@@ -242,22 +283,16 @@ def main():
                    "final_rel_residual": r64["res"], "vcycle_ms": r64["vcycle_ms"],
                    "setup_maps_s": r64["maps_s"], "setup_device_s": r64["bind_s"]},
     }
-    a = r64["alg_bytes"] / r64["t_apply"] / 1e9
-    out["roofline"] = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": a / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": f"level operator y = A x FP64 (fam_op + fam_sum), level {r64['lmax']} "
-                                 f"({r64['level_dofs']} DoFs, {r64['level_cells']} cells), 16 B/DoF algorithmic",
-                       "t_launch_us": r64["t_apply"] * 1e6}
+    traffic = measured_traffic()
+    out["roofline"] = roofline(r64, traffic.get("fp64"))
     if 32 in results:
         r32 = results[32]
-        a32 = r32["alg_bytes"] / r32["t_apply"] / 1e9
         d = float(np.linalg.norm(r32["u"] - r64["u"]) / np.linalg.norm(r64["u"]))
         out["fp32_mg"] = {"value": r32["N"] / (r32["ms"] * 1e-3), "unit": "DoFs/s", "ms_per_step": r32["ms"],
                           "cg_iterations": r32["its"], "final_rel_residual": r32["res"],
                           "vcycle_ms": r32["vcycle_ms"], "rel_diff_vs_fp64_mg": d,
                           "speedup_vs_fp64_mg": r64["ms"] / r32["ms"],
-                          "roofline_apply": {"achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                             "frac": a32 / HBM_PEAK_GBS, "t_launch_us": r32["t_apply"] * 1e6}}
+                          "roofline": roofline(r32, traffic.get("fp32"))}
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
         out["serve"] = serve_leg(args.serve)

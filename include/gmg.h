@@ -206,6 +206,8 @@ int gmg_solve_rhs(gmg_problem p, const double* d_b, double* d_u, int32_t* iterat
  *     (rows of S nodes give A^S x^S when x is zero on I and D nodes);
  *   variant 1 (edge): y^S = A^{SI} x^I: input restricted to I nodes, output
  *     to S rows, other rows 0;
+ *   variant 2 (timing): one Chebyshev smoothing step (Sec. 4.1) on the
+ *     level's V-cycle work vectors, levels >= 1; d_in and d_out unused;
  * one V-cycle z = B r (FP64 in and out, [n_dofs]). */
 int gmg_apply_leaf(gmg_problem p, const double* d_in, double* d_out, hipStream_t stream);
 int gmg_apply_level(gmg_problem p, int level, int variant, const void* d_in, void* d_out,

@@ -304,7 +304,7 @@ int gmg_apply_leaf(gmg_problem p, const double* x, double* y, hipStream_t s) {
 int gmg_apply_level(gmg_problem p, int level, int variant, const void* x, void* y, hipStream_t s) {
   return guard([&] {
     REQUIRE(p && x && y, "null argument");
-    REQUIRE(variant == 0 || variant == 1, "variant must be 0 or 1");
+    REQUIRE(variant >= 0 && variant <= 2, "variant must be 0, 1 or 2");
     gmg::apply_level_hook(p->P, level, variant, x, y, s);
     return 0;
   });

@@ -8,7 +8,8 @@
 // Operator, two passes.  Pass 1 (fam_op): a workgroup stages the node
 // patches of FB families in LDS (interiors, contiguous in memory, by
 // coalesced loads; entity nodes through the entity bases), one lane computes
-// one cell, siblings combine in LDS.  Values at nodes no other family
+// one cell, siblings combine by lane shuffles (floating-point atomics in LDS
+// measured several times slower for FP32).  Values at nodes no other family
 // touches (the family interior, and level-boundary entities) are final and
 // go straight through the epilogue (Chebyshev update, residual, or plain
 // output); values at shared entities go to the entity's slot for this
@@ -112,34 +113,46 @@ struct FamShape {
   // different LDS banks
   static constexpr int MFP = sizeof(T) == 4 ? (MF % 2 ? MF + 2 : MF + 1) : MF + 1;
   static constexpr int budget = K >= 3 ? 163840 : 81920;
-  static constexpr int fixed = G::NB * 6 + 256;
+  static constexpr int fixed = G::NB * 14 + 256;
   static constexpr int fb_lds = (budget - fixed) / (2 * MFP * (int)sizeof(T) + NJ * 4 + 4);
   static constexpr int fb_cap = 256 / CPF;
   static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
   static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
   static constexpr int THREADS = FB * CPF;
+  // sibling sum: lane shuffles for 4-byte values (FP32 atomic adds in LDS are
+  // slow), LDS atomic adds for FP64 (a 64-bit shuffle takes two exchanges)
+  static constexpr bool SHUFFLE = sizeof(T) == 4;
+  // entity positions handled per round of the output epilogue (registers)
+  static constexpr int CH = 5;
   static constexpr int ITI = (G::NI * FB + THREADS - 1) / THREADS;
   static constexpr int ITB = (G::NB * FB + THREADS - 1) / THREADS;
 };
 
-// operator slot of a shared-entity position (r >= 1)
+// Operator slot of a shared-entity position (r >= 1) of a family whose
+// entity base is gb: eoff[r] + (gb - sec[r]) 2^r + pos size_r + loc.  All
+// terms but gb 2^r depend on the position only and are tabulated per
+// workgroup (bo, from stage_bases), so that the per-section offsets of the
+// view are not indexed at run time in the hot loops.
 template <int DIM, int K>
-__device__ __forceinline__ int64_t ent_slot(const LevelView& v, int32_t gb, uint32_t c) {
+__device__ __forceinline__ int64_t slot_part(const LevelView& v, uint32_t c) {
   using G = Geo<DIM, K>;
   const int r = G::cr(c);
   const int sz = r == 1 ? G::size_r(1) : r == 2 ? G::size_r(2) : G::size_r(3);
-  return v.eoff[r] + ((int64_t)(gb - v.sec[r]) << r) + (int64_t)G::cpos(c) * sz + G::cloc(c);
+  return v.eoff[r] - (v.sec[r] << r) + (int64_t)G::cpos(c) * sz + G::cloc(c);
 }
 
-// Epilogue on IT nodes (node < 0: nothing).  All loads first, at a valid
-// index (node 0 of the level when the node is skipped), then the updates.
+// Epilogue on IT nodes (node < 0: nothing).  Three phases without control
+// flow between a load and its use: all loads (at a valid index, node 0 of
+// the level, when the node is skipped), all arithmetic, then the stores
+// under their predicates; stores share the wait counter with loads, so no
+// store is issued before the last value it depends on is known.
 // FLAGS: the nodes may be interface or Dirichlet nodes (residual rows of D
 // nodes are zero); family-interior nodes are always smoothed nodes.
 // xo: the node's x before this operator application (Chebyshev update).
 template <typename T, int EPI, int IT, bool FLAGS>
-__device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int64_t (&node)[IT], const T (&ax)[IT],
+__device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int32_t (&node)[IT], const T (&ax)[IT],
                                           const T (&xo)[IT]) {
-  int64_t ii[IT];
+  int32_t ii[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) ii[it] = node[it] >= 0 ? node[it] : 0;
   if (EPI == kEpiPlain || EPI == kEpiDiag) {
@@ -155,11 +168,12 @@ __device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int64_t (&node
       iv[it] = ep.dinv[ii[it]];
     }
 #pragma unroll
+    for (int it = 0; it < IT; ++it) dv[it] = ep.c1 * dv[it] + ep.c2 * iv[it] * (gv[it] - ax[it]);
+#pragma unroll
     for (int it = 0; it < IT; ++it)
       if (node[it] >= 0) {
-        const T dn = ep.c1 * dv[it] + ep.c2 * iv[it] * (gv[it] - ax[it]);
-        ep.d[ii[it]] = dn;
-        ep.x[ii[it]] = xo[it] + dn;
+        ep.d[ii[it]] = dv[it];
+        ep.x[ii[it]] = xo[it] + dv[it];
       }
   } else if (EPI == kEpiResid) {
     T gv[IT];
@@ -170,8 +184,10 @@ __device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int64_t (&node
       fv[it] = FLAGS ? ep.flags[ii[it]] : 0;
     }
 #pragma unroll
+    for (int it = 0; it < IT; ++it) gv[it] = fv[it] == 2 ? T(0) : gv[it] - ax[it];
+#pragma unroll
     for (int it = 0; it < IT; ++it)
-      if (node[it] >= 0) ep.y[ii[it]] = fv[it] == 2 ? T(0) : gv[it] - ax[it];
+      if (node[it] >= 0) ep.y[ii[it]] = gv[it];
   } else {  // kEpiRStart
     T gv[IT], iv[IT];
 #pragma unroll
@@ -180,14 +196,17 @@ __device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int64_t (&node
       iv[it] = ep.smooth ? ep.dinv[ii[it]] : T(0);
     }
 #pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      gv[it] += ax[it];
+      iv[it] = ep.c2 * iv[it] * gv[it];
+    }
+#pragma unroll
     for (int it = 0; it < IT; ++it)
       if (node[it] >= 0) {
-        const T gi = gv[it] + ax[it];
-        ep.g[ii[it]] = gi;
+        ep.g[ii[it]] = gv[it];
         if (ep.smooth) {
-          const T dn = ep.c2 * iv[it] * gi;
-          ep.d[ii[it]] = dn;
-          ep.x[ii[it]] = dn;
+          ep.d[ii[it]] = iv[it];
+          ep.x[ii[it]] = iv[it];
         }
       }
   }
@@ -216,10 +235,10 @@ __device__ __forceinline__ void epi_shared(const Epi<T>& ep, int64_t i, T ax) {
 }
 
 // stage the entity bases and exclusivity bits of the workgroup's families
-// and the table of entity positions (position, code)
+// and the table of entity positions (position, code, slot part)
 template <int DIM, int K, typename T>
 __device__ __forceinline__ void stage_bases(const LevelView& v, int64_t f0, int32_t* sgb, uint32_t* sex,
-                                            uint16_t* bq, uint32_t* bc) {
+                                            uint16_t* bq, uint32_t* bc, int64_t* bo) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   for (int e = threadIdx.x; e < S::FB * G::NJ; e += S::THREADS) {
@@ -233,6 +252,7 @@ __device__ __forceinline__ void stage_bases(const LevelView& v, int64_t f0, int3
       const int b = G::bidx(q);
       bq[b] = (uint16_t)q;
       bc[b] = c;
+      bo[b] = slot_part<DIM, K>(v, c);
     }
   }
 }
@@ -248,6 +268,54 @@ __device__ __forceinline__ int cell_patch_pos(int cid, int j) {
   return ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx);
 }
 
+// Sum over the 2^d sibling cells of a family of their per-node values.  The
+// cells of a family sit in 2^d consecutive lanes of one wave (lane bits =
+// child position bits x, y, z).  Axis by axis, the two cells on either side
+// of the family's middle plane exchange their values on that plane with an
+// xor shuffle and keep the sum; after d stages every lane holds, for each of
+// its nodes, the sum over all cells of the family that contain the node.
+// Every lane of the wave must take part.
+template <int DIM, int N, typename T>
+__device__ __forceinline__ void family_sum(int cid, T (&w)[DIM == 3 ? N * N * N : N * N]) {
+  constexpr int K = N - 1;
+  constexpr int NZ = DIM == 3 ? N : 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const bool hi = (cid >> a) & 1;
+#pragma unroll
+    for (int s = 0; s < N * NZ; ++s) {
+      // the two other local indices of a node on the plane normal to a
+      const int u = s % N, v = s / N;
+      int i0, iK;  // local node with index 0 / K along a
+      if (a == 0) {
+        i0 = (v * N + u) * N;
+        iK = i0 + K;
+      } else if (a == 1) {
+        i0 = v * N * N + u;
+        iK = i0 + K * N;
+      } else {
+        i0 = v * N + u;
+        iK = i0 + K * N * N;
+      }
+      T t = hi ? w[i0] : w[iK];
+      t += __shfl_xor(t, 1 << a, 64);
+      if (hi)
+        w[i0] = t;
+      else
+        w[iK] = t;
+    }
+  }
+}
+
+// lane cid writes its local node j to the family patch iff no sibling with
+// a lower child position contains the node
+template <int DIM, int N>
+__device__ __forceinline__ bool family_owner(int cid, int j) {
+  const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+  const int m = (jx == 0 ? 1 : 0) | (jy == 0 ? 2 : 0) | (DIM == 3 && jz == 0 ? 4 : 0);
+  return (cid & m) == 0;
+}
+
 // ------------------------------------------------------------------ pass 1
 // Output of a family patch held in LDS (sout): interior nodes and nodes of
 // exclusive entities through the epilogue, shared entities to their slots.
@@ -255,13 +323,14 @@ __device__ __forceinline__ int cell_patch_pos(int cid, int j) {
 template <int DIM, int K, typename T, int EPI>
 __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf, const T* sout, const T* sin,
                                           const int32_t* sgb, const uint32_t* sex, const uint16_t* bq,
-                                          const uint32_t* bc, const Epi<T>& ep, T* __restrict__ E) {
+                                          const uint32_t* bc, const int64_t* bo, const Epi<T>& ep,
+                                          T* __restrict__ E) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
   const int tid = threadIdx.x;
   {
-    int64_t node[S::ITI];
+    int32_t node[S::ITI];
     T ax[S::ITI], xo[S::ITI];
 #pragma unroll
     for (int it = 0; it < S::ITI; ++it) {
@@ -270,38 +339,44 @@ __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf
       ax[it] = xo[it] = T(0);
       if (e < nf * NI) {
         const int fl = e / NI, q = G::iq(e % NI);
-        node[it] = f0 * NI + e;
+        node[it] = (int32_t)(f0 * NI + e);
         ax[it] = sout[fl * MFP + q];
         if (EPI == kEpiCheb) xo[it] = sin[fl * MFP + q];
       }
     }
     epi_batch<T, EPI, S::ITI, false>(ep, node, ax, xo);
   }
-  {
-    int64_t node[S::ITB];
-    T ax[S::ITB], xo[S::ITB];
+  // entity positions, in rounds of CH: values and targets from LDS, the slot
+  // stores of shared entities, then the epilogue of exclusive ones
 #pragma unroll
-    for (int it = 0; it < S::ITB; ++it) {
+  for (int c0 = 0; c0 < S::ITB; c0 += S::CH) {
+    int32_t node[S::CH], slot[S::CH];
+    T ax[S::CH], xo[S::CH];
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k) {
+      const int it = c0 + k;
       const int e = tid + it * S::THREADS;
-      node[it] = -1;
-      ax[it] = xo[it] = T(0);
-      if (e < nf * NB) {
+      node[k] = slot[k] = -1;
+      ax[k] = xo[k] = T(0);
+      if (it < S::ITB && e < nf * NB) {
         const int fl = e / NB, b = e % NB;
         const int q = bq[b];
         const uint32_t c = bc[b];
         const int j = G::cj(c);
         const int32_t gb = sgb[fl * NJ + j];
-        const T val = sout[fl * MFP + q];
+        ax[k] = sout[fl * MFP + q];
         if ((sex[fl] >> j) & 1u) {
-          node[it] = (int64_t)gb + G::cloc(c);
-          ax[it] = val;
-          if (EPI == kEpiCheb) xo[it] = sin[fl * MFP + q];
+          node[k] = gb + G::cloc(c);
+          if (EPI == kEpiCheb) xo[k] = sin[fl * MFP + q];
         } else {
-          E[ent_slot<DIM, K>(v, gb, c)] = val;
+          slot[k] = (int32_t)(bo[b] + ((int64_t)gb << G::cr(c)));
         }
       }
     }
-    epi_batch<T, EPI, S::ITB, true>(ep, node, ax, xo);
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k)
+      if (slot[k] >= 0) E[slot[k]] = ax[k];
+    epi_batch<T, EPI, S::CH, true>(ep, node, ax, xo);
   }
 }
 
@@ -318,11 +393,13 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   __shared__ uint32_t sex[FB];
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
   const int64_t f0 = xcd_block() * FB;
   const int nf = (int)(v.n_fam - f0 < FB ? v.n_fam - f0 : FB);
   const int tid = threadIdx.x;
-  stage_bases<DIM, K, T>(v, f0, sgb, sex, bq, bc);
-  for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
+  stage_bases<DIM, K, T>(v, f0, sgb, sex, bq, bc, bo);
+  if constexpr (!S::SHUFFLE)
+    for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
   __syncthreads();
   if (EPI != kEpiDiag) {
     T vi[S::ITI], vb[S::ITB];
@@ -354,38 +431,47 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
     __syncthreads();
   }
   {
+    // one lane per cell (all lanes take part in the family sum; lanes of
+    // families beyond the level compute on zeros)
     const int fl = tid / CPF, cid = tid % CPF;
     const int64_t f = f0 + fl;
-    if (fl < nf) {
-      T w[NP];
-      if (EPI == kEpiDiag) {
+    T w[NP];
+    if (EPI == kEpiDiag) {
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
-          const T mx = m.M[jx * N + jx], my = m.M[jy * N + jy], kx = m.K[jx * N + jx], ky = m.K[jy * N + jy];
-          if (DIM == 3) {
-            const T mz = m.M[jz * N + jz], kz = m.K[jz * N + jz];
-            w[j] = kx * my * mz + mx * ky * mz + mx * my * kz;
-          } else {
-            w[j] = kx * my + mx * ky;
-          }
+      for (int j = 0; j < NP; ++j) {
+        const int jx = j % N, jy = (j / N) % N, jz = DIM == 3 ? j / (N * N) : 0;
+        const T mx = m.M[jx * N + jx], my = m.M[jy * N + jy], kx = m.K[jx * N + jx], ky = m.K[jy * N + jy];
+        if (DIM == 3) {
+          const T mz = m.M[jz * N + jz], kz = m.K[jz * N + jz];
+          w[j] = kx * my * mz + mx * ky * mz + mx * my * kz;
+        } else {
+          w[j] = kx * my + mx * ky;
         }
-      } else {
-        T u[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) u[j] = sin[fl * MFP + cell_patch_pos<DIM, K>(cid, j)];
-        if (DIM == 3)
-          laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(w));
-        else
-          laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(w));
       }
-      const T sc = T(v.scale ? v.scale[f * CPF + cid] : v.scale0);
+    } else {
+      T u[NP];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], sc * w[j]);
+      for (int j = 0; j < NP; ++j) u[j] = sin[fl * MFP + cell_patch_pos<DIM, K>(cid, j)];
+      if (DIM == 3)
+        laplace3<N, T>(m, *reinterpret_cast<const T(*)[N * N * N]>(u), *reinterpret_cast<T(*)[N * N * N]>(w));
+      else
+        laplace2<N, T>(m, *reinterpret_cast<const T(*)[N * N]>(u), *reinterpret_cast<T(*)[N * N]>(w));
+    }
+    const T sc = fl < nf ? T(v.scale ? v.scale[f * CPF + cid] : v.scale0) : T(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) w[j] *= sc;
+    if constexpr (S::SHUFFLE) {
+      family_sum<DIM, N, T>(cid, w);
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = w[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], w[j]);
     }
   }
   __syncthreads();
-  patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, ep, E);
+  patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E);
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -399,10 +485,14 @@ __device__ __forceinline__ T sum_slots(const LevelView& v, const T* __restrict__
   const int loc = (int)(t - e * SZ);
   const uint32_t pm = v.pmask[v.entoff[R] + e];
   const T* p = E + v.eoff[R] + ((e << R) * SZ) + loc;
+  // every position slot of a shared entity lies inside the buffer; slots of
+  // absent families hold stale values and are dropped by the select
+  T a[1 << R];
+#pragma unroll
+  for (int pos = 0; pos < (1 << R); ++pos) a[pos] = p[pos * SZ];
   T s = T(0);
 #pragma unroll
-  for (int pos = 0; pos < (1 << R); ++pos)
-    if ((pm >> pos) & 1u) s += p[pos * SZ];
+  for (int pos = 0; pos < (1 << R); ++pos) s += ((pm >> pos) & 1u) ? a[pos] : T(0);
   return s;
 }
 
@@ -512,24 +602,33 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(L
   __shared__ uint32_t sex[FB];
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
   const int64_t f0 = xcd_block() * FB;
   const int nf = (int)(coarse.n_fam - f0 < FB ? coarse.n_fam - f0 : FB);
   const int tid = threadIdx.x;
-  stage_bases<DIM, K, T>(coarse, f0, sgb, sex, bq, bc);
-  for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
+  stage_bases<DIM, K, T>(coarse, f0, sgb, sex, bq, bc, bo);
+  if constexpr (!S::SHUFFLE)
+    for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
   __syncthreads();
   {
     const int fl = tid / CPF, cid = tid % CPF;
     const int64_t f = fl < nf ? coarse.child[(int64_t)cid * coarse.n_fam + f0 + fl] : -1;
-    if (f >= 0) {
-      T out[NP];
-      restrict_family<DIM, K, T>(fine, f, r, m, out);
+    T out[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) out[j] = T(0);
+    if (f >= 0) restrict_family<DIM, K, T>(fine, f, r, m, out);
+    if constexpr (S::SHUFFLE) {
+      family_sum<DIM, G::N, T>(cid, out);
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        if (family_owner<DIM, G::N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = out[j];
+    } else if (f >= 0) {
 #pragma unroll
       for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], out[j]);
     }
   }
   __syncthreads();
-  patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, ep, E);
+  patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, bo, ep, E);
 }
 
 // Restriction from level 1 into level 0 (no families there): one lane per

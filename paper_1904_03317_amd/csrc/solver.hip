@@ -700,6 +700,16 @@ template <typename T>
 static void level_hook(Problem& P, int l, int variant, const T* x, T* y, hipStream_t s) {
   DevLevel& V = P.lv[l];
   const int64_t n = V.v.n_dofs;
+  if (variant == 2) {
+    // one Chebyshev step (the second of the semi-iteration) on the level's
+    // V-cycle work vectors; x and y are not used
+    if (l < 1) fail(GMG_E_INVAL, "smoothing step needs a level >= 1");
+    const int keep = P.opt.cheb_degree;
+    P.opt.cheb_degree = 2;
+    smooth_steps<T>(P, l, 2, s);
+    P.opt.cheb_degree = keep;
+    return;
+  }
   if (variant == 0) {
     level_apply<T>(P, l, x, y, s);
     return;
@@ -714,7 +724,7 @@ static void level_hook(Problem& P, int l, int variant, const T* x, T* y, hipStre
 void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hipStream_t s) {
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
   if (l < 0 || l >= (int)P.lv.size()) fail(GMG_E_INVAL, "level out of range");
-  if (variant != 0 && variant != 1) fail(GMG_E_INVAL, "variant must be 0 or 1");
+  if (variant < 0 || variant > 2) fail(GMG_E_INVAL, "variant must be 0, 1 or 2");
   if (P.opt.mg_precision == 32)
     level_hook<float>(P, l, variant, (const float*)x, (float*)y, s);
   else

@@ -164,6 +164,19 @@ inline void unsafeAtomicAdd(T* p, T v) {
   atomicAdd(p, v);
 }
 
+// lane exchange inside a block through block scratch: every thread of the
+// block must take part (two barriers per call)
+template <typename T>
+inline T __shfl_xor(T v, int mask, int w = 64) {
+  const unsigned t = threadIdx.x;
+  emu::g_shfl[t] = (double)v;
+  __syncthreads();
+  const unsigned o = t ^ (unsigned)mask;
+  const double r = (o < blockDim.x && (o / (unsigned)w) == (t / (unsigned)w)) ? emu::g_shfl[o] : (double)v;
+  __syncthreads();
+  return (T)r;
+}
+
 // wave-wide shuffle through block scratch (waves of 64 lanes)
 inline double __shfl_down(double v, int o, int w) {
   const unsigned t = threadIdx.x, lane = t % (unsigned)w;

@@ -91,6 +91,9 @@ def test_errors_are_reported():
     x = np.zeros(P.n_dofs)
     code = L.gmg_vcycle(P.h, x.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p), None)
     assert code == -8
+    xp = x.ctypes.data_as(ctypes.c_void_p)
+    assert L.gmg_apply_level(P.h, 0, 3, xp, xp, None) == -1     # unknown variant
+    assert L.gmg_apply_level(P.h, 0, 2, xp, xp, None) == -8     # not bound
     with pytest.raises(ValueError):
         m.refine(np.ones(5, np.uint8))
 
@@ -114,6 +117,36 @@ def test_workspace_accounts_for_precision():
     _, P32, _ = library_problem(rec, k, mg_precision=32)
     _, P64, _ = library_problem(rec, k, mg_precision=64)
     assert P64.workspace_bytes() > P32.workspace_bytes() > 0
+
+
+def test_level_permutation_is_entity_layout():
+    """Level vectors on levels >= 1 live in the family-entity layout: the
+    permutation is a bijection, family interiors come first (sections of the
+    layout) and the cell map in device numbering gives every family the same
+    positions of its (2k+1)^d patch (checked against the oracle's level maps)."""
+    rec, k = CASES["fichera-q2"]
+    _, P, _ = library_problem(rec, k)
+    d = discretize(op.build_forest(rec), k)
+    for l, lev in enumerate(d.levels):
+        perm = P.array("LEVEL_PERM", l)
+        assert np.array_equal(np.sort(perm), np.arange(lev.n_dofs))
+        if l == 0:
+            assert np.array_equal(perm, np.arange(lev.n_dofs))
+            continue
+        # interiors: the (2k-1)^3 interior nodes of family f are f*27 .. f*27+26
+        cm = perm[lev.cellmap]                      # [cells, (k+1)^3] in device numbering
+        n = k + 1
+        nf = lev.cellmap.shape[0] // 8
+        for f in range(nf):
+            patch = np.full((2 * k + 1,) * 3, -1)
+            for c in range(8):
+                bx, by, bz = (c & 1) * k, ((c >> 1) & 1) * k, ((c >> 2) & 1) * k
+                blk = cm[f * 8 + c].reshape(n, n, n)     # [z][y][x]
+                sub = patch[bz:bz + n, by:by + n, bx:bx + n]
+                assert np.all((sub < 0) | (sub == blk))
+                patch[bz:bz + n, by:by + n, bx:bx + n] = blk
+            inner = patch[1:-1, 1:-1, 1:-1].ravel()
+            assert np.array_equal(inner, f * (2 * k - 1) ** 3 + np.arange((2 * k - 1) ** 3))
 
 
 def test_clone_keeps_maps():
