@@ -119,9 +119,9 @@ struct FamShape {
   static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
   static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
   static constexpr int THREADS = FB * CPF;
-  // sibling sum: lane shuffles for 4-byte values (FP32 atomic adds in LDS are
-  // slow), LDS atomic adds for FP64 (a 64-bit shuffle takes two exchanges)
-  static constexpr bool SHUFFLE = sizeof(T) == 4;
+  // sibling sum by lane moves (FP32 atomic adds in LDS measured several
+  // times slower; kept as the alternative for FP64)
+  static constexpr bool SHUFFLE = true;
   // entity positions handled per round of the output epilogue (registers)
   static constexpr int CH = 5;
   static constexpr int ITI = (G::NI * FB + THREADS - 1) / THREADS;
@@ -268,43 +268,71 @@ __device__ __forceinline__ int cell_patch_pos(int cid, int j) {
   return ((bz + jz) * M2 + (by + jy)) * M2 + (bx + jx);
 }
 
+// Value of the lane whose index differs in bit B (B = 0, 1, 2) from this
+// lane's, by data-parallel moves inside each group of 8 lanes (no LDS):
+// xor 1 and xor 2 are quad permutations, xor 4 is the mirror inside each
+// half row followed by the reversal inside each quad.
+template <int B>
+__device__ __forceinline__ int32_t lane_xor(int32_t v) {
+  constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kQuadRev = 0x1B, kHalfMirror = 0x141;
+  if (B == 0) return __builtin_amdgcn_mov_dpp(v, kQuadXor1, 0xF, 0xF, false);
+  if (B == 1) return __builtin_amdgcn_mov_dpp(v, kQuadXor2, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, kHalfMirror, 0xF, 0xF, false), kQuadRev, 0xF, 0xF,
+                                  false);
+}
+template <int B>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(lane_xor<B>(__float_as_int(v)));
+}
+template <int B>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long u = __double_as_longlong(v);
+  const int32_t lo = lane_xor<B>((int32_t)(u & 0xffffffffLL)), hi = lane_xor<B>((int32_t)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
+// c ? a : b by bit masks: a value select the compiler cannot turn into a
+// select of addresses (which would index the cell array at run time and move
+// it from registers to scratch memory)
+__device__ __forceinline__ float sel(bool c, float a, float b) {
+  const int32_t m = -(int32_t)c;
+  return __int_as_float((__float_as_int(a) & m) | (__float_as_int(b) & ~m));
+}
+__device__ __forceinline__ double sel(bool c, double a, double b) {
+  const long long m = -(long long)c;
+  return __longlong_as_double((__double_as_longlong(a) & m) | (__double_as_longlong(b) & ~m));
+}
+
 // Sum over the 2^d sibling cells of a family of their per-node values.  The
 // cells of a family sit in 2^d consecutive lanes of one wave (lane bits =
 // child position bits x, y, z).  Axis by axis, the two cells on either side
-// of the family's middle plane exchange their values on that plane with an
-// xor shuffle and keep the sum; after d stages every lane holds, for each of
-// its nodes, the sum over all cells of the family that contain the node.
-// Every lane of the wave must take part.
-template <int DIM, int N, typename T>
-__device__ __forceinline__ void family_sum(int cid, T (&w)[DIM == 3 ? N * N * N : N * N]) {
+// of the family's middle plane exchange their values on that plane and keep
+// the sum (the same sum in both lanes: addition is commutative); after d
+// stages every lane holds, for each of its nodes, the sum over all cells of
+// the family that contain the node.  Every lane of the wave must take part.
+template <int DIM, int N, int A, typename T>
+__device__ __forceinline__ void family_sum_axis(int cid, T (&w)[DIM == 3 ? N * N * N : N * N]) {
   constexpr int K = N - 1;
   constexpr int NZ = DIM == 3 ? N : 1;
+  const bool hi = (cid >> A) & 1;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const bool hi = (cid >> a) & 1;
-#pragma unroll
-    for (int s = 0; s < N * NZ; ++s) {
-      // the two other local indices of a node on the plane normal to a
-      const int u = s % N, v = s / N;
-      int i0, iK;  // local node with index 0 / K along a
-      if (a == 0) {
-        i0 = (v * N + u) * N;
-        iK = i0 + K;
-      } else if (a == 1) {
-        i0 = v * N * N + u;
-        iK = i0 + K * N;
-      } else {
-        i0 = v * N + u;
-        iK = i0 + K * N * N;
-      }
-      T t = hi ? w[i0] : w[iK];
-      t += __shfl_xor(t, 1 << a, 64);
-      if (hi)
-        w[i0] = t;
-      else
-        w[iK] = t;
-    }
+  for (int s = 0; s < N * NZ; ++s) {
+    // the two other local indices of a node on the plane normal to A
+    const int u = s % N, v = s / N;
+    const int i0 = A == 0 ? (v * N + u) * N : A == 1 ? v * N * N + u : v * N + u;  // index 0 along A
+    const int iK = i0 + K * (A == 0 ? 1 : A == 1 ? N : N * N);                    // index K along A
+    const T a = w[i0], b = w[iK];
+    T t = sel(hi, a, b);
+    t += lane_xor<A>(t);
+    w[i0] = sel(hi, t, a);
+    w[iK] = sel(hi, b, t);
   }
+}
+template <int DIM, int N, typename T>
+__device__ __forceinline__ void family_sum(int cid, T (&w)[DIM == 3 ? N * N * N : N * N]) {
+  family_sum_axis<DIM, N, 0, T>(cid, w);
+  family_sum_axis<DIM, N, 1, T>(cid, w);
+  if (DIM == 3) family_sum_axis<DIM, N, 2, T>(cid, w);
 }
 
 // lane cid writes its local node j to the family patch iff no sibling with

@@ -177,6 +177,46 @@ inline T __shfl_xor(T v, int mask, int w = 64) {
   return (T)r;
 }
 
+// data-parallel lane moves used by the kernels (gfx9 DPP controls: quad
+// permutation 0x00-0xFF, row half mirror 0x141), through block scratch:
+// every thread of the block must take part
+inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool) {
+  const unsigned t = threadIdx.x;
+  emu::g_shfl[t] = (double)v;
+  __syncthreads();
+  unsigned src = t;
+  if (ctrl >= 0 && ctrl <= 0xFF) {
+    src = (t & ~3u) + ((unsigned)(ctrl >> (2 * (t & 3))) & 3u);
+  } else if (ctrl == 0x141) {
+    src = (t & ~7u) + (7u - (t & 7u));
+  } else {
+    std::abort();
+  }
+  const int r = src < blockDim.x ? (int)emu::g_shfl[src] : v;
+  __syncthreads();
+  return r;
+}
+inline float __int_as_float(int v) {
+  float f;
+  std::memcpy(&f, &v, 4);
+  return f;
+}
+inline int __float_as_int(float f) {
+  int v;
+  std::memcpy(&v, &f, 4);
+  return v;
+}
+inline double __longlong_as_double(long long v) {
+  double d;
+  std::memcpy(&d, &v, 8);
+  return d;
+}
+inline long long __double_as_longlong(double d) {
+  long long v;
+  std::memcpy(&v, &d, 8);
+  return v;
+}
+
 // wave-wide shuffle through block scratch (waves of 64 lanes)
 inline double __shfl_down(double v, int o, int w) {
   const unsigned t = threadIdx.x, lane = t % (unsigned)w;
