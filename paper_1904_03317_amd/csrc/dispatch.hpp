@@ -65,10 +65,12 @@ struct LevelOps {
   void (*op)(const LevelView&, int epi, const T* x, const dev::Epi<T>&, T* E, const MatsH<T>&, hipStream_t);
   // levels >= 1, pass 2: shared nodes, same epilogue
   void (*sum)(const LevelView&, int epi, const T* E, const dev::Epi<T>&, hipStream_t);
-  // restriction of the fine residual r into coarse level >= 1 (rstart
-  // epilogue on the coarse interiors, coarse slots for the rest)
+  // restriction of the fine residual r into coarse level >= 1: the
+  // restricted values of each fine family's parent cell into rb, then the
+  // coarse patches (rstart epilogue on their final nodes, coarse slots for
+  // the rest)
   void (*restrict_fc)(const LevelView& fine, const LevelView& coarse, const T* r, const dev::Epi<T>& coarse_ep,
-                      T* E, const MatsH<T>&, hipStream_t);
+                      T* rb, T* E, const MatsH<T>&, hipStream_t);
   // restriction from level 1 into the level-0 slots
   void (*restrict0)(const LevelView& fine, const T* r, T* E, const MatsH<T>&, hipStream_t);
   // x_f += P x_c

@@ -141,74 +141,97 @@ __device__ __forceinline__ int64_t slot_part(const LevelView& v, uint32_t c) {
   return v.eoff[r] - (v.sec[r] << r) + (int64_t)G::cpos(c) * sz + G::cloc(c);
 }
 
-// Epilogue on IT nodes (node < 0: nothing).  Three phases without control
-// flow between a load and its use: all loads (at a valid index, node 0 of
-// the level, when the node is skipped), all arithmetic, then the stores
-// under their predicates; stores share the wait counter with loads, so no
-// store is issued before the last value it depends on is known.
+// Epilogue on IT nodes (node < 0: nothing), split into the loads of its
+// operands (epi_load, at a valid index — node 0 of the level — when the node
+// is skipped) and the arithmetic plus predicated stores (epi_apply), so that
+// the loads can be issued early and no control flow sits between a load and
+// its use; stores share the wait counter with loads.
 // FLAGS: the nodes may be interface or Dirichlet nodes (residual rows of D
 // nodes are zero); family-interior nodes are always smoothed nodes.
 // xo: the node's x before this operator application (Chebyshev update).
+template <typename T, int IT>
+struct EpiOps {
+  T d[IT], g[IT], di[IT];
+  uint8_t fl[IT];
+};
+
 template <typename T, int EPI, int IT, bool FLAGS>
-__device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int32_t (&node)[IT], const T (&ax)[IT],
-                                          const T (&xo)[IT]) {
-  int32_t ii[IT];
+__device__ __forceinline__ void epi_load(const Epi<T>& ep, const int32_t (&node)[IT], EpiOps<T, IT>& o) {
 #pragma unroll
-  for (int it = 0; it < IT; ++it) ii[it] = node[it] >= 0 ? node[it] : 0;
+  for (int it = 0; it < IT; ++it) {
+    const int32_t i = node[it] >= 0 ? node[it] : 0;
+    if (EPI == kEpiCheb) {
+      o.d[it] = ep.d[i];
+      o.g[it] = ep.g[i];
+      o.di[it] = ep.dinv[i];
+    } else if (EPI == kEpiResid) {
+      o.g[it] = ep.g[i];
+      o.fl[it] = FLAGS ? ep.flags[i] : 0;
+    } else if (EPI == kEpiRStart) {
+      o.g[it] = ep.g[i];
+      o.di[it] = ep.smooth ? ep.dinv[i] : T(0);
+    }
+  }
+}
+
+template <typename T, int EPI, int IT>
+__device__ __forceinline__ void epi_apply(const Epi<T>& ep, const int32_t (&node)[IT], const T (&ax)[IT],
+                                          const T (&xo)[IT], EpiOps<T, IT>& o) {
   if (EPI == kEpiPlain || EPI == kEpiDiag) {
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-      if (node[it] >= 0) ep.y[ii[it]] = ax[it];
+      if (node[it] >= 0) ep.y[node[it]] = ax[it];
   } else if (EPI == kEpiCheb) {
-    T dv[IT], gv[IT], iv[IT];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      dv[it] = ep.d[ii[it]];
-      gv[it] = ep.g[ii[it]];
-      iv[it] = ep.dinv[ii[it]];
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) dv[it] = ep.c1 * dv[it] + ep.c2 * iv[it] * (gv[it] - ax[it]);
+    for (int it = 0; it < IT; ++it) o.d[it] = ep.c1 * o.d[it] + ep.c2 * o.di[it] * (o.g[it] - ax[it]);
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       if (node[it] >= 0) {
-        ep.d[ii[it]] = dv[it];
-        ep.x[ii[it]] = xo[it] + dv[it];
+        ep.d[node[it]] = o.d[it];
+        ep.x[node[it]] = xo[it] + o.d[it];
       }
   } else if (EPI == kEpiResid) {
-    T gv[IT];
-    uint8_t fv[IT];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      gv[it] = ep.g[ii[it]];
-      fv[it] = FLAGS ? ep.flags[ii[it]] : 0;
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) gv[it] = fv[it] == 2 ? T(0) : gv[it] - ax[it];
+    for (int it = 0; it < IT; ++it) o.g[it] = o.fl[it] == 2 ? T(0) : o.g[it] - ax[it];
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-      if (node[it] >= 0) ep.y[ii[it]] = gv[it];
+      if (node[it] >= 0) ep.y[node[it]] = o.g[it];
   } else {  // kEpiRStart
-    T gv[IT], iv[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      gv[it] = ep.g[ii[it]];
-      iv[it] = ep.smooth ? ep.dinv[ii[it]] : T(0);
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      gv[it] += ax[it];
-      iv[it] = ep.c2 * iv[it] * gv[it];
+      o.g[it] += ax[it];
+      o.di[it] = ep.c2 * o.di[it] * o.g[it];
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       if (node[it] >= 0) {
-        ep.g[ii[it]] = gv[it];
+        ep.g[node[it]] = o.g[it];
         if (ep.smooth) {
-          ep.d[ii[it]] = iv[it];
-          ep.x[ii[it]] = iv[it];
+          ep.d[node[it]] = o.di[it];
+          ep.x[node[it]] = o.di[it];
         }
       }
+  }
+}
+
+template <typename T, int EPI, int IT, bool FLAGS>
+__device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int32_t (&node)[IT], const T (&ax)[IT],
+                                          const T (&xo)[IT]) {
+  EpiOps<T, IT> o;
+  epi_load<T, EPI, IT, FLAGS>(ep, node, o);
+  epi_apply<T, EPI, IT>(ep, node, ax, xo, o);
+}
+
+// interior nodes of the workgroup's families: node f0 NI + e for e < nf NI
+// (contiguous), else -1
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void interior_nodes(int64_t f0, int nf, int32_t (&node)[FamShape<DIM, K, T>::ITI]) {
+  using S = FamShape<DIM, K, T>;
+  constexpr int NI = Geo<DIM, K>::NI;
+#pragma unroll
+  for (int it = 0; it < S::ITI; ++it) {
+    const int e = threadIdx.x + it * S::THREADS;
+    node[it] = e < nf * NI ? (int32_t)(f0 * NI + e) : -1;
   }
 }
 
@@ -352,27 +375,27 @@ template <int DIM, int K, typename T, int EPI>
 __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf, const T* sout, const T* sin,
                                           const int32_t* sgb, const uint32_t* sex, const uint16_t* bq,
                                           const uint32_t* bc, const int64_t* bo, const Epi<T>& ep,
-                                          T* __restrict__ E) {
+                                          T* __restrict__ E,
+                                          const int32_t (&inode)[FamShape<DIM, K, T>::ITI],
+                                          EpiOps<T, FamShape<DIM, K, T>::ITI>& iops) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
   const int tid = threadIdx.x;
   {
-    int32_t node[S::ITI];
+    // interior nodes: operands were loaded before the compute
     T ax[S::ITI], xo[S::ITI];
 #pragma unroll
     for (int it = 0; it < S::ITI; ++it) {
       const int e = tid + it * S::THREADS;
-      node[it] = -1;
       ax[it] = xo[it] = T(0);
-      if (e < nf * NI) {
+      if (inode[it] >= 0) {
         const int fl = e / NI, q = G::iq(e % NI);
-        node[it] = (int32_t)(f0 * NI + e);
         ax[it] = sout[fl * MFP + q];
         if (EPI == kEpiCheb) xo[it] = sin[fl * MFP + q];
       }
     }
-    epi_batch<T, EPI, S::ITI, false>(ep, node, ax, xo);
+    epi_apply<T, EPI, S::ITI>(ep, inode, ax, xo, iops);
   }
   // entity positions, in rounds of CH: values and targets from LDS, the slot
   // stores of shared entities, then the epilogue of exclusive ones
@@ -408,6 +431,44 @@ __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf
   }
 }
 
+// node patches of the workgroup's families into LDS (sin[fl MFP + q]):
+// interiors by coalesced loads of a contiguous block, entity positions
+// through the staged entity bases; all loads issued before the LDS stores
+template <int DIM, int K, typename T>
+__device__ __forceinline__ void gather_patch(int64_t f0, int nf, const T* __restrict__ xin, const int32_t* sgb,
+                                             const uint16_t* bq, const uint32_t* bc, T* sin) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
+  const int tid = threadIdx.x;
+  T vi[S::ITI], vb[S::ITB];
+#pragma unroll
+  for (int it = 0; it < S::ITI; ++it) {
+    const int e = tid + it * S::THREADS;
+    vi[it] = e < nf * NI ? xin[f0 * NI + e] : T(0);
+  }
+#pragma unroll
+  for (int it = 0; it < S::ITB; ++it) {
+    const int e = tid + it * S::THREADS;
+    vb[it] = T(0);
+    if (e < nf * NB) {
+      const int fl = e / NB;
+      const uint32_t c = bc[e % NB];
+      vb[it] = xin[sgb[fl * NJ + G::cj(c)] + G::cloc(c)];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < S::ITI; ++it) {
+    const int e = tid + it * S::THREADS;
+    if (e < nf * NI) sin[(e / NI) * MFP + G::iq(e % NI)] = vi[it];
+  }
+#pragma unroll
+  for (int it = 0; it < S::ITB; ++it) {
+    const int e = tid + it * S::THREADS;
+    if (e < nf * NB) sin[(e / NB) * MFP + bq[e % NB]] = vb[it];
+  }
+}
+
 template <int DIM, int K, typename T, int EPI>
 __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelView v, const T* __restrict__ xin,
                                                                           Epi<T> ep, T* __restrict__ E, Mats<T> m) {
@@ -425,37 +486,17 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   const int64_t f0 = xcd_block() * FB;
   const int nf = (int)(v.n_fam - f0 < FB ? v.n_fam - f0 : FB);
   const int tid = threadIdx.x;
+  // interior epilogue operands: contiguous, known before anything else
+  int32_t inode[S::ITI];
+  interior_nodes<DIM, K, T>(f0, nf, inode);
+  EpiOps<T, S::ITI> iops;
+  epi_load<T, EPI, S::ITI, false>(ep, inode, iops);
   stage_bases<DIM, K, T>(v, f0, sgb, sex, bq, bc, bo);
   if constexpr (!S::SHUFFLE)
     for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
   __syncthreads();
   if (EPI != kEpiDiag) {
-    T vi[S::ITI], vb[S::ITB];
-#pragma unroll
-    for (int it = 0; it < S::ITI; ++it) {
-      const int e = tid + it * S::THREADS;
-      vi[it] = e < nf * NI ? xin[f0 * NI + e] : T(0);
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITB; ++it) {
-      const int e = tid + it * S::THREADS;
-      vb[it] = T(0);
-      if (e < nf * NB) {
-        const int fl = e / NB;
-        const uint32_t c = bc[e % NB];
-        vb[it] = xin[sgb[fl * NJ + G::cj(c)] + G::cloc(c)];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITI; ++it) {
-      const int e = tid + it * S::THREADS;
-      if (e < nf * NI) sin[(e / NI) * MFP + G::iq(e % NI)] = vi[it];
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITB; ++it) {
-      const int e = tid + it * S::THREADS;
-      if (e < nf * NB) sin[(e / NB) * MFP + bq[e % NB]] = vb[it];
-    }
+    gather_patch<DIM, K, T>(f0, nf, xin, sgb, bq, bc, sin);
     __syncthreads();
   }
   {
@@ -499,7 +540,7 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
     }
   }
   __syncthreads();
-  patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E);
+  patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -555,8 +596,9 @@ __device__ __forceinline__ int64_t fam_node(const int32_t (&gb)[Geo<DIM, K>::NJ]
 }
 
 // Restriction R = P^T of the fine residual r on the nodes the fine family
-// owns, contracted to the (k+1)^d values of its parent cell (row by row
-// while loading).
+// owns, contracted to the (k+1)^d values of its parent cell: fine z-slab by
+// z-slab (x contraction row by row while loading, then y, then the slab's
+// share of the z contraction), so that only one slab is live at a time.
 template <int DIM, int K, typename T>
 __device__ __forceinline__ void restrict_family(const LevelView& fine, int64_t f, const T* __restrict__ r,
                                                 const Mats<T>& m, T (&out)[Geo<DIM, K>::NP]) {
@@ -567,60 +609,152 @@ __device__ __forceinline__ void restrict_family(const LevelView& fine, int64_t f
 #pragma unroll
   for (int j = 0; j < NJ; ++j) gb[j] = fine.gbase[(int64_t)j * fine.n_fam + f];
   const uint32_t ow = fine.own[f];
-  T a[NZ * M2 * N];
 #pragma unroll
-  for (int zy = 0; zy < NZ * M2; ++zy) {
-    T rv[M2];
+  for (int j = 0; j < G::NP; ++j) out[j] = T(0);
 #pragma unroll
-    for (int i = 0; i < M2; ++i) rv[i] = r[fam_node<DIM, K>(gb, zy * M2 + i)];
+  for (int iz = 0; iz < NZ; ++iz) {
+    T a[M2 * N];
 #pragma unroll
-    for (int i = 0; i < M2; ++i)
-      if (!((ow >> G::cj(G::code(zy * M2 + i))) & 1u)) rv[i] = T(0);
+    for (int iy = 0; iy < M2; ++iy) {
+      T rv[M2];
 #pragma unroll
-    for (int J = 0; J < N; ++J) {
-      T s = 0;
+      for (int ix = 0; ix < M2; ++ix) rv[ix] = r[fam_node<DIM, K>(gb, (iz * M2 + iy) * M2 + ix)];
 #pragma unroll
-      for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * rv[i];
-      a[zy * N + J] = s;
-    }
-  }
-  T b[NZ * N * N];
-#pragma unroll
-  for (int z = 0; z < NZ; ++z)
-#pragma unroll
-    for (int x = 0; x < N; ++x)
+      for (int ix = 0; ix < M2; ++ix)
+        if (!((ow >> G::cj(G::code((iz * M2 + iy) * M2 + ix))) & 1u)) rv[ix] = T(0);
 #pragma unroll
       for (int J = 0; J < N; ++J) {
         T s = 0;
 #pragma unroll
-        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * a[(z * M2 + i) * N + x];
-        b[(z * N + J) * N + x] = s;
+        for (int ix = 0; ix < M2; ++ix) s += m.E[ix * N + J] * rv[ix];
+        a[iy * N + J] = s;
       }
-  if (DIM == 2) {
+    }
+    T b[N * N];
 #pragma unroll
-    for (int j = 0; j < N * N; ++j) out[j] = b[j];
-  } else {
+    for (int Jy = 0; Jy < N; ++Jy)
 #pragma unroll
-    for (int J = 0; J < N; ++J)
-#pragma unroll
-      for (int yx = 0; yx < N * N; ++yx) {
+      for (int Jx = 0; Jx < N; ++Jx) {
         T s = 0;
 #pragma unroll
-        for (int i = 0; i < M2; ++i) s += m.E[i * N + J] * b[i * N * N + yx];
-        out[J * N * N + yx] = s;
+        for (int iy = 0; iy < M2; ++iy) s += m.E[iy * N + Jy] * a[iy * N + Jx];
+        b[Jy * N + Jx] = s;
       }
+    if (DIM == 2) {
+#pragma unroll
+      for (int j = 0; j < N * N; ++j) out[j] = b[j];
+    } else {
+#pragma unroll
+      for (int Jz = 0; Jz < N; ++Jz) {
+        const T w = m.E[iz * N + Jz];
+#pragma unroll
+        for (int yx = 0; yx < N * N; ++yx) out[Jz * N * N + yx] += w * b[yx];
+      }
+    }
   }
 }
 
-// Restriction into a level with families: one workgroup per FB coarse
-// families, one lane per coarse cell restricting the residual of the cell's
-// fine family (if the cell is refined); the coarse patch is summed in LDS
-// and leaves like an operator result with the rstart epilogue (every coarse
-// node of the level passes through it, restricted contribution or not;
-// pass 2 of the coarse level finishes the shared nodes).
+// Restriction, fine side: fine families in workgroups like the operator;
+// the fine residual patch is staged in LDS, one lane per fine cell takes
+// the patch nodes it owns (first cell of the family containing the node, and
+// only on entities the family owns: every fine node is counted once), applies
+// the transposed 1D embedding rows of its child position per axis, and the
+// 2^d lanes sum their (k+1)^d parent-cell values; rb[f (k+1)^d + j] receives
+// the restricted residual of family f's parent cell.
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(LevelView fine, LevelView coarse,
-                                                                                const T* __restrict__ r, Epi<T> ep,
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(LevelView fine, const T* __restrict__ r,
+                                                                             T* __restrict__ rb, Mats<T> m) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
+  __shared__ T sin[FB * MFP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  stage_bases<DIM, K, T>(fine, f0, sgb, sex, bq, bc, bo);
+  __syncthreads();
+  gather_patch<DIM, K, T>(f0, nf, r, sgb, bq, bc, sin);
+  __syncthreads();
+  const int fl = tid / CPF, cid = tid % CPF;
+  const uint32_t ow = fl < nf ? fine.own[f0 + fl] : 0u;
+  const bool hx = cid & 1, hy = (cid >> 1) & 1, hz = DIM == 3 && ((cid >> 2) & 1);
+  T v[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int q = cell_patch_pos<DIM, K>(cid, j);
+    const bool keep = family_owner<DIM, N>(cid, j) && ((ow >> G::cj(G::code(q))) & 1u);
+    v[j] = keep ? sin[fl * MFP + q] : T(0);
+  }
+  constexpr int NZ = DIM == 3 ? N : 1;
+  // x: t[z][y][J] = sum_i E[b_x k + i][J] v[z][y][i]
+  T t[NP];
+#pragma unroll
+  for (int rr = 0; rr < NZ * N; ++rr)
+#pragma unroll
+    for (int J = 0; J < N; ++J) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += sel(hx, m.E[(K + i) * N + J], m.E[i * N + J]) * v[rr * N + i];
+      t[rr * N + J] = s;
+    }
+  // y
+#pragma unroll
+  for (int z = 0; z < NZ; ++z)
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      T col[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) col[i] = t[(z * N + i) * N + x];
+#pragma unroll
+      for (int J = 0; J < N; ++J) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += sel(hy, m.E[(K + i) * N + J], m.E[i * N + J]) * col[i];
+        t[(z * N + J) * N + x] = s;
+      }
+    }
+  // z
+#pragma unroll
+  for (int yx = 0; yx < N * N; ++yx)
+#pragma unroll
+    for (int J = 0; J < NZ; ++J) {
+      if (DIM == 3) {
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += sel(hz, m.E[(K + i) * N + J], m.E[i * N + J]) * t[i * N * N + yx];
+        v[J * N * N + yx] = s;
+      } else {
+        v[yx] = t[yx];
+      }
+    }
+  // sum over the family's cells (every lane ends with the same totals)
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    v[j] += lane_xor<0>(v[j]);
+    v[j] += lane_xor<1>(v[j]);
+    if (DIM == 3) v[j] += lane_xor<2>(v[j]);
+  }
+  if (fl < nf) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (j % CPF == cid) rb[(f0 + fl) * NP + j] = v[j];
+  }
+}
+
+// Restriction, coarse side: one workgroup per FB coarse families, one lane
+// per coarse cell reading the restricted values of its fine family (if the
+// cell is refined); siblings combine as in the operator and the coarse
+// patch leaves through the restriction-start epilogue (every coarse node of
+// the level passes through it, restricted contribution or not; pass 2 of
+// the coarse level finishes the shared nodes).
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(LevelView coarse,
+                                                                                const T* __restrict__ rb, Epi<T> ep,
                                                                                 T* __restrict__ E, Mats<T> m) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
@@ -634,29 +768,25 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(L
   const int64_t f0 = xcd_block() * FB;
   const int nf = (int)(coarse.n_fam - f0 < FB ? coarse.n_fam - f0 : FB);
   const int tid = threadIdx.x;
+  int32_t inode[S::ITI];
+  interior_nodes<DIM, K, T>(f0, nf, inode);
+  EpiOps<T, S::ITI> iops;
+  epi_load<T, kEpiRStart, S::ITI, false>(ep, inode, iops);
   stage_bases<DIM, K, T>(coarse, f0, sgb, sex, bq, bc, bo);
-  if constexpr (!S::SHUFFLE)
-    for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
   __syncthreads();
   {
     const int fl = tid / CPF, cid = tid % CPF;
     const int64_t f = fl < nf ? coarse.child[(int64_t)cid * coarse.n_fam + f0 + fl] : -1;
     T out[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) out[j] = T(0);
-    if (f >= 0) restrict_family<DIM, K, T>(fine, f, r, m, out);
-    if constexpr (S::SHUFFLE) {
-      family_sum<DIM, G::N, T>(cid, out);
+    for (int j = 0; j < NP; ++j) out[j] = f >= 0 ? rb[f * NP + j] : T(0);
+    family_sum<DIM, G::N, T>(cid, out);
 #pragma unroll
-      for (int j = 0; j < NP; ++j)
-        if (family_owner<DIM, G::N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = out[j];
-    } else if (f >= 0) {
-#pragma unroll
-      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], out[j]);
-    }
+    for (int j = 0; j < NP; ++j)
+      if (family_owner<DIM, G::N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = out[j];
   }
   __syncthreads();
-  patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, bo, ep, E);
+  patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, bo, ep, E, inode, iops);
 }
 
 // Restriction from level 1 into level 0 (no families there): one lane per
@@ -674,114 +804,166 @@ __global__ void __launch_bounds__(kBlock) fam_restrict0(LevelView fine, const T*
   for (int j = 0; j < G::NP; ++j) E[fine.rslot[(int64_t)j * fine.n_fam + f]] = out[j];
 }
 
-// Prolongation x_f += P x_c of one fine family from its parent cell's
-// (k+1)^d values u: the family's (2k+1)^d patch, written on the entities it
-// owns (each fine node is owned by exactly one family).
+// Prolongation x_f += P x_c, fine families in workgroups like the operator:
+// the parent cell's (k+1)^d coarse values of each family are staged in LDS
+// (through the coarse family's entity bases, or the level-0 cell map), one
+// lane per fine cell interpolates its (k+1)^d nodes (rows b k .. b k + k of
+// the 1D embedding per axis, b its child position bit), the family patch
+// is assembled in LDS, and the workgroup adds it to x_f on the entities each
+// family owns (interiors contiguous, entity positions by table).
 template <int DIM, int K, typename T>
-__device__ __forceinline__ void prolong_family(const LevelView& fine, int64_t f, const T (&u)[Geo<DIM, K>::NP],
-                                               T* __restrict__ xf, const Mats<T>& m) {
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(LevelView fine, LevelView coarse,
+                                                                               const T* __restrict__ xc,
+                                                                               T* __restrict__ xf, Mats<T> m) {
+  using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
-  constexpr int N = G::N, M2 = G::M2, NJ = G::NJ;
-  constexpr int NZ = DIM == 3 ? N : 1;
-  int32_t gb[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) gb[j] = fine.gbase[(int64_t)j * fine.n_fam + f];
-  const uint32_t ow = fine.own[f];
-  T a[NZ * N * M2];
-#pragma unroll
-  for (int rr = 0; rr < NZ * N; ++rr)
-#pragma unroll
-    for (int i = 0; i < M2; ++i) {
-      T s = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) s += m.E[i * N + j] * u[rr * N + j];
-      a[rr * M2 + i] = s;
+  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP;
+  constexpr int NI = G::NI, NB = G::NB;
+  __shared__ T sout[FB * MFP];
+  __shared__ T su[FB * NP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sown[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < FB * NJ; e += S::THREADS) {
+    const int j = e / FB, fl = e % FB;
+    sgb[fl * NJ + j] = fl < nf ? fine.gbase[(int64_t)j * fine.n_fam + f0 + fl] : 0;
+  }
+  for (int fl = tid; fl < FB; fl += S::THREADS) sown[fl] = fl < nf ? fine.own[f0 + fl] : 0u;
+  for (int q = tid; q < G::MF; q += S::THREADS) {
+    const uint32_t c = G::code(q);
+    if (G::cr(c) != 0) {
+      const int b = G::bidx(q);
+      bq[b] = (uint16_t)q;
+      bc[b] = c;
     }
-  T b[NZ * M2 * M2];
+  }
+  // parent values
+  for (int e = tid; e < FB * NP; e += S::THREADS) {
+    const int fl = e / NP, j = e % NP;
+    T val = T(0);
+    if (fl < nf) {
+      const int64_t p = fine.parent[f0 + fl];
+      if (coarse.gbase) {
+        const int64_t F = p >> DIM;
+        const int cid = (int)(p & (CPF - 1));
+        const int jc[3] = {j % N, (j / N) % N, DIM == 3 ? j / (N * N) : 0};
+        int jj = 0, loc = 0, mul = 1, st = 1;
+        for (int a = 0; a < DIM; ++a) {
+          const int qa = ((cid >> a) & 1) * K + jc[a];
+          const int c = qa == 0 ? 0 : qa == 2 * K ? 2 : 1;
+          jj += c * mul;
+          mul *= 3;
+          if (c == 1) {
+            loc += (qa - 1) * st;
+            st *= G::S1;
+          }
+        }
+        val = xc[coarse.gbase[(int64_t)jj * coarse.n_fam + F] + loc];
+      } else {
+        val = xc[coarse.cmap[(int64_t)j * coarse.n_cells + p]];
+      }
+    }
+    su[fl * NP + j] = val;
+  }
+  __syncthreads();
+  {
+    // fine cell cid of family fl: v = (E_z ⊗ E_y ⊗ E_x) u on its sub-box
+    const int fl = tid / CPF, cid = tid % CPF;
+    const bool hx = cid & 1, hy = (cid >> 1) & 1, hz = DIM == 3 && ((cid >> 2) & 1);
+    T u[NP];
 #pragma unroll
-  for (int z = 0; z < NZ; ++z)
+    for (int j = 0; j < NP; ++j) u[j] = su[fl * NP + j];
+    constexpr int NZ = DIM == 3 ? N : 1;
+    // x: t[jz][jy][i] = sum_jx E[b_x k + i][jx] u[jz][jy][jx]
+    T t[NP];
 #pragma unroll
-    for (int x = 0; x < M2; ++x)
+    for (int r = 0; r < NZ * N; ++r)
 #pragma unroll
-      for (int i = 0; i < M2; ++i) {
+      for (int i = 0; i < N; ++i) {
         T s = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) s += m.E[i * N + j] * a[(z * N + j) * M2 + x];
-        b[(z * M2 + i) * M2 + x] = s;
+        for (int jx = 0; jx < N; ++jx) s += sel(hx, m.E[(K + i) * N + jx], m.E[i * N + jx]) * u[r * N + jx];
+        t[r * N + i] = s;
       }
-  constexpr int NZF = DIM == 3 ? M2 : 1;
+    // y
 #pragma unroll
-  for (int iz = 0; iz < NZF; ++iz) {
-    T old[M2 * M2];
+    for (int z = 0; z < NZ; ++z)
 #pragma unroll
-    for (int yx = 0; yx < M2 * M2; ++yx) old[yx] = xf[fam_node<DIM, K>(gb, iz * M2 * M2 + yx)];
+      for (int x = 0; x < N; ++x) {
+        T col[N];
 #pragma unroll
-    for (int yx = 0; yx < M2 * M2; ++yx) {
-      const int q = iz * M2 * M2 + yx;
-      T s;
-      if (DIM == 3) {
-        s = 0;
+        for (int jy = 0; jy < N; ++jy) col[jy] = t[(z * N + jy) * N + x];
 #pragma unroll
-        for (int j = 0; j < N; ++j) s += m.E[iz * N + j] * b[j * M2 * M2 + yx];
-      } else {
-        s = b[yx];
+        for (int i = 0; i < N; ++i) {
+          T s = 0;
+#pragma unroll
+          for (int jy = 0; jy < N; ++jy) s += sel(hy, m.E[(K + i) * N + jy], m.E[i * N + jy]) * col[jy];
+          t[(z * N + i) * N + x] = s;
+        }
       }
-      if ((ow >> G::cj(G::code(q))) & 1u) xf[fam_node<DIM, K>(gb, q)] = old[yx] + s;
+    // z
+    T v[NP];
+#pragma unroll
+    for (int yx = 0; yx < N * N; ++yx)
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) {
+        if (DIM == 3) {
+          T s = 0;
+#pragma unroll
+          for (int jz = 0; jz < N; ++jz) s += sel(hz, m.E[(K + i) * N + jz], m.E[i * N + jz]) * t[jz * N * N + yx];
+          v[i * N * N + yx] = s;
+        } else {
+          v[yx] = t[yx];
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = v[j];
+  }
+  __syncthreads();
+  // x_f += patch on the owned entities: interiors, then entity positions
+  {
+    int32_t node[S::ITI];
+    T old[S::ITI];
+    interior_nodes<DIM, K, T>(f0, nf, node);
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) old[it] = xf[node[it] >= 0 ? node[it] : 0];
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) {
+      const int e = tid + it * S::THREADS;
+      if (node[it] >= 0) xf[node[it]] = old[it] + sout[(e / NI) * MFP + G::iq(e % NI)];
     }
   }
-}
-
-// Prolongation from a level with families: one lane per fine family; the
-// parent cell's nodes are positions of the coarse family's patch, whose
-// entity bases the lane keeps in its own LDS row (indexed at run time).
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) fam_prolong(LevelView fine, LevelView coarse, const T* __restrict__ xc,
-                                                      T* __restrict__ xf, Mats<T> m) {
-  using G = Geo<DIM, K>;
-  constexpr int N = G::N, NJ = G::NJ, NP = G::NP;
-  __shared__ int32_t cg[kBlock * NJ];
-  const int64_t f = xcd_tid();
-  if (f >= fine.n_fam) return;
-  const int64_t p = fine.parent[f];
-  const int64_t F = p >> DIM;
-  const int cid = (int)(p & (G::CPF - 1));
-  int32_t* row = cg + threadIdx.x * NJ;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) row[j] = coarse.gbase[(int64_t)j * coarse.n_fam + F];
-  int b[3] = {(cid & 1) * K, ((cid >> 1) & 1) * K, DIM == 3 ? ((cid >> 2) & 1) * K : 0};
-  T u[NP];
+  for (int c0 = 0; c0 < S::ITB; c0 += S::CH) {
+    int32_t node[S::CH];
+    T val[S::CH], old[S::CH];
 #pragma unroll
-  for (int jn = 0; jn < NP; ++jn) {
-    const int jc[3] = {jn % N, (jn / N) % N, DIM == 3 ? jn / (N * N) : 0};
-    int j = 0, loc = 0, mul = 1, st = 1;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const int qa = b[a] + jc[a];
-      const int c = qa == 0 ? 0 : qa == 2 * K ? 2 : 1;
-      j += c * mul;
-      mul *= 3;
-      if (c == 1) {
-        loc += (qa - 1) * st;
-        st *= G::S1;
+    for (int k = 0; k < S::CH; ++k) {
+      const int it = c0 + k;
+      const int e = tid + it * S::THREADS;
+      node[k] = -1;
+      val[k] = T(0);
+      if (it < S::ITB && e < nf * NB) {
+        const int fl = e / NB, b = e % NB;
+        const uint32_t c = bc[b];
+        const int j = G::cj(c);
+        if ((sown[fl] >> j) & 1u) {
+          node[k] = sgb[fl * NJ + j] + G::cloc(c);
+          val[k] = sout[fl * MFP + bq[b]];
+        }
       }
     }
-    u[jn] = xc[row[j] + loc];
-  }
-  prolong_family<DIM, K, T>(fine, f, u, xf, m);
-}
-
-// Prolongation from level 0 (per-cell node map): one lane per level-1 family.
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) fam_prolong0(LevelView fine, LevelView coarse, const T* __restrict__ xc,
-                                                       T* __restrict__ xf, Mats<T> m) {
-  using G = Geo<DIM, K>;
-  const int64_t f = xcd_tid();
-  if (f >= fine.n_fam) return;
-  const int64_t p = fine.parent[f];
-  T u[G::NP];
 #pragma unroll
-  for (int j = 0; j < G::NP; ++j) u[j] = xc[coarse.cmap[(int64_t)j * coarse.n_cells + p]];
-  prolong_family<DIM, K, T>(fine, f, u, xf, m);
+    for (int k = 0; k < S::CH; ++k) old[k] = xf[node[k] >= 0 ? node[k] : 0];
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k)
+      if (node[k] >= 0) xf[node[k]] = old[k] + val[k];
+  }
 }
 
 }  // namespace dev

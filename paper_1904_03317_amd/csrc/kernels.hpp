@@ -473,6 +473,14 @@ __global__ void copy_from_levels(int64_t n, const int32_t* __restrict__ copy, co
   if (i < n) z[i] = double(lx[copy[i]]);
 }
 
+// z = level solution read back through the copy map, fused with the partial
+// sums of r.z (kFuseNPT nodes per thread, one partial per block)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const int32_t* __restrict__ copy,
+                                                               const T* __restrict__ lx, double* __restrict__ z,
+                                                               const double* __restrict__ r,
+                                                               double* __restrict__ part);
+
 // exact coarse solve: x0[S] = A0^{-1} d0[S] (FP64), other rows of x0 zero
 template <typename T>
 __global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, const double* __restrict__ ainv,
@@ -617,6 +625,51 @@ __global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restric
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     s += ri * ri;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// nodes per thread of the kernels fused with a dot product (kFuseNPT
+// consecutive block-strided nodes, unrolled so that their loads issue
+// together; one partial per block, summed in fixed order by cg_scalars)
+constexpr int kFuseNPT = 8;
+
+// leaf operator, pass 2, fused with the partial sums of p.q
+__global__ void __launch_bounds__(kBlock) seg_dir_dot(int64_t n, const int32_t* __restrict__ off,
+                                                      const double* __restrict__ E, const uint8_t* __restrict__ dir,
+                                                      double* __restrict__ q, const double* __restrict__ p,
+                                                      double* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kFuseNPT + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i < n) {
+      const double v = dir[i] ? 0.0 : seg_sum(off, E, i);
+      q[i] = v;
+      s += p[i] * v;
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const int32_t* __restrict__ copy,
+                                                               const T* __restrict__ lx, double* __restrict__ z,
+                                                               const double* __restrict__ r,
+                                                               double* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kFuseNPT + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i < n) {
+      const double v = double(lx[copy[i]]);
+      z[i] = v;
+      s += r[i] * v;
+    }
   }
   s = block_sum(s);
   if (threadIdx.x == 0) part[blockIdx.x] = s;

@@ -50,7 +50,8 @@ struct Problem {
   const int32_t* copy = nullptr;
   void *lx = nullptr, *lg = nullptr, *lt = nullptr, *ld = nullptr, *ldinv = nullptr;
   double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cb = nullptr;
-  double* E = nullptr;     // node-major slots of the two-pass operator (used as float or double)
+  double* E = nullptr;     // slots of the two-pass operators (used as float or double)
+  char* rbuf = nullptr;    // restricted parent-cell values of fine families (mg precision)
   double *scal = nullptr, *part = nullptr;
   double* ainv = nullptr;
   const int32_t* cidx = nullptr;

@@ -38,6 +38,11 @@ static unsigned grid1(int64_t n) {
   int64_t g = (n + dev::kBlock - 1) / dev::kBlock;
   return (unsigned)std::max<int64_t>(1, g);
 }
+// grid of the kernels fused with a dot product (one partial per block)
+static unsigned fuse_grid(int64_t n) {
+  const int64_t per = (int64_t)dev::kBlock * dev::kFuseNPT;
+  return (unsigned)std::max<int64_t>(1, (n + per - 1) / per);
+}
 static unsigned dot_grid(int64_t n) {
   return (unsigned)std::min<int64_t>(dev::kDotBlocks, std::max<int64_t>(1, (n + dev::kBlock - 1) / dev::kBlock));
 }
@@ -197,8 +202,13 @@ size_t plan_workspace(Problem& P, char* base) {
   e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
   if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
   P.E = pl.take<double>(e_max);
+  // restricted parent-cell values of the fine families of one level
+  int64_t fam_max = 0;
+  for (int l = 1; l <= L; ++l) fam_max = std::max<int64_t>(fam_max, M.levels[l].n_fam);
+  P.rbuf = pl.take<char>(size_t(fam_max) * M.npc * esz);
   P.scal = pl.take<double>(dev::kNumScalars + 8);
-  P.part = pl.take<double>(dev::kDotBlocks);
+  // dot partials: the fixed dot grid, or one per block of the fused kernels
+  P.part = pl.take<double>(std::max<int64_t>(dev::kDotBlocks, (N + dev::kBlock - 1) / dev::kBlock));
   int n0 = 0;
   for (auto f : M.levels[0].flags) n0 += f == kFlagS;
   if (n0 > 6000) fail(GMG_E_INVAL, "coarse level too large for the dense coarse solve (> 6000 free nodes)");
@@ -599,7 +609,7 @@ static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
 // I rows is restricted; after prolongation the interface values enter the
 // post-smoothing residuals through A^{SI}.
 template <typename T>
-static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
+static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool dot_rz) {
   const Maps& M = P.maps;
   const int L = (int)P.lv.size() - 1;
   const int64_t N = M.n_dofs;
@@ -641,7 +651,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
       ep.flags = W.v.flags;
       ep.c2 = T(1.0 / cheb_of(P, l - 1).theta);
       ep.smooth = 1;
-      op.restrict_fc(V.v, W.v, R + V.off, ep, E, mats<T>(P), s);
+      op.restrict_fc(V.v, W.v, R + V.off, ep, (T*)P.rbuf, E, mats<T>(P), s);
       op.sum(W.v, dev::kEpiRStart, E, ep, s);
     } else {
       op.restrict0(V.v, R + V.off, E, mats<T>(P), s);
@@ -656,14 +666,18 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s) {
     op.prolong(V.v, P.lv[l - 1].v, X + P.lv[l - 1].off, X + V.off, mats<T>(P), s);
     if (V.n_S > 0) smooth_steps<T>(P, l, 1, s);
   }
-  hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, X, z);
+  if (dot_rz)  // partial sums of r.z for the CG (the dot's grid)
+    hipLaunchKernelGGL(dev::copy_from_levels_dot<T>, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P.copy,
+                       (const T*)X, z, r, P.part);
+  else
+    hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, X, z);
 }
 
-static void vcycle_any(Problem& P, const double* r, double* z, hipStream_t s) {
+static void vcycle_any(Problem& P, const double* r, double* z, hipStream_t s, bool dot_rz = false) {
   if (P.opt.mg_precision == 32)
-    vcycle_t<float>(P, r, z, s);
+    vcycle_t<float>(P, r, z, s, dot_rz);
   else
-    vcycle_t<double>(P, r, z, s);
+    vcycle_t<double>(P, r, z, s, dot_rz);
 }
 
 void vcycle(Problem& P, const double* r, double* z, hipStream_t s) {
@@ -676,7 +690,7 @@ void vcycle(Problem& P, const double* r, double* z, hipStream_t s) {
 // fixed CG buffers r -> z when enabled
 static void precondition(Problem& P, hipStream_t s) {
   if (!P.opt.use_graph) {
-    vcycle_any(P, P.cr, P.cz, s);
+    vcycle_any(P, P.cr, P.cz, s, true);
     return;
   }
   if (!P.graph) {
@@ -684,7 +698,7 @@ static void precondition(Problem& P, hipStream_t s) {
     HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g;
     HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    vcycle_any(P, P.cr, P.cz, cs);
+    vcycle_any(P, P.cr, P.cz, cs, true);
     HIPCHECK(hipStreamEndCapture(cs, &g));
     HIPCHECK(hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0));
     HIPCHECK(hipGraphDestroy(g));
@@ -771,14 +785,16 @@ static void cg_enqueue_iteration(Problem& P) {
   const unsigned dg = dot_grid(N);
   double* sc = P.scal;
   if (C.timed) HIPCHECK(hipEventRecord(P.ev[2], s));
-  precondition(P, s);
+  precondition(P, s);  // z = B r, with the partial sums of r.z
   if (C.timed) HIPCHECK(hipEventRecord(P.ev[3], s));
-  hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cr, P.cz, P.part);
-  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 0);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)fuse_grid(N), P.part, sc, 0);
   hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
-  apply_leaf(P, P.cp, P.cq, false, s);
-  hipLaunchKernelGGL(dev::dot_partial, dim3(dg), dim3(dev::kBlock), 0, s, N, P.cp, P.cq, P.part);
-  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 1);
+  // q = A p, with the partial sums of p.q
+  P.kt->leaf_e(P.leaf, P.cp, P.E, false, P.m64, s);
+  hipLaunchKernelGGL(dev::seg_dir_dot, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff,
+                     (const double*)P.E,
+                     P.leaf.dir, P.cq, (const double*)P.cp, P.part);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)fuse_grid(N), P.part, sc, 1);
   hipLaunchKernelGGL(dev::update_xr, dim3(dg), dim3(dev::kBlock), 0, s, N, C.u, P.cr, P.cp, P.cq, sc, P.part);
   hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 2);
   HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
