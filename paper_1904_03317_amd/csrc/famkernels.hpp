@@ -112,7 +112,10 @@ struct FamShape {
   // padded patch length: odd in 4-byte words so that families fall on
   // different LDS banks
   static constexpr int MFP = sizeof(T) == 4 ? (MF % 2 ? MF + 2 : MF + 1) : MF + 1;
-  static constexpr int budget = K >= 3 ? 163840 : 81920;
+  // LDS budget per workgroup: two workgroups per CU at k <= 2 (FP64 half
+  // that: its register count allows two waves per SIMD anyway, and smaller
+  // workgroups overlap their memory phases better), one at k >= 3
+  static constexpr int budget = K >= 3 ? 163840 : sizeof(T) == 8 ? 40960 : 81920;
   static constexpr int fixed = G::NB * 14 + 256;
   static constexpr int fb_lds = (budget - fixed) / (2 * MFP * (int)sizeof(T) + NJ * 4 + 4);
   static constexpr int fb_cap = 256 / CPF;
