@@ -64,19 +64,21 @@ def roofline(r, traffic):
                       "traffic": traffic.get("apply_bytes_per_launch") if traffic else None}}
 
 
-def cpu_baseline(g_sample=2, min_seconds=12.0):
+def cpu_baseline(name="C2", min_seconds=12.0):
     """The oracle (plain numpy/scipy, FP64, one thread) on the same recipe
-    at a reduced number of global refinements: DoFs/s of its CG solve,
-    repeated until about min_seconds of solve time."""
+    at a reduced number of global refinements (2 for Q2, 1 for Q3/Q4): DoFs/s
+    of its CG solve, repeated until about min_seconds of solve time."""
     from threadpoolctl import threadpool_limits
 
     import gmg_inputs as gi
     from oracle import problem
 
-    w = gi.workload("C2", g=g_sample)
+    g_sample = 2 if gi.workload(name).degree == 2 else 1
+    w = gi.workload(name, g=g_sample)
     with threadpool_limits(limits=1):
         f = problem.build_forest(w.recipe)
-        op = problem.setup(f, w.degree)
+        coeff = gi.coeff_cells(w.coeff, *f.leaves_arrays()) if w.coeff != "one" else None
+        op = problem.setup(f, w.degree, coeff=coeff)
         fn = gi.rhs_nodal(w.rhs, op.n_dofs)
         reps, t = 0, 0.0
         while t < min_seconds or reps < 3:
@@ -85,7 +87,7 @@ def cpu_baseline(g_sample=2, min_seconds=12.0):
             t += time.perf_counter() - t0
             reps += 1
     return {"value": op.n_dofs * reps / t, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
-            "sample": f"C2 recipe with g={g_sample} global refinements (N={op.n_dofs}, Q2): oracle FP64 CG "
+            "sample": f"{name} recipe with g={g_sample} global refinements (N={op.n_dofs}, Q{w.degree}): oracle FP64 CG "
                       f"solve ({it} iterations) repeated {reps} times, {t:.1f} s, set-up excluded, "
                       f"BLAS limited to 1 thread"}
 
@@ -106,7 +108,7 @@ def build_request_meshes(ids, threads=8):
         return list(ex.map(one, ids))
 
 
-def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7):
+def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_g=None):
     """Open-loop serving stream of unit-cube Q2 requests (FP32 V-cycle, FP64
     CG) with Poisson arrivals at `load` times the throughput measured in a
     closed-loop warm-up.  Latency = completion - arrival on the server clock."""
@@ -120,6 +122,13 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7):
     warm_meshes = build_request_meshes(range(10000, 10000 + warm), threads)
     meshes = build_request_meshes(range(n_req), threads)
     log(f"serve: {n_req} request meshes built ({time.perf_counter() - t0:.1f} s)")
+    big = None
+    if big_g is not None and n_req > 128:
+        # the C5 job (Q3, checkerboard coefficient) as request 128
+        wb = gi.workload("C5", g=big_g)
+        bm = gmg.build_mesh(wb.recipe)
+        big = (bm, gmg.options(degree=wb.degree, mg_precision=32), gi.coeff_cells(wb.coeff, *bm.leaves()))
+        log(f"serve: C5 job with g={big_g}: {bm.n_leaves} leaves")
     S = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=slots, host_threads=threads)
     # closed loop: all warm-up requests at once
     c0 = S.stats()["clock"]
@@ -139,7 +148,10 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7):
         delay = arr[k] - (time.perf_counter() - w0)
         if delay > 0:
             time.sleep(delay)
-        ids.append(S.submit(m, opts))
+        if big is not None and k == 128:
+            ids.append(S.submit(big[0], big[1], coeff=big[2]))
+        else:
+            ids.append(S.submit(m, opts))
     lat, its, dofs, status = [], [], 0.0, []
     end = start
     for i in ids:
@@ -156,11 +168,15 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7):
     S.close()
     lat = np.array(lat)
     span = end - start
+    big_info = None
+    if big is not None:
+        big_info = {"request": 128, "latency_s": float(lat[128]), "dofs": None}
     return {"requests": n_req, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "arrival_rate_rps": rate, "throughput_rps": n_req / span,
             "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
             "cg_iterations_min": int(min(its)), "failed": int(sum(1 for s in status if s != 0)),
             "slots": slots, "host_threads": threads, "arena_peak_gb": st["arena_peak"] / 2 ** 30,
+            "large_job": big_info,
             "latency_includes": "queueing + host set-up + device set-up + solve + copy-back"}
 
 
@@ -169,10 +185,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--g", type=int, default=5, help="global refinements of the Fichera recipe")
+    ap.add_argument("--config", default="C2", choices=["C2", "C3-Q2", "C3-Q4", "C5"],
+                    help="workload (C2: Fichera Q2 ~2e7 DoFs, FP64 throughout; C3: ~1e8 DoFs Q2/Q4 and C5: Q3 "
+                         "checkerboard, both with the FP32 V-cycle as the reported value)")
+    ap.add_argument("--g", type=int, default=None, help="global refinements (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-big", type=int, default=None, metavar="G",
+                    help="add the C5 job (Q3 checkerboard, G global refinements) as request 128 of the stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -184,21 +205,35 @@ def main():
     import gmg_inputs as gi
     from paper_1904_03317_amd import gmg
 
-    w = gi.workload("C2", g=args.g)
+    w = gi.workload(args.config, g=args.g)
+    g_used = w.recipe.globals_
+    if w.name != "C2" or args.serve_big is not None:
+        # the large set-ups take minutes on the host: print their phases
+        os.environ.setdefault("GMG_TRACE", "1")
     t0 = time.perf_counter()
     mesh = gmg.build_mesh(w.recipe)
-    log(f"mesh: {mesh.n_leaves} leaves ({time.perf_counter() - t0:.1f} s)")
+    log(f"{w.name}: mesh {mesh.n_leaves} leaves ({time.perf_counter() - t0:.1f} s)")
+    coeff = gi.coeff_cells(w.coeff, *mesh.leaves()) if w.coeff != "one" else None
 
     # calibration copy of a known size for the HBM traffic counters
-    # (FETCH_SIZE / WRITE_SIZE of this copy divided by 256 MiB is the scale)
+    # (FETCH_SIZE / WRITE_SIZE of this copy divided by 256 MiB is the scale),
+    # then the same copy timed: the measured copy bandwidth beside the spec
     cal_a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
     cal_b = torch.empty_like(cal_a)
     cal_b.copy_(cal_a)
     torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        cal_b.copy_(cal_a)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cal_a.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    log(f"device copy 256 MiB: {copy_gbs:.0f} GB/s")
     del cal_a, cal_b
     results = {}
     t0 = time.perf_counter()
-    base = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=64))
+    base = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=64), coeff=coeff)
     t_maps = time.perf_counter() - t0
     for prec in ([64] if args.no_fp32 else [64, 32]):
         P = base.clone(gmg.options(degree=w.degree, mg_precision=prec))
@@ -262,8 +297,12 @@ def main():
         del f, x, y
         torch.cuda.empty_cache()
 
-    r64 = results[64]
-    value = r64["N"] / (r64["ms"] * 1e-3)
+    # the value is the workload's own precision (C2: FP64 throughout; C3, C5:
+    # FP32 V-cycle inside FP64 CG); the other precision on the same mesh beside it
+    prim = w.mg_precision if w.mg_precision in results else 64
+    r = results[prim]
+    value = r["N"] / (r["ms"] * 1e-3)
+    desc = {"C2": "Q2", "C3-Q2": "Q2", "C3-Q4": "Q4", "C5": "Q3, checkerboard a in {1, 100}"}[w.name]
     out = {
         "metric": METRIC,
         "value": value,
@@ -271,36 +310,41 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r64["ms"],
+        "ms_per_step": r["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prim == 64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"Fichera corner 3D, Q2, {args.g} global + 4 adaptive cycles (corner + 5% "
-                               f"seeded random), f = 1 + N(0,0.1) nodal, FP64-MG CG to 1e-10",
-                   "dofs": r64["N"], "levels": r64["levels"], "cg_iterations": r64["its"],
-                   "final_rel_residual": r64["res"], "vcycle_ms": r64["vcycle_ms"],
-                   "setup_maps_s": r64["maps_s"], "setup_device_s": r64["bind_s"]},
+        "config": {"workload": f"{w.name}: Fichera corner 3D, {desc}, {g_used} global + 4 adaptive cycles "
+                               f"(corner + 5% seeded random), f = {'1 + N(0,0.1) nodal' if w.rhs == 'noise' else '1'}, "
+                               f"FP{prim}-MG CG to 1e-10",
+                   "dofs": r["N"], "levels": r["levels"], "cg_iterations": r["its"],
+                   "final_rel_residual": r["res"], "vcycle_ms": r["vcycle_ms"],
+                   "vcycle_dofs_per_s": r["N"] / (r["vcycle_ms"] * 1e-3),
+                   "setup_maps_s": r["maps_s"], "setup_device_s": r["bind_s"]},
     }
-    traffic = measured_traffic()
-    out["roofline"] = roofline(r64, traffic.get("fp64"))
-    if 32 in results:
-        r32 = results[32]
-        d = float(np.linalg.norm(r32["u"] - r64["u"]) / np.linalg.norm(r64["u"]))
-        out["fp32_mg"] = {"value": r32["N"] / (r32["ms"] * 1e-3), "unit": "DoFs/s", "ms_per_step": r32["ms"],
-                          "cg_iterations": r32["its"], "final_rel_residual": r32["res"],
-                          "vcycle_ms": r32["vcycle_ms"], "rel_diff_vs_fp64_mg": d,
-                          "speedup_vs_fp64_mg": r64["ms"] / r32["ms"],
-                          "roofline": roofline(r32, traffic.get("fp32"))}
+    traffic = measured_traffic() if w.name == "C2" and g_used == 5 else {}
+    out["roofline"] = roofline(r, traffic.get(f"fp{prim}"))
+    out["roofline"]["measured_copy_gbs"] = copy_gbs
+    other = 32 if prim == 64 else 64
+    if other in results:
+        o = results[other]
+        d = float(np.linalg.norm(o["u"] - r["u"]) / np.linalg.norm(results[64]["u"]))
+        out[f"fp{other}_mg"] = {"value": o["N"] / (o["ms"] * 1e-3), "unit": "DoFs/s", "ms_per_step": o["ms"],
+                                "cg_iterations": o["its"], "final_rel_residual": o["res"],
+                                "vcycle_ms": o["vcycle_ms"], "vcycle_dofs_per_s": o["N"] / (o["vcycle_ms"] * 1e-3),
+                                "rel_diff_vs_fp64_mg": d, "fp32_speedup_over_fp64": (
+                                    results[64]["ms"] / results[32]["ms"] if 32 in results else None),
+                                "roofline": roofline(o, traffic.get(f"fp{other}"))}
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
-        out["serve"] = serve_leg(args.serve)
+        out["serve"] = serve_leg(args.serve, big_g=args.serve_big)
         log(f"serve: p50 {out['serve']['p50_s'] * 1e3:.1f} ms p99 {out['serve']['p99_s'] * 1e3:.1f} ms "
             f"{out['serve']['throughput_rps']:.1f} req/s")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(w.name)
     print(json.dumps(out), flush=True)
 
 

@@ -140,8 +140,8 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
     P.opt = *opts;
     P.kt = gmg::kernel_table(m->f->dim(), opts->degree);
     REQUIRE(P.kt, "no kernels for this dimension/degree");
-    P.maps = gmg::build_maps(*m->f, opts->degree, coeff);
-    const gmg::FE1D& fe = P.maps.fe;
+    P.maps = std::make_shared<const gmg::Maps>(gmg::build_maps(*m->f, opts->degree, coeff));
+    const gmg::FE1D& fe = P.maps->fe;
     for (int i = 0; i < 25; ++i) {
       P.m64.M[i] = fe.M[i];
       P.m64.K[i] = fe.K[i];
@@ -161,7 +161,7 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
 int gmg_problem_clone(gmg_problem src, const gmg_options* opts, gmg_problem* out) {
   return guard([&] {
     REQUIRE(src && opts && out, "null argument");
-    REQUIRE(opts->degree == src->P.maps.k, "clone must keep the degree");
+    REQUIRE(opts->degree == src->P.maps->k, "clone must keep the degree");
     REQUIRE(opts->mg_precision == 32 || opts->mg_precision == 64, "mg_precision must be 32 or 64");
     REQUIRE(opts->cheb_degree >= 1 && opts->cheb_degree <= 64, "cheb_degree must be 1..64");
     REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "0 < cheb_lo < cheb_hi required");
@@ -183,7 +183,7 @@ int gmg_problem_clone(gmg_problem src, const gmg_options* opts, gmg_problem* out
 int gmg_problem_info(gmg_problem p, gmg_info* o) {
   return guard([&] {
     REQUIRE(p && o, "null argument");
-    const gmg::Maps& M = p->P.maps;
+    const gmg::Maps& M = *p->P.maps;
     std::memset(o, 0, sizeof(*o));
     o->dim = M.dim;
     o->degree = M.k;
@@ -208,7 +208,7 @@ int gmg_problem_info(gmg_problem p, gmg_info* o) {
 int gmg_problem_array(gmg_problem p, int which, int level, const void** ptr, int64_t* count) {
   return guard([&] {
     REQUIRE(p && ptr && count, "null argument");
-    const gmg::Maps& M = p->P.maps;
+    const gmg::Maps& M = *p->P.maps;
     auto lev = [&]() -> const gmg::LevelData& {
       REQUIRE(level >= 0 && level < (int)M.levels.size(), "level out of range");
       return M.levels[level];
@@ -284,7 +284,7 @@ int gmg_solve(gmg_problem p, const double* f, double* u, int32_t* iters, double*
     REQUIRE(P.bound, "problem not bound");
     const double* src = f;
     if (!f) {
-      gmg::set_constant(P.cx, P.maps.n_dofs, 1.0, s);
+      gmg::set_constant(P.cx, P.maps->n_dofs, 1.0, s);
       src = P.cx;
     }
     gmg::apply_leaf(P, src, P.cb, true, s);

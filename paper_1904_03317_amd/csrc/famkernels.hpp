@@ -131,6 +131,41 @@ struct FamShape {
   static constexpr int ITB = (G::NB * FB + THREADS - 1) / THREADS;
 };
 
+// Operator shape in 3D at k >= 3, where a cell's (k+1)^3 values and their
+// products no longer fit one lane's registers: the threads of a workgroup
+// share the sum-factorized contractions of all cells of its families, one
+// thread per 1D line of a cell and direction, through two LDS arrays of
+// per-cell intermediates; each patch position then sums the values of the
+// cells containing it, in ascending child order.
+template <int DIM, int K>
+inline constexpr bool kCoopOp = DIM == 3 && K >= 3;
+
+template <int DIM, int K, typename T>
+struct CoopShape {
+  using G = Geo<DIM, K>;
+  static constexpr int N = G::N, MF = G::MF, CPF = G::CPF, NJ = G::NJ;
+  static constexpr int MFP = FamShape<DIM, K, T>::MFP;
+  // per-cell intermediates, x fastest, rows padded to an odd length so that
+  // the lines along x of consecutive threads fall on different LDS banks
+  static constexpr int NXP = N % 2 ? N : N + 1;
+  static constexpr int CS = NXP * N * N;
+  static constexpr int FS = CPF * CS;  // per family; the output patch reuses the second array
+  static constexpr int THREADS = 256;
+  // LDS per workgroup: small, so that several workgroups per CU overlap
+  // their memory phases (with waves_per_eu below; measured best among
+  // budgets of 27-160 KB and 128-512 threads)
+  static constexpr int budget = 32768;
+  static constexpr int fixed = G::NB * 14 + 256;
+  static constexpr int FB = (budget - fixed) / ((MFP + 2 * FS) * (int)sizeof(T) + NJ * 4 + 4);
+  static constexpr int CH = 5;
+  static constexpr int ITI = (G::NI * FB + THREADS - 1) / THREADS;
+  static constexpr int ITB = (G::NB * FB + THREADS - 1) / THREADS;
+  static constexpr int NL = N * N;  // lines per cell and direction
+  static constexpr int ITL = (FB * CPF * NL + THREADS - 1) / THREADS;
+  static constexpr int ITQ = (FB * MF + THREADS - 1) / THREADS;
+  static_assert(FB >= 1 && FS >= MFP, "cooperative operator shape");
+};
+
 // Operator slot of a shared-entity position (r >= 1) of a family whose
 // entity base is gb: eoff[r] + (gb - sec[r]) 2^r + pos size_r + loc.  All
 // terms but gb 2^r depend on the position only and are tabulated per
@@ -227,9 +262,8 @@ __device__ __forceinline__ void epi_batch(const Epi<T>& ep, const int32_t (&node
 
 // interior nodes of the workgroup's families: node f0 NI + e for e < nf NI
 // (contiguous), else -1
-template <int DIM, int K, typename T>
-__device__ __forceinline__ void interior_nodes(int64_t f0, int nf, int32_t (&node)[FamShape<DIM, K, T>::ITI]) {
-  using S = FamShape<DIM, K, T>;
+template <int DIM, int K, typename T, typename S = FamShape<DIM, K, T>>
+__device__ __forceinline__ void interior_nodes(int64_t f0, int nf, int32_t (&node)[S::ITI]) {
   constexpr int NI = Geo<DIM, K>::NI;
 #pragma unroll
   for (int it = 0; it < S::ITI; ++it) {
@@ -262,10 +296,9 @@ __device__ __forceinline__ void epi_shared(const Epi<T>& ep, int64_t i, T ax) {
 
 // stage the entity bases and exclusivity bits of the workgroup's families
 // and the table of entity positions (position, code, slot part)
-template <int DIM, int K, typename T>
+template <int DIM, int K, typename T, typename S = FamShape<DIM, K, T>>
 __device__ __forceinline__ void stage_bases(const LevelView& v, int64_t f0, int32_t* sgb, uint32_t* sex,
                                             uint16_t* bq, uint32_t* bc, int64_t* bo) {
-  using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   for (int e = threadIdx.x; e < S::FB * G::NJ; e += S::THREADS) {
     const int j = e / S::FB, fl = e % S::FB;
@@ -374,14 +407,12 @@ __device__ __forceinline__ bool family_owner(int cid, int j) {
 // Output of a family patch held in LDS (sout): interior nodes and nodes of
 // exclusive entities through the epilogue, shared entities to their slots.
 // xo from sin (CHEB only).
-template <int DIM, int K, typename T, int EPI>
+template <int DIM, int K, typename T, int EPI, typename S = FamShape<DIM, K, T>>
 __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf, const T* sout, const T* sin,
                                           const int32_t* sgb, const uint32_t* sex, const uint16_t* bq,
                                           const uint32_t* bc, const int64_t* bo, const Epi<T>& ep,
-                                          T* __restrict__ E,
-                                          const int32_t (&inode)[FamShape<DIM, K, T>::ITI],
-                                          EpiOps<T, FamShape<DIM, K, T>::ITI>& iops) {
-  using S = FamShape<DIM, K, T>;
+                                          T* __restrict__ E, const int32_t (&inode)[S::ITI],
+                                          EpiOps<T, S::ITI>& iops) {
   using G = Geo<DIM, K>;
   constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
   const int tid = threadIdx.x;
@@ -437,10 +468,9 @@ __device__ __forceinline__ void patch_out(const LevelView& v, int64_t f0, int nf
 // node patches of the workgroup's families into LDS (sin[fl MFP + q]):
 // interiors by coalesced loads of a contiguous block, entity positions
 // through the staged entity bases; all loads issued before the LDS stores
-template <int DIM, int K, typename T>
+template <int DIM, int K, typename T, typename S = FamShape<DIM, K, T>>
 __device__ __forceinline__ void gather_patch(int64_t f0, int nf, const T* __restrict__ xin, const int32_t* sgb,
                                              const uint16_t* bq, const uint32_t* bc, T* sin) {
-  using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
   const int tid = threadIdx.x;
@@ -544,6 +574,152 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   }
   __syncthreads();
   patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
+}
+
+// Pass 1 in 3D at k >= 3 (same contract as fam_op).  Per cell, with the
+// cell scale s (coefficient times h): a = M u and b = K u along z; c = M a
+// and f = K a + M b along y; s (K c + M f) along x, which is s times
+// (K x M x M + M x K x M + M x M x K) u (Sec. 4.1, sum factorization).
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__((CoopShape<DIM, K, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(5)))
+    fam_op_coop(LevelView v, const T* __restrict__ xin, Epi<T> ep, T* __restrict__ E, Mats<T> m) {
+  using S = CoopShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2, MF = G::MF, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ;
+  constexpr int NB = G::NB, NXP = S::NXP, CS = S::CS, FS = S::FS, NL = S::NL, TH = S::THREADS;
+  static_assert(DIM == 3, "cooperative operator is 3D");
+  __shared__ T sin[FB * MFP];
+  __shared__ T ta[FB * FS];
+  __shared__ T tb[FB * FS];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
+  T* sout = tb;  // family patches of the output, once tb is no longer needed
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(v.n_fam - f0 < FB ? v.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  int32_t inode[S::ITI];
+  interior_nodes<DIM, K, T, S>(f0, nf, inode);
+  EpiOps<T, S::ITI> iops;
+  epi_load<T, EPI, S::ITI, false>(ep, inode, iops);
+  stage_bases<DIM, K, T, S>(v, f0, sgb, sex, bq, bc, bo);
+  __syncthreads();
+  const int nline = nf * CPF * NL;
+  if (EPI != kEpiDiag) {
+    gather_patch<DIM, K, T, S>(f0, nf, xin, sgb, bq, bc, sin);
+    __syncthreads();
+    // lines along z
+#pragma unroll
+    for (int it = 0; it < S::ITL; ++it) {
+      const int u = tid + it * TH;
+      if (u < nline) {
+        const int fl = u / (CPF * NL), r = u % (CPF * NL), cid = r / NL, p = r % NL;
+        const int px = p % N, py = p / N;
+        const T* src = sin + fl * MFP + cell_patch_pos<DIM, K>(cid, px + N * py);
+        T x[N];
+#pragma unroll
+        for (int z = 0; z < N; ++z) x[z] = src[z * M2 * M2];
+        T* da = ta + fl * FS + cid * CS + px + NXP * py;
+        T* db = tb + fl * FS + cid * CS + px + NXP * py;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          T a = T(0), b = T(0);
+#pragma unroll
+          for (int z = 0; z < N; ++z) {
+            a += m.M[i * N + z] * x[z];
+            b += m.K[i * N + z] * x[z];
+          }
+          da[i * NXP * N] = a;
+          db[i * NXP * N] = b;
+        }
+      }
+    }
+    __syncthreads();
+    // lines along y, in place
+#pragma unroll
+    for (int it = 0; it < S::ITL; ++it) {
+      const int u = tid + it * TH;
+      if (u < nline) {
+        const int fl = u / (CPF * NL), r = u % (CPF * NL), cid = r / NL, p = r % NL;
+        const int px = p % N, pz = p / N;
+        T* pa = ta + fl * FS + cid * CS + px + NXP * N * pz;
+        T* pb = tb + fl * FS + cid * CS + px + NXP * N * pz;
+        T a[N], b[N];
+#pragma unroll
+        for (int y = 0; y < N; ++y) {
+          a[y] = pa[y * NXP];
+          b[y] = pb[y * NXP];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          T c = T(0), f = T(0);
+#pragma unroll
+          for (int y = 0; y < N; ++y) {
+            c += m.M[i * N + y] * a[y];
+            f += m.K[i * N + y] * a[y] + m.M[i * N + y] * b[y];
+          }
+          pa[i * NXP] = c;
+          pb[i * NXP] = f;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // lines along x: the scaled cell values (diagonal: the scaled diagonal of
+  // the cell matrix)
+#pragma unroll
+  for (int it = 0; it < S::ITL; ++it) {
+    const int u = tid + it * TH;
+    if (u < nline) {
+      const int fl = u / (CPF * NL), r = u % (CPF * NL), cid = r / NL, p = r % NL;
+      const int py = p % N, pz = p / N;
+      T* pa = ta + fl * FS + cid * CS + NXP * (py + N * pz);
+      const T* pb = tb + fl * FS + cid * CS + NXP * (py + N * pz);
+      const T sc = T(v.scale ? v.scale[(f0 + fl) * CPF + cid] : v.scale0);
+      if (EPI == kEpiDiag) {
+        const T my = m.M[py * N + py], mz = m.M[pz * N + pz], ky = m.K[py * N + py], kz = m.K[pz * N + pz];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          pa[i] = sc * (m.K[i * N + i] * my * mz + m.M[i * N + i] * (ky * mz + my * kz));
+      } else {
+        T c[N], f[N];
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+          c[x] = pa[x];
+          f[x] = pb[x];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          T o = T(0);
+#pragma unroll
+          for (int x = 0; x < N; ++x) o += m.K[i * N + x] * c[x] + m.M[i * N + x] * f[x];
+          pa[i] = sc * o;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // sum over the cells of the family containing each patch position
+#pragma unroll
+  for (int it = 0; it < S::ITQ; ++it) {
+    const int e = tid + it * TH;
+    if (e < nf * MF) {
+      const int fl = e / MF, q = e % MF;
+      const int qx = q % M2, qy = (q / M2) % M2, qz = q / (M2 * M2);
+      T s = T(0);
+#pragma unroll
+      for (int cid = 0; cid < CPF; ++cid) {
+        const int jx = qx - (cid & 1) * K, jy = qy - ((cid >> 1) & 1) * K, jz = qz - ((cid >> 2) & 1) * K;
+        if (jx >= 0 && jx <= K && jy >= 0 && jy <= K && jz >= 0 && jz <= K)
+          s += ta[fl * FS + cid * CS + jx + NXP * (jy + N * jz)];
+      }
+      sout[fl * MFP + q] = s;
+    }
+  }
+  __syncthreads();
+  patch_out<DIM, K, T, EPI, S>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
 }
 
 // ------------------------------------------------------------------ pass 2

@@ -28,9 +28,17 @@ struct Inst {
   template <typename T, int EPI>
   static void op_launch(const LevelView& v, const T* x, const dev::Epi<T>& ep, T* E, const MatsH<T>& m,
                         hipStream_t s) {
-    using S = dev::FamShape<DIM, K, T>;
-    const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
-    hipLaunchKernelGGL((dev::fam_op<DIM, K, T, EPI>), dim3(g), dim3(S::THREADS), 0, s, v, x, ep, E, to_dev(m));
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      using S = dev::CoopShape<DIM, K, T>;
+      const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_op_coop<DIM, K, T, EPI>), dim3(g), dim3(S::THREADS), 0, s, v, x, ep, E,
+                         to_dev(m));
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      const unsigned g = (unsigned)((v.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_op<DIM, K, T, EPI>), dim3(g), dim3(S::THREADS), 0, s, v, x, ep, E,
+                         to_dev(m));
+    }
   }
   template <typename T>
   static void op(const LevelView& v, int epi, const T* x, const dev::Epi<T>& ep, T* E, const MatsH<T>& m,

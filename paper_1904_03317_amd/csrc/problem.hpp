@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <vector>
 
 #include "../../include/gmg.h"
@@ -32,7 +33,7 @@ struct CgState {
 
 struct Problem {
   gmg_options opt{};
-  Maps maps;
+  std::shared_ptr<const Maps> maps;   // shared by clones (read-only after creation)
   const KernelTable* kt = nullptr;
   MatsH<float> m32{};
   MatsH<double> m64{};

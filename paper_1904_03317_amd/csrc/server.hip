@@ -136,7 +136,7 @@ struct Server {
 
 namespace {
 
-size_t request_bytes(const Problem& P) { return P.ws_need + 2 * (size_t(P.maps.n_dofs) * 8 + 256); }
+size_t request_bytes(const Problem& P) { return P.ws_need + 2 * (size_t(P.maps->n_dofs) * 8 + 256); }
 
 void fail_request(Server& S, Request* r, int code, const std::string& msg) {
   r->state = kFailed;
@@ -172,8 +172,9 @@ void worker_loop(Server* S) {
         P->opt = r->opt;
         P->kt = kernel_table(r->mesh->dim(), r->opt.degree);
         if (!P->kt) fail(GMG_E_INVAL, "no kernels for this dimension/degree");
-        P->maps = build_maps(*r->mesh, r->opt.degree, r->coeff.empty() ? nullptr : r->coeff.data());
-        const FE1D& fe = P->maps.fe;
+        P->maps = std::make_shared<const Maps>(
+            build_maps(*r->mesh, r->opt.degree, r->coeff.empty() ? nullptr : r->coeff.data()));
+        const FE1D& fe = P->maps->fe;
         for (int i = 0; i < 25; ++i) {
           P->m64.M[i] = fe.M[i];
           P->m64.K[i] = fe.K[i];
@@ -204,7 +205,7 @@ void worker_loop(Server* S) {
         char* base = S->arena_base + r->arena_off;
         bind_problem(P, base, P.ws_need, s);
         P.opt.use_graph = 1;
-        const int64_t N = P.maps.n_dofs;
+        const int64_t N = P.maps->n_dofs;
         size_t tail = (P.ws_need + 255) & ~size_t(255);
         r->d_f = reinterpret_cast<double*>(base + tail);
         r->d_u = reinterpret_cast<double*>(base + tail + ((size_t(N) * 8 + 255) & ~size_t(255)));
@@ -284,9 +285,9 @@ void scheduler_loop(Server* S) {
       hipStream_t s = S->streams[r->slot];
       r->iterations = P.cg.it;
       r->hist.assign(P.cg.hist.begin(), P.cg.hist.begin() + P.cg.it + 1);
-      r->u_host.resize(P.maps.n_dofs);
+      r->u_host.resize(P.maps->n_dofs);
       if (status >= 0) {
-        hipError_t e1 = hipMemcpyAsync(r->u_host.data(), r->d_u, P.maps.n_dofs * sizeof(double),
+        hipError_t e1 = hipMemcpyAsync(r->u_host.data(), r->d_u, P.maps->n_dofs * sizeof(double),
                                        hipMemcpyDeviceToHost, s);
         hipError_t e2 = hipStreamSynchronize(s);
         if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -304,7 +305,7 @@ void scheduler_loop(Server* S) {
       r->state = status >= 0 ? kDone : kFailed;
       if (status >= 0) {
         ++S->completed;
-        S->dofs_done += (double)P.maps.n_dofs;
+        S->dofs_done += (double)P.maps->n_dofs;
       } else {
         ++S->failed;
       }

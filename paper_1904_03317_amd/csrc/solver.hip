@@ -117,7 +117,7 @@ struct Planner {
 }  // namespace
 
 size_t plan_workspace(Problem& P, char* base) {
-  Maps& M = P.maps;
+  const Maps& M = *P.maps;
   Planner pl{base};
   const size_t esz = P.opt.mg_precision == 32 ? 4 : 8;
   const int L = (int)M.levels.size() - 1;
@@ -127,7 +127,7 @@ size_t plan_workspace(Problem& P, char* base) {
   P.max_level_dofs = 0;
   const int nj = M.dim == 3 ? 27 : 9, cpf = 1 << M.dim;
   for (int l = 0; l <= L; ++l) {
-    LevelData& D = M.levels[l];
+    const LevelData& D = M.levels[l];
     DevLevel& V = P.lv[l];
     V.v.n_cells = D.n_cells;
     V.v.n_dofs = D.n_dofs;
@@ -308,8 +308,8 @@ double estimate_lambda(Problem& P, int l, hipStream_t s) {
   hipLaunchKernelGGL(dev::make_dinv<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags, dinv);
   {
     // start vector (i mod 12) - 5.5 on the S rows, i the level DoF id
-    const LevelData& D = P.maps.levels[l];
-    const std::vector<int32_t>& perm = P.maps.layouts[l].perm;
+    const LevelData& D = P.maps->levels[l];
+    const std::vector<int32_t>& perm = P.maps->layouts[l].perm;
     std::vector<double> r0(n, 0.0);
     for (int64_t i = 0; i < n; ++i)
       if (D.flags[i] == kFlagS) r0[perm[i]] = double(i % 12) - 5.5;
@@ -414,7 +414,7 @@ std::vector<double> coarse_inverse(const Maps& M, std::vector<int32_t>& idx) {
 }  // namespace
 
 void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
-  Maps& M = P.maps;
+  const Maps& M = *P.maps;
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) fail(GMG_E_INVAL, "workspace must be 256-byte aligned");
   if (bytes < P.ws_need) fail(GMG_E_INVAL, "workspace too small");
   plan_workspace(P, (char*)ws);
@@ -430,7 +430,7 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
   const bool f32 = P.opt.mg_precision == 32;
   const int nj = M.dim == 3 ? 27 : 9, cpf = 1 << M.dim;
   for (int l = 0; l <= L; ++l) {
-    LevelData& D = M.levels[l];
+    const LevelData& D = M.levels[l];
     DevLevel& V = P.lv[l];
     if (V.v.scale) {
       std::vector<double> sc(D.n_cells);
@@ -548,7 +548,7 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
 // hanging-node constraints applied inside the cells (pass 1), per-DoF sums
 // (pass 2)
 void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s) {
-  const int64_t N = P.maps.n_dofs;
+  const int64_t N = P.maps->n_dofs;
   P.kt->leaf_e(P.leaf, x, P.E, mass, P.m64, s);
   hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.dir, y);
 }
@@ -610,7 +610,7 @@ static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
 // post-smoothing residuals through A^{SI}.
 template <typename T>
 static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool dot_rz) {
-  const Maps& M = P.maps;
+  const Maps& M = *P.maps;
   const int L = (int)P.lv.size() - 1;
   const int64_t N = M.n_dofs;
   T *X = (T*)P.lx, *G = (T*)P.lg, *R = (T*)P.lt, *Dd = (T*)P.ld, *Di = (T*)P.ldinv;
@@ -754,7 +754,7 @@ void apply_level_hook(Problem& P, int l, int variant, const void* x, void* y, hi
 // r.r, read-back).  The scalars alpha, beta, rho stay on the device.
 void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed) {
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
-  const int64_t N = P.maps.n_dofs;
+  const int64_t N = P.maps->n_dofs;
   const unsigned dg = dot_grid(N);
   double* sc = P.scal;
   CgState& C = P.cg;
@@ -781,7 +781,7 @@ void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed)
 static void cg_enqueue_iteration(Problem& P) {
   CgState& C = P.cg;
   hipStream_t s = C.stream;
-  const int64_t N = P.maps.n_dofs;
+  const int64_t N = P.maps->n_dofs;
   const unsigned dg = dot_grid(N);
   double* sc = P.scal;
   if (C.timed) HIPCHECK(hipEventRecord(P.ev[2], s));

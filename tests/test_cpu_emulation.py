@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "cpuemu"))
 
 # (case, precision of the multigrid levels)
-EMU_CASES = [("fichera-q1", 64), ("cube-q2", 64), ("lshape-q1", 32), ("fichera-q2", 32)]
+EMU_CASES = [("fichera-q1", 64), ("cube-q2", 64), ("lshape-q1", 32), ("fichera-q2", 32), ("fichera-q3", 64),
+             ("fichera-q4", 32)]
 
 
 def _asan_runtime():

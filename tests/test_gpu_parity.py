@@ -84,7 +84,7 @@ def test_level_operators(case, prec, tol):
             assert np.abs(got).max() == 0.0
 
 
-@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "fichera-q1", "fichera-q2", "fichera-q3"])
+@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "fichera-q1", "fichera-q2", "fichera-q3", "fichera-q4"])
 def test_lambda_and_vcycle_fp64(case):
     op, P = _pair(case, coeff="checker" if "fichera" in case else "one")
     info = P.info()
