@@ -128,7 +128,7 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
         wb = gi.workload("C5", g=big_g)
         bm = gmg.build_mesh(wb.recipe)
         big = (bm, gmg.options(degree=wb.degree, mg_precision=32), gi.coeff_cells(wb.coeff, *bm.leaves()))
-        log(f"serve: C5 job with g={big_g}: {bm.n_leaves} leaves")
+        log(f"serve: C5 job with g={big_g}: {bm.n_leaves} leaves (its host set-up runs on a server thread)")
     S = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=slots, host_threads=threads)
     # closed loop: all warm-up requests at once
     c0 = S.stats()["clock"]
@@ -152,7 +152,7 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
             ids.append(S.submit(big[0], big[1], coeff=big[2]))
         else:
             ids.append(S.submit(m, opts))
-    lat, its, dofs, status = [], [], 0.0, []
+    lat, its, dofs, status, nd = [], [], 0.0, [], []
     end = start
     for i in ids:
         S.wait(i, 1200)
@@ -161,6 +161,7 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
         lat.append(t["finished"] - t["arrival"])
         its.append(r["iterations"])
         dofs += len(r["u"])
+        nd.append(len(r["u"]))
         status.append(r["status"])
         end = max(end, t["finished"])
         S.release(i)
@@ -170,7 +171,9 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
     span = end - start
     big_info = None
     if big is not None:
-        big_info = {"request": 128, "latency_s": float(lat[128]), "dofs": None}
+        big_info = {"request": 128, "latency_s": float(lat[128]), "dofs": nd[128], "cg_iterations": its[128],
+                    "p50_s_others": float(np.percentile(np.delete(lat, 128), 50)),
+                    "p99_s_others": float(np.percentile(np.delete(lat, 128), 99))}
     return {"requests": n_req, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "arrival_rate_rps": rate, "throughput_rps": n_req / span,
             "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
@@ -207,9 +210,10 @@ def main():
 
     w = gi.workload(args.config, g=args.g)
     g_used = w.recipe.globals_
-    if w.name != "C2" or args.serve_big is not None:
-        # the large set-ups take minutes on the host: print their phases
-        os.environ.setdefault("GMG_TRACE", "1")
+    # the large set-ups take minutes on the host: print their phases
+    trace = w.name != "C2" and "GMG_TRACE" not in os.environ
+    if trace:
+        os.environ["GMG_TRACE"] = "1"
     t0 = time.perf_counter()
     mesh = gmg.build_mesh(w.recipe)
     log(f"{w.name}: mesh {mesh.n_leaves} leaves ({time.perf_counter() - t0:.1f} s)")
@@ -235,6 +239,8 @@ def main():
     t0 = time.perf_counter()
     base = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=64), coeff=coeff)
     t_maps = time.perf_counter() - t0
+    if trace:
+        del os.environ["GMG_TRACE"]
     for prec in ([64] if args.no_fp32 else [64, 32]):
         P = base.clone(gmg.options(degree=w.degree, mg_precision=prec))
         t0 = time.perf_counter()

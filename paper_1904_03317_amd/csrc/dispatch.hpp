@@ -38,7 +38,9 @@ struct LevelView {
 };
 
 struct LeafView {
-  int64_t n_cells = 0, n_dofs = 0;
+  // 3D at degree >= 3: cells with in-cell constraints first, [0, n_con);
+  // otherwise n_con = n_cells
+  int64_t n_cells = 0, n_dofs = 0, n_con = 0;
   const int32_t* cmap = nullptr;    // SoA [npc][n_cells], parent-arranged DoFs on refinement edges
   const uint16_t* mask = nullptr;   // [n_cells] in-cell constraint mask
   const double* scale = nullptr;    // a_K h^{d-2}

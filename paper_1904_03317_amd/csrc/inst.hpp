@@ -116,18 +116,38 @@ struct Inst {
     if (!v.n_cells) return;
     if (!v.slot || !v.cmap) fail(GMG_E_STATE, "per-cell operator called on a level without cell maps");
     hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, T, false, false>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock),
-                       0, s, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const uint16_t*)nullptr, E,
-                       to_dev(m));
+                       0, s, v.n_cells, v.n_cells, v.cmap, v.slot, v.scale, v.scale0, x, (const uint16_t*)nullptr,
+                       E, to_dev(m));
   }
   static void leaf_e(const LeafView& v, const double* x, double* E, bool mass, const MatsH<double>& m,
                      hipStream_t s) {
     if (!v.n_cells) return;
-    if (mass)
-      hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(v.n_cells)),
-                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.mscale, 1.0, x, v.mask, E, to_dev(m));
-    else
-      hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(v.n_cells)),
-                         dim3(dev::kBlock), 0, s, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, v.mask, E, to_dev(m));
+    // 3D, degree >= 3: the constrained cells (first) lane by lane, the rest
+    // by the cooperative kernel; otherwise every cell lane by lane
+    constexpr bool coop = DIM == 3 && K >= 3;
+    const int64_t n_lane = coop ? v.n_con : v.n_cells;
+    if (n_lane) {
+      if (mass)
+        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(n_lane)),
+                           dim3(dev::kBlock), 0, s, v.n_cells, n_lane, v.cmap, v.slot, v.mscale, 1.0, x, v.mask, E,
+                           to_dev(m));
+      else
+        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(n_lane)),
+                           dim3(dev::kBlock), 0, s, v.n_cells, n_lane, v.cmap, v.slot, v.scale, 1.0, x, v.mask, E,
+                           to_dev(m));
+    }
+    if constexpr (coop) {
+      const int64_t nr = v.n_cells - v.n_con;
+      if (!nr) return;
+      const unsigned g = (unsigned)((nr + dev::LeafCoop<N>::CB - 1) / dev::LeafCoop<N>::CB);
+      const dim3 b(dev::LeafCoop<N>::THREADS);
+      if (mass)
+        hipLaunchKernelGGL((dev::leaf_coop<N, true>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.cmap, v.slot, v.mscale,
+                           1.0, x, E, to_dev(m));
+      else
+        hipLaunchKernelGGL((dev::leaf_coop<N, false>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.cmap, v.slot, v.scale,
+                           1.0, x, E, to_dev(m));
+    }
   }
   static void diag0(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;

@@ -340,13 +340,11 @@ __device__ __forceinline__ void face_dispatch(const Mats<T>& m, const int* bb, c
   }
 }
 
-// u <- C_K u (fwd) or v <- C_K^T v (bwd) for the mask of a leaf
+// u <- C_K u (fwd) or v <- C_K^T v (bwd) for the mask of a leaf, with c a
+// copy of the input (registers, or LDS in the cooperative kernels)
 template <int DIM, int N, typename T>
-__device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u, bool fwd) {
+__device__ __forceinline__ void constrain_from(const Mats<T>& m, uint32_t mask, const T* c, T* u, bool fwd) {
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
-  T c[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) c[j] = u[j];
   const int bb[3] = {(int)(mask & 1u), (int)((mask >> 1) & 1u), (int)((mask >> 2) & 1u)};
   uint32_t used[(NP + 31) / 32];
 #pragma unroll
@@ -361,20 +359,29 @@ __device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u,
   }
 }
 
+template <int DIM, int N, typename T>
+__device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u, bool fwd) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  T c[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) c[j] = u[j];
+  constrain_from<DIM, N, T>(m, mask, c, u, fwd);
+}
+
 // Two-pass operator, pass 1: every (cell, local node) owns one slot of the
 // node-major buffer E (the slots of a node are contiguous), so the cell
 // results are written with plain stores and no two lanes ever write the same
 // address.  Pass 2 (seg_*) sums the slots of each node in a fixed order:
-// deterministic and free of atomics.  LEAF: ids >= n_main address the
-// hanging-node part of the input.
+// deterministic and free of atomics.  LEAF: cells carry in-cell
+// constraint masks.  Cells [0, c_end) of n_cells (the stride of the maps).
 template <int DIM, int N, typename T, bool LEAF, bool MASS>
 __global__ void __launch_bounds__(kBlock) cell_to_slots(
-    int64_t n_cells, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
+    int64_t n_cells, int64_t c_end, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
     const double* __restrict__ scale, double scale0, const T* __restrict__ x,
     const uint16_t* __restrict__ mask, T* __restrict__ E, Mats<T> m) {
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   const int64_t c = xcd_tid();
-  if (c >= n_cells) return;
+  if (c >= c_end) return;
   T u[NP], v[NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) u[j] = x[cmap[(int64_t)j * n_cells + c]];
@@ -391,6 +398,140 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   const T s = T(scale ? scale[c] : scale0);
 #pragma unroll
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
+}
+
+// Leaf pass 1 in 3D at degree >= 3 for the cells without in-cell
+// constraints, [c_first, n_cells) (otherwise the contract of
+// cell_to_slots): the cells' (k+1)^3 values do not fit one lane's
+// registers, so a workgroup stages CB cells in LDS and its threads share the
+// work: the gather and the slot stores one thread per (node, cell), the
+// sum-factorized contractions one thread per line of a cell and direction
+// (as in the cooperative level operator: a = M u, b = K u along z; c = M a,
+// f = K a + M b along y; K c + M f along x; the mass matrix is M M M).
+template <int N>
+struct LeafCoop {
+  static constexpr int NP = N * N * N, NL = N * N, THREADS = 256;
+  static constexpr int CB = 32768 / (2 * NP * 8);
+  static constexpr int ITG = (CB * NP + THREADS - 1) / THREADS;
+  static constexpr int ITL = (CB * NL + THREADS - 1) / THREADS;
+};
+
+template <int N, bool MASS>
+__global__ void __launch_bounds__(LeafCoop<N>::THREADS) __attribute__((amdgpu_waves_per_eu(5)))
+    leaf_coop(int64_t n_cells, int64_t c_first, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
+              const double* __restrict__ scale, double scale0, const double* __restrict__ x,
+              double* __restrict__ E, Mats<double> m) {
+  using S = LeafCoop<N>;
+  constexpr int NP = S::NP, NL = S::NL, CB = S::CB, TH = S::THREADS;
+  // input values (tu), then the second intermediate in the same space
+  __shared__ double tu[CB * NP];
+  __shared__ double ta[CB * NP];
+  double* tb = tu;
+  const int64_t c0 = c_first + xcd_block() * CB;
+  const int nc = (int)(n_cells - c0 < CB ? n_cells - c0 : CB);
+  const int tid = threadIdx.x;
+  {
+    double g[S::ITG];
+#pragma unroll
+    for (int it = 0; it < S::ITG; ++it) {
+      const int e = tid + it * TH, j = e / CB, cl = e % CB;
+      g[it] = e < CB * NP && cl < nc ? x[cmap[(int64_t)j * n_cells + c0 + cl]] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITG; ++it) {
+      const int e = tid + it * TH, j = e / CB, cl = e % CB;
+      if (e < CB * NP && cl < nc) tu[cl * NP + j] = g[it];
+    }
+  }
+  __syncthreads();
+  const int nline = nc * NL;
+  // lines along z
+#pragma unroll
+  for (int it = 0; it < S::ITL; ++it) {
+    const int u = tid + it * TH;
+    if (u < nline) {
+      const int cl = u / NL, p = u % NL;
+      const int o = cl * NP + p;  // (px, py, z = 0)
+      double v[N];
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = tu[o + z * NL];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int z = 0; z < N; ++z) {
+          a += m.M[i * N + z] * v[z];
+          if (!MASS) b += m.K[i * N + z] * v[z];
+        }
+        ta[o + i * NL] = a;
+        if (!MASS) tb[o + i * NL] = b;
+      }
+    }
+  }
+  __syncthreads();
+  // lines along y, in place
+#pragma unroll
+  for (int it = 0; it < S::ITL; ++it) {
+    const int u = tid + it * TH;
+    if (u < nline) {
+      const int cl = u / NL, p = u % NL, px = p % N, pz = p / N;
+      const int o = cl * NP + px + pz * NL;
+      double a[N], b[N];
+#pragma unroll
+      for (int y = 0; y < N; ++y) {
+        a[y] = ta[o + y * N];
+        if (!MASS) b[y] = tb[o + y * N];
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double c = 0.0, f = 0.0;
+#pragma unroll
+        for (int y = 0; y < N; ++y) {
+          c += m.M[i * N + y] * a[y];
+          if (!MASS) f += m.K[i * N + y] * a[y] + m.M[i * N + y] * b[y];
+        }
+        ta[o + i * N] = c;
+        if (!MASS) tb[o + i * N] = f;
+      }
+    }
+  }
+  __syncthreads();
+  // lines along x, in place
+#pragma unroll
+  for (int it = 0; it < S::ITL; ++it) {
+    const int u = tid + it * TH;
+    if (u < nline) {
+      const int cl = u / NL, p = u % NL;
+      const int o = cl * NP + p * N;
+      double c[N], f[N];
+#pragma unroll
+      for (int xx = 0; xx < N; ++xx) {
+        c[xx] = ta[o + xx];
+        if (!MASS) f[xx] = tb[o + xx];
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double r = 0.0;
+#pragma unroll
+        for (int xx = 0; xx < N; ++xx) {
+          if (MASS)
+            r += m.M[i * N + xx] * c[xx];
+          else
+            r += m.K[i * N + xx] * c[xx] + m.M[i * N + xx] * f[xx];
+        }
+        ta[o + i] = r;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < S::ITG; ++it) {
+    const int e = tid + it * TH, j = e / CB, cl = e % CB;
+    if (e < CB * NP && cl < nc) {
+      const int64_t c = c0 + cl;
+      E[slot[(int64_t)j * n_cells + c]] = (scale ? scale[c] : scale0) * ta[cl * NP + j];
+    }
+  }
 }
 
 // diagonal of the cell Laplacian, accumulated per node (FP64)
