@@ -990,22 +990,14 @@ __global__ void __launch_bounds__(kBlock) fam_restrict0(LevelView fine, const T*
 // the 1D embedding per axis, b its child position bit), the family patch
 // is assembled in LDS, and the workgroup adds it to x_f on the entities each
 // family owns (interiors contiguous, entity positions by table).
-template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(LevelView fine, LevelView coarse,
-                                                                               const T* __restrict__ xc,
-                                                                               T* __restrict__ xf, Mats<T> m) {
-  using S = FamShape<DIM, K, T>;
+// Prolongation staging: entity bases and ownership of the fine families,
+// the entity-position table, and the parent cell's coarse values su.
+template <int DIM, int K, typename T, typename S>
+__device__ __forceinline__ void prolong_stage(const LevelView& fine, const LevelView& coarse,
+                                              const T* __restrict__ xc, int64_t f0, int nf, int32_t* sgb,
+                                              uint32_t* sown, uint16_t* bq, uint32_t* bc, T* su) {
   using G = Geo<DIM, K>;
-  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP;
-  constexpr int NI = G::NI, NB = G::NB;
-  __shared__ T sout[FB * MFP];
-  __shared__ T su[FB * NP];
-  __shared__ int32_t sgb[FB * NJ];
-  __shared__ uint32_t sown[FB];
-  __shared__ uint16_t bq[NB];
-  __shared__ uint32_t bc[NB];
-  const int64_t f0 = xcd_block() * FB;
-  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  constexpr int N = G::N, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP;
   const int tid = threadIdx.x;
   for (int e = tid; e < FB * NJ; e += S::THREADS) {
     const int j = e / FB, fl = e % FB;
@@ -1048,6 +1040,74 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(Le
     }
     su[fl * NP + j] = val;
   }
+}
+
+// x_f += the assembled fine patch on the entities each family owns:
+// interiors (contiguous), then entity positions by table.
+template <int DIM, int K, typename T, typename S>
+__device__ __forceinline__ void prolong_add(int64_t f0, int nf, const T* sout, const int32_t* sgb,
+                                            const uint32_t* sown, const uint16_t* bq, const uint32_t* bc,
+                                            T* __restrict__ xf) {
+  using G = Geo<DIM, K>;
+  constexpr int MFP = S::MFP, NJ = G::NJ, NI = G::NI, NB = G::NB;
+  const int tid = threadIdx.x;
+  {
+    int32_t node[S::ITI];
+    T old[S::ITI];
+    interior_nodes<DIM, K, T, S>(f0, nf, node);
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) old[it] = xf[node[it] >= 0 ? node[it] : 0];
+#pragma unroll
+    for (int it = 0; it < S::ITI; ++it) {
+      const int e = tid + it * S::THREADS;
+      if (node[it] >= 0) xf[node[it]] = old[it] + sout[(e / NI) * MFP + G::iq(e % NI)];
+    }
+  }
+#pragma unroll
+  for (int c0 = 0; c0 < S::ITB; c0 += S::CH) {
+    int32_t node[S::CH];
+    T val[S::CH], old[S::CH];
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k) {
+      const int it = c0 + k;
+      const int e = tid + it * S::THREADS;
+      node[k] = -1;
+      val[k] = T(0);
+      if (it < S::ITB && e < nf * NB) {
+        const int fl = e / NB, b = e % NB;
+        const uint32_t c = bc[b];
+        const int j = G::cj(c);
+        if ((sown[fl] >> j) & 1u) {
+          node[k] = sgb[fl * NJ + j] + G::cloc(c);
+          val[k] = sout[fl * MFP + bq[b]];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k) old[k] = xf[node[k] >= 0 ? node[k] : 0];
+#pragma unroll
+    for (int k = 0; k < S::CH; ++k)
+      if (node[k] >= 0) xf[node[k]] = old[k] + val[k];
+  }
+}
+
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(LevelView fine, LevelView coarse,
+                                                                               const T* __restrict__ xc,
+                                                                               T* __restrict__ xf, Mats<T> m) {
+  using S = FamShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
+  __shared__ T sout[FB * MFP];
+  __shared__ T su[FB * NP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sown[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  prolong_stage<DIM, K, T, S>(fine, coarse, xc, f0, nf, sgb, sown, bq, bc, su);
   __syncthreads();
   {
     // fine cell cid of family fl: v = (E_z ⊗ E_y ⊗ E_x) u on its sub-box
@@ -1104,45 +1164,234 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(Le
       if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = v[j];
   }
   __syncthreads();
-  // x_f += patch on the owned entities: interiors, then entity positions
-  {
-    int32_t node[S::ITI];
-    T old[S::ITI];
-    interior_nodes<DIM, K, T>(f0, nf, node);
-#pragma unroll
-    for (int it = 0; it < S::ITI; ++it) old[it] = xf[node[it] >= 0 ? node[it] : 0];
-#pragma unroll
-    for (int it = 0; it < S::ITI; ++it) {
-      const int e = tid + it * S::THREADS;
-      if (node[it] >= 0) xf[node[it]] = old[it] + sout[(e / NI) * MFP + G::iq(e % NI)];
-    }
+  prolong_add<DIM, K, T, S>(f0, nf, sout, sgb, sown, bq, bc, xf);
+}
+
+// ------------------------------------------------------------------ transfers, 3D at k >= 3
+// The same three transfer kernels with the cells' line contractions shared
+// by the threads of a workgroup through LDS (per-cell arrays laid out as in
+// the cooperative operator), for the degrees whose (k+1)^3 cell values do
+// not fit one lane's registers.  E^(b)[i][J] = E[(b k + i) (k+1) + J]: the
+// 1D embedding rows of child position b.
+template <int K, typename T>
+__device__ __forceinline__ T emb_rows(const Mats<T>& m, bool hi, int i, int J) {
+  return sel(hi, m.E[(K + i) * (K + 1) + J], m.E[i * (K + 1) + J]);
+}
+
+// Restriction, fine side (contract of fam_rfine): the owned patch values of
+// each cell are contracted with the transposed rows along x, y, z in place,
+// and every parent-cell node sums its 2^d cells in ascending child order.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((CoopShape<DIM, K, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(5)))
+    fam_rfine_coop(LevelView fine, const T* __restrict__ r, T* __restrict__ rb, Mats<T> m) {
+  using S = CoopShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
+  constexpr int NXP = S::NXP, CS = S::CS, FS = S::FS, NL = S::NL, TH = S::THREADS;
+  static_assert(DIM == 3, "cooperative transfers are 3D");
+  __shared__ T sin[FB * MFP];
+  __shared__ T ta[FB * FS];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ uint32_t sown[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  stage_bases<DIM, K, T, S>(fine, f0, sgb, sex, bq, bc, bo);
+  for (int fl = tid; fl < FB; fl += TH) sown[fl] = fl < nf ? fine.own[f0 + fl] : 0u;
+  __syncthreads();
+  gather_patch<DIM, K, T, S>(f0, nf, r, sgb, bq, bc, sin);
+  __syncthreads();
+  // each cell's values at the patch nodes it counts (first cell of the
+  // family containing the node, on entities the family owns)
+  for (int e = tid; e < nf * CPF * NP; e += TH) {
+    const int fl = e / (CPF * NP), rr = e % (CPF * NP), cid = rr / NP, j = rr % NP;
+    const int q = cell_patch_pos<DIM, K>(cid, j);
+    const bool keep = family_owner<DIM, N>(cid, j) && ((sown[fl] >> G::cj(G::code(q))) & 1u);
+    const int jx = j % N, jy = (j / N) % N, jz = j / (N * N);
+    ta[fl * FS + cid * CS + jx + NXP * (jy + N * jz)] = keep ? sin[fl * MFP + q] : T(0);
   }
+  __syncthreads();
+  const int nline = nf * CPF * NL;
+  // axis a = 0, 1, 2: t[J] = sum_i E^(b_a)[i][J] v[i] along the lines of axis a
 #pragma unroll
-  for (int c0 = 0; c0 < S::ITB; c0 += S::CH) {
-    int32_t node[S::CH];
-    T val[S::CH], old[S::CH];
+  for (int a = 0; a < 3; ++a) {
 #pragma unroll
-    for (int k = 0; k < S::CH; ++k) {
-      const int it = c0 + k;
-      const int e = tid + it * S::THREADS;
-      node[k] = -1;
-      val[k] = T(0);
-      if (it < S::ITB && e < nf * NB) {
-        const int fl = e / NB, b = e % NB;
-        const uint32_t c = bc[b];
-        const int j = G::cj(c);
-        if ((sown[fl] >> j) & 1u) {
-          node[k] = sgb[fl * NJ + j] + G::cloc(c);
-          val[k] = sout[fl * MFP + bq[b]];
+    for (int it = 0; it < S::ITL; ++it) {
+      const int u = tid + it * TH;
+      if (u < nline) {
+        const int fl = u / (CPF * NL), rr = u % (CPF * NL), cid = rr / NL, p = rr % NL;
+        const int p0 = p % N, p1 = p / N;
+        const int o = fl * FS + cid * CS +
+                      (a == 0 ? NXP * (p0 + N * p1) : a == 1 ? p0 + NXP * N * p1 : p0 + NXP * p1);
+        const int st = a == 0 ? 1 : a == 1 ? NXP : NXP * N;
+        const bool hi = (cid >> a) & 1;
+        T v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = ta[o + i * st];
+#pragma unroll
+        for (int J = 0; J < N; ++J) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < N; ++i) s += emb_rows<K>(m, hi, i, J) * v[i];
+          ta[o + J * st] = s;
         }
       }
     }
-#pragma unroll
-    for (int k = 0; k < S::CH; ++k) old[k] = xf[node[k] >= 0 ? node[k] : 0];
-#pragma unroll
-    for (int k = 0; k < S::CH; ++k)
-      if (node[k] >= 0) xf[node[k]] = old[k] + val[k];
+    __syncthreads();
   }
+  for (int e = tid; e < nf * NP; e += TH) {
+    const int fl = e / NP, j = e % NP;
+    const int jx = j % N, jy = (j / N) % N, jz = j / (N * N);
+    T s = T(0);
+#pragma unroll
+    for (int cid = 0; cid < CPF; ++cid) s += ta[fl * FS + cid * CS + jx + NXP * (jy + N * jz)];
+    rb[(f0 + fl) * NP + j] = s;
+  }
+}
+
+// Restriction, coarse side (contract of fam_restrict): every coarse patch
+// position sums the restricted values of the cells containing it that are
+// refined, in ascending child order, then the restriction-start epilogue.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((CoopShape<DIM, K, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(5)))
+    fam_restrict_coop(LevelView coarse, const T* __restrict__ rb, Epi<T> ep, T* __restrict__ E, Mats<T> m) {
+  using S = CoopShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2, MF = G::MF, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ;
+  constexpr int NP = G::NP, NB = G::NB, TH = S::THREADS;
+  static_assert(DIM == 3, "cooperative transfers are 3D");
+  __shared__ T sout[FB * MFP];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sex[FB];
+  __shared__ int32_t sch[FB * CPF];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  __shared__ int64_t bo[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(coarse.n_fam - f0 < FB ? coarse.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  int32_t inode[S::ITI];
+  interior_nodes<DIM, K, T, S>(f0, nf, inode);
+  EpiOps<T, S::ITI> iops;
+  epi_load<T, kEpiRStart, S::ITI, false>(ep, inode, iops);
+  stage_bases<DIM, K, T, S>(coarse, f0, sgb, sex, bq, bc, bo);
+  for (int e = tid; e < FB * CPF; e += TH) {
+    const int fl = e / CPF, cid = e % CPF;
+    sch[e] = fl < nf ? coarse.child[(int64_t)cid * coarse.n_fam + f0 + fl] : -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < S::ITQ; ++it) {
+    const int e = tid + it * TH;
+    if (e < nf * MF) {
+      const int fl = e / MF, q = e % MF;
+      const int qx = q % M2, qy = (q / M2) % M2, qz = q / (M2 * M2);
+      T v[CPF];
+#pragma unroll
+      for (int cid = 0; cid < CPF; ++cid) {
+        const int jx = qx - (cid & 1) * K, jy = qy - ((cid >> 1) & 1) * K, jz = qz - ((cid >> 2) & 1) * K;
+        const int32_t f = sch[fl * CPF + cid];
+        const bool in = jx >= 0 && jx <= K && jy >= 0 && jy <= K && jz >= 0 && jz <= K && f >= 0;
+        v[cid] = in ? rb[(int64_t)f * NP + jx + N * (jy + N * jz)] : T(0);
+      }
+      T s = T(0);
+#pragma unroll
+      for (int cid = 0; cid < CPF; ++cid) s += v[cid];
+      sout[fl * MFP + q] = s;
+    }
+  }
+  __syncthreads();
+  patch_out<DIM, K, T, kEpiRStart, S>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, bo, ep, E, inode, iops);
+}
+
+// Prolongation (contract of fam_prolong): the parent values are embedded
+// along x into each cell's array, then along y and z in place; every patch
+// position takes the value of the lowest cell containing it.
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((CoopShape<DIM, K, T>::THREADS)) __attribute__((amdgpu_waves_per_eu(5)))
+    fam_prolong_coop(LevelView fine, LevelView coarse, const T* __restrict__ xc, T* __restrict__ xf, Mats<T> m) {
+  using S = CoopShape<DIM, K, T>;
+  using G = Geo<DIM, K>;
+  constexpr int N = G::N, M2 = G::M2, MF = G::MF, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ;
+  constexpr int NP = G::NP, NB = G::NB, NXP = S::NXP, CS = S::CS, FS = S::FS, NL = S::NL, TH = S::THREADS;
+  static_assert(DIM == 3, "cooperative transfers are 3D");
+  __shared__ T sout[FB * MFP];
+  __shared__ T su[FB * NP];
+  __shared__ T ta[FB * FS];
+  __shared__ int32_t sgb[FB * NJ];
+  __shared__ uint32_t sown[FB];
+  __shared__ uint16_t bq[NB];
+  __shared__ uint32_t bc[NB];
+  const int64_t f0 = xcd_block() * FB;
+  const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
+  const int tid = threadIdx.x;
+  prolong_stage<DIM, K, T, S>(fine, coarse, xc, f0, nf, sgb, sown, bq, bc, su);
+  __syncthreads();
+  const int nline = nf * CPF * NL;
+  // x: from the parent values into the cell arrays
+#pragma unroll
+  for (int it = 0; it < S::ITL; ++it) {
+    const int u = tid + it * TH;
+    if (u < nline) {
+      const int fl = u / (CPF * NL), rr = u % (CPF * NL), cid = rr / NL, p = rr % NL;
+      const bool hi = cid & 1;
+      T v[N];
+#pragma unroll
+      for (int J = 0; J < N; ++J) v[J] = su[fl * NP + p * N + J];
+      T* o = ta + fl * FS + cid * CS + NXP * p;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        T s = T(0);
+#pragma unroll
+        for (int J = 0; J < N; ++J) s += emb_rows<K>(m, hi, i, J) * v[J];
+        o[i] = s;
+      }
+    }
+  }
+  __syncthreads();
+  // y, z in place
+#pragma unroll
+  for (int a = 1; a < 3; ++a) {
+#pragma unroll
+    for (int it = 0; it < S::ITL; ++it) {
+      const int u = tid + it * TH;
+      if (u < nline) {
+        const int fl = u / (CPF * NL), rr = u % (CPF * NL), cid = rr / NL, p = rr % NL;
+        const int p0 = p % N, p1 = p / N;
+        const int o = fl * FS + cid * CS + (a == 1 ? p0 + NXP * N * p1 : p0 + NXP * p1);
+        const int st = a == 1 ? NXP : NXP * N;
+        const bool hi = (cid >> a) & 1;
+        T v[N];
+#pragma unroll
+        for (int J = 0; J < N; ++J) v[J] = ta[o + J * st];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          T s = T(0);
+#pragma unroll
+          for (int J = 0; J < N; ++J) s += emb_rows<K>(m, hi, i, J) * v[J];
+          ta[o + i * st] = s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int it = 0; it < S::ITQ; ++it) {
+    const int e = tid + it * TH;
+    if (e < nf * MF) {
+      const int fl = e / MF, q = e % MF;
+      const int qx = q % M2, qy = (q / M2) % M2, qz = q / (M2 * M2);
+      const int bx = qx > K, by = qy > K, bz = qz > K;
+      const int cid = bx | (by << 1) | (bz << 2);
+      sout[fl * MFP + q] = ta[fl * FS + cid * CS + (qx - bx * K) + NXP * ((qy - by * K) + N * (qz - bz * K))];
+    }
+  }
+  __syncthreads();
+  prolong_add<DIM, K, T, S>(f0, nf, sout, sgb, sown, bq, bc, xf);
 }
 
 }  // namespace dev

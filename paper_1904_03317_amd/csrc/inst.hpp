@@ -87,15 +87,27 @@ struct Inst {
   template <typename T>
   static void restrict_fc(const LevelView& f, const LevelView& c, const T* r, const dev::Epi<T>& ep, T* rb, T* E,
                           const MatsH<T>& m, hipStream_t s) {
-    using S = dev::FamShape<DIM, K, T>;
-    if (f.n_fam) {
-      const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
-      hipLaunchKernelGGL((dev::fam_rfine<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, r, rb, to_dev(m));
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      using S = dev::CoopShape<DIM, K, T>;
+      if (f.n_fam) {
+        const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
+        hipLaunchKernelGGL((dev::fam_rfine_coop<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, r, rb, to_dev(m));
+      }
+      if (!c.n_fam) return;
+      const unsigned g = (unsigned)((c.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_restrict_coop<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, c, (const T*)rb, ep,
+                         E, to_dev(m));
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      if (f.n_fam) {
+        const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
+        hipLaunchKernelGGL((dev::fam_rfine<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, r, rb, to_dev(m));
+      }
+      if (!c.n_fam) return;
+      const unsigned g = (unsigned)((c.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_restrict<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, c, (const T*)rb, ep, E,
+                         to_dev(m));
     }
-    if (!c.n_fam) return;
-    const unsigned g = (unsigned)((c.n_fam + S::FB - 1) / S::FB);
-    hipLaunchKernelGGL((dev::fam_restrict<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, c, (const T*)rb, ep, E,
-                       to_dev(m));
   }
   template <typename T>
   static void restrict0(const LevelView& f, const T* r, T* E, const MatsH<T>& m, hipStream_t s) {
@@ -107,9 +119,16 @@ struct Inst {
   static void prolong(const LevelView& f, const LevelView& c, const T* xc, T* xf, const MatsH<T>& m,
                       hipStream_t s) {
     if (!f.n_fam) return;
-    using S = dev::FamShape<DIM, K, T>;
-    const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
-    hipLaunchKernelGGL((dev::fam_prolong<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, c, xc, xf, to_dev(m));
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      using S = dev::CoopShape<DIM, K, T>;
+      const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_prolong_coop<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, c, xc, xf,
+                         to_dev(m));
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      const unsigned g = (unsigned)((f.n_fam + S::FB - 1) / S::FB);
+      hipLaunchKernelGGL((dev::fam_prolong<DIM, K, T>), dim3(g), dim3(S::THREADS), 0, s, f, c, xc, xf, to_dev(m));
+    }
   }
   template <typename T>
   static void cell_e(const LevelView& v, const T* x, T* E, const MatsH<T>& m, hipStream_t s) {
