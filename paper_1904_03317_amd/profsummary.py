@@ -2,7 +2,11 @@
 kernel total time, dispatch count and average duration, optionally per grid
 size, as short text for the profiles/ folder.
 
-python -m paper_1904_03317_amd.profsummary <results.db> [--by-grid PATTERN] [--per-iteration]
+python -m paper_1904_03317_amd.profsummary <results.db> [--by-grid PATTERN [--last N]] [--per-iteration]
+
+--last N: beside each grid's average over all its dispatches, the average
+of its last N dispatches (bench.py's timed repetitions of one level
+operator come last for each precision).
 
 --per-iteration: kernel time per CG iteration inside the last timed solve of
 each precision, delimited by the update_xr dispatches (one per iteration).
@@ -18,7 +22,7 @@ def short(name):
     return name.replace("void gmg::dev::", "").replace("gmg::dev::", "")
 
 
-def summarize(db_path, top=30, by_grid=None):
+def summarize(db_path, top=30, by_grid=None, last=20):
     db = sqlite3.connect(db_path)
     rows = db.execute("select name, duration, grid_x, start, end from kernels order by start").fetchall()
     out = []
@@ -41,8 +45,9 @@ def summarize(db_path, top=30, by_grid=None):
         out.append(f"per grid size, kernels matching '{by_grid}':")
         for gx in sorted(g):
             v = g[gx]
+            t = v[-last:]
             out.append(f"  grid_x {gx:10d} threads: n={len(v):5d} avg {sum(v) / len(v) / 1e3:9.2f} us "
-                       f"min {min(v) / 1e3:9.2f} us")
+                       f"min {min(v) / 1e3:9.2f} us, last {len(t)} avg {sum(t) / len(t) / 1e3:9.2f} us")
     return "\n".join(out)
 
 
@@ -81,8 +86,9 @@ if __name__ == "__main__":
     ap.add_argument("--top", type=int, default=30)
     ap.add_argument("--by-grid", default=None)
     ap.add_argument("--per-iteration", action="store_true")
+    ap.add_argument("--last", type=int, default=20)
     a = ap.parse_args()
-    print(summarize(a.db, a.top, a.by_grid))
+    print(summarize(a.db, a.top, a.by_grid, a.last))
     if a.per_iteration:
         print()
         print(per_iteration(a.db))
