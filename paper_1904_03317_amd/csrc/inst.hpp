@@ -141,31 +141,41 @@ struct Inst {
   static void leaf_e(const LeafView& v, const double* x, double* E, bool mass, const MatsH<double>& m,
                      hipStream_t s) {
     if (!v.n_cells) return;
-    // 3D, degree >= 3: the constrained cells (first) lane by lane, the rest
-    // by the cooperative kernel; otherwise every cell lane by lane
-    constexpr bool coop = DIM == 3 && K >= 3;
-    const int64_t n_lane = coop ? v.n_con : v.n_cells;
-    if (n_lane) {
-      if (mass)
-        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(n_lane)),
-                           dim3(dev::kBlock), 0, s, v.n_cells, n_lane, v.cmap, v.slot, v.mscale, 1.0, x, v.mask, E,
-                           to_dev(m));
-      else
-        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(n_lane)),
-                           dim3(dev::kBlock), 0, s, v.n_cells, n_lane, v.cmap, v.slot, v.scale, 1.0, x, v.mask, E,
-                           to_dev(m));
-    }
-    if constexpr (coop) {
+    // 3D, degree >= 3: the cooperative kernel, on the constrained cells
+    // (first) with the in-cell constraint steps and on the rest without;
+    // otherwise every cell lane by lane
+    if constexpr (DIM == 3 && K >= 3) {
+      using LC = dev::LeafCoop<N>;
+      const dim3 b(LC::THREADS);
+      const double* sc = mass ? v.mscale : v.scale;
+      if (v.n_con) {
+        const unsigned g = (unsigned)((v.n_con + LC::CB - 1) / LC::CB);
+        if (mass)
+          hipLaunchKernelGGL((dev::leaf_coop<N, true, true>), dim3(g), b, 0, s, v.n_cells, (int64_t)0, v.n_con,
+                             v.cmap, v.slot, sc, 1.0, x, v.mask, E, to_dev(m));
+        else
+          hipLaunchKernelGGL((dev::leaf_coop<N, false, true>), dim3(g), b, 0, s, v.n_cells, (int64_t)0, v.n_con,
+                             v.cmap, v.slot, sc, 1.0, x, v.mask, E, to_dev(m));
+      }
       const int64_t nr = v.n_cells - v.n_con;
-      if (!nr) return;
-      const unsigned g = (unsigned)((nr + dev::LeafCoop<N>::CB - 1) / dev::LeafCoop<N>::CB);
-      const dim3 b(dev::LeafCoop<N>::THREADS);
+      if (nr) {
+        const unsigned g = (unsigned)((nr + LC::CB - 1) / LC::CB);
+        if (mass)
+          hipLaunchKernelGGL((dev::leaf_coop<N, true, false>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.n_cells,
+                             v.cmap, v.slot, sc, 1.0, x, v.mask, E, to_dev(m));
+        else
+          hipLaunchKernelGGL((dev::leaf_coop<N, false, false>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.n_cells,
+                             v.cmap, v.slot, sc, 1.0, x, v.mask, E, to_dev(m));
+      }
+    } else {
       if (mass)
-        hipLaunchKernelGGL((dev::leaf_coop<N, true>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.cmap, v.slot, v.mscale,
-                           1.0, x, E, to_dev(m));
+        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, true>), dim3(grid_for(v.n_cells)),
+                           dim3(dev::kBlock), 0, s, v.n_cells, v.n_cells, v.cmap, v.slot, v.mscale, 1.0, x, v.mask,
+                           E, to_dev(m));
       else
-        hipLaunchKernelGGL((dev::leaf_coop<N, false>), dim3(g), b, 0, s, v.n_cells, v.n_con, v.cmap, v.slot, v.scale,
-                           1.0, x, E, to_dev(m));
+        hipLaunchKernelGGL((dev::cell_to_slots<DIM, N, double, true, false>), dim3(grid_for(v.n_cells)),
+                           dim3(dev::kBlock), 0, s, v.n_cells, v.n_cells, v.cmap, v.slot, v.scale, 1.0, x, v.mask,
+                           E, to_dev(m));
     }
   }
   static void diag0(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {

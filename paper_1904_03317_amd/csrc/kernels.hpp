@@ -400,14 +400,133 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
 }
 
-// Leaf pass 1 in 3D at degree >= 3 for the cells without in-cell
-// constraints, [c_first, n_cells) (otherwise the contract of
-// cell_to_slots): the cells' (k+1)^3 values do not fit one lane's
-// registers, so a workgroup stages CB cells in LDS and its threads share the
-// work: the gather and the slot stores one thread per (node, cell), the
-// sum-factorized contractions one thread per line of a cell and direction
-// (as in the cooperative level operator: a = M u, b = K u along z; c = M a,
-// f = K a + M b along y; K c + M f along x; the mass matrix is M M M).
+// In-cell constraints of one node, gathered (3D, used by the cooperative
+// leaf kernel, one thread per node of a cell).  The constraint entities of
+// a leaf with mask mk are the faces normal to axis e (mask bit 3 + e) and
+// the edges along axis e (bit 6 + e) on the side of its child position
+// bits; with c the cell's values:
+//  forward:   u_j = the interpolation of the last active entity (faces x, y,
+//             z, then edges x, y, z) containing node j, else c_j (the
+//             order in which constrain_from overwrites);
+//  transpose: v_J = (J claimed ? 0 : c_J) + the sum, over the active
+//             entities containing J, of the embedding weights times c_p of
+//             the nodes p each entity claims (the first active entity
+//             containing p, as the used-mask of constrain_from).
+// sE holds the 1D embedding rows E (2k+1 rows of k+1) in LDS: run-time
+// indices into a kernel argument would move it to scratch memory.
+template <int N>
+struct CellCon {
+  static constexpr int K = N - 1;
+  uint32_t mk;
+  int bb[3], JB[3];
+  __device__ __forceinline__ explicit CellCon(uint32_t m) : mk(m) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bb[a] = (int)((m >> a) & 1u);
+      JB[a] = bb[a] * K;
+    }
+  }
+  static constexpr int P(int a) { return a == 0 ? 1 : 0; }
+  static constexpr int Q(int a) { return a == 2 ? 1 : 2; }
+  static __device__ __forceinline__ int lid(const int (&q)[3]) { return q[0] + N * (q[1] + N * q[2]); }
+  __device__ __forceinline__ bool active(int e) const { return (mk >> (3 + e)) & 1u; }
+  // e is a compile-time constant wherever these are called (unrolled loops)
+  __device__ __forceinline__ bool contains(int e, const int (&p)[3]) const {
+    if (e < 3) return p[e] == JB[e];
+    return p[P(e - 3)] == JB[P(e - 3)] && p[Q(e - 3)] == JB[Q(e - 3)];
+  }
+  __device__ __forceinline__ int claim(const int (&p)[3]) const {
+    int c = -1;
+#pragma unroll
+    for (int e = 5; e >= 0; --e)
+      if (active(e) && contains(e, p)) c = e;
+    return c;
+  }
+  static __device__ __forceinline__ double emb(const double* sE, int b, int j, int J) {
+    return sE[(b * K + j) * N + J];
+  }
+  // interpolation of entity e at node p from the cell's values c
+  __device__ __forceinline__ double interp(int e, const double* sE, const double* c, const int (&p)[3]) const {
+    double s = 0.0;
+    if (e < 3) {
+      const int A = e, Pa = P(A), Qa = Q(A);
+#pragma unroll
+      for (int Jq = 0; Jq < N; ++Jq)
+#pragma unroll
+        for (int Jp = 0; Jp < N; ++Jp) {
+          int q[3];
+          q[A] = JB[A];
+          q[Pa] = Jp;
+          q[Qa] = Jq;
+          s += emb(sE, bb[Pa], p[Pa], Jp) * emb(sE, bb[Qa], p[Qa], Jq) * c[lid(q)];
+        }
+    } else {
+      const int A = e - 3;
+#pragma unroll
+      for (int J = 0; J < N; ++J) {
+        int q[3];
+        q[A] = J;
+        q[P(A)] = JB[P(A)];
+        q[Q(A)] = JB[Q(A)];
+        s += emb(sE, bb[A], p[A], J) * c[lid(q)];
+      }
+    }
+    return s;
+  }
+  __device__ __forceinline__ double forward(const double* sE, const double* c, int j) const {
+    const int p[3] = {j % N, (j / N) % N, j / (N * N)};
+    int last = -1;
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+      if (active(e) && contains(e, p)) last = e;
+    double s = c[j];
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+      if (e == last) s = interp(e, sE, c, p);
+    return s;
+  }
+  __device__ __forceinline__ double transpose(const double* sE, const double* c, int jj) const {
+    const int J[3] = {jj % N, (jj / N) % N, jj / (N * N)};
+    double s = claim(J) < 0 ? c[jj] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      if (!active(e) || !contains(e, J)) continue;
+      if (e < 3) {
+        const int A = e, Pa = P(A), Qa = Q(A);
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            int q[3];
+            q[A] = JB[A];
+            q[Pa] = a;
+            q[Qa] = b;
+            if (claim(q) == e) s += emb(sE, bb[Pa], a, J[Pa]) * emb(sE, bb[Qa], b, J[Qa]) * c[lid(q)];
+          }
+      } else {
+        const int A = e - 3;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          int q[3];
+          q[A] = a;
+          q[P(A)] = JB[P(A)];
+          q[Q(A)] = JB[Q(A)];
+          if (claim(q) == e) s += emb(sE, bb[A], a, J[A]) * c[lid(q)];
+        }
+      }
+    }
+    return s;
+  }
+};
+
+// Leaf pass 1 in 3D at degree >= 3 on cells [c_first, n_cells) (otherwise
+// the contract of cell_to_slots): the cells' (k+1)^3 values do not fit one
+// lane's registers, so a workgroup stages CB cells in LDS and its threads
+// share the work: the gather, the in-cell constraints (CON) and the slot
+// stores one thread per (node, cell), the sum-factorized contractions one
+// thread per line of a cell and direction (as in the cooperative level
+// operator: a = M u, b = K u along z; c = M a, f = K a + M b along y;
+// K c + M f along x; the mass matrix is M M M).
 template <int N>
 struct LeafCoop {
   static constexpr int NP = N * N * N, NL = N * N, THREADS = 256;
@@ -416,20 +535,30 @@ struct LeafCoop {
   static constexpr int ITL = (CB * NL + THREADS - 1) / THREADS;
 };
 
-template <int N, bool MASS>
+template <int N, bool MASS, bool CON>
 __global__ void __launch_bounds__(LeafCoop<N>::THREADS) __attribute__((amdgpu_waves_per_eu(5)))
-    leaf_coop(int64_t n_cells, int64_t c_first, const int32_t* __restrict__ cmap, const int32_t* __restrict__ slot,
-              const double* __restrict__ scale, double scale0, const double* __restrict__ x,
-              double* __restrict__ E, Mats<double> m) {
+    leaf_coop(int64_t n_cells, int64_t c_first, int64_t c_end, const int32_t* __restrict__ cmap,
+              const int32_t* __restrict__ slot, const double* __restrict__ scale, double scale0,
+              const double* __restrict__ x, const uint16_t* __restrict__ mask, double* __restrict__ E,
+              Mats<double> m) {
   using S = LeafCoop<N>;
   constexpr int NP = S::NP, NL = S::NL, CB = S::CB, TH = S::THREADS;
   // input values (tu), then the second intermediate in the same space
   __shared__ double tu[CB * NP];
   __shared__ double ta[CB * NP];
+  __shared__ double sE[(2 * N - 1) * N];
+  __shared__ uint32_t smk[CB];
   double* tb = tu;
   const int64_t c0 = c_first + xcd_block() * CB;
-  const int nc = (int)(n_cells - c0 < CB ? n_cells - c0 : CB);
+  const int nc = (int)(c_end - c0 < CB ? c_end - c0 : CB);
   const int tid = threadIdx.x;
+  if (CON) {
+    if (tid == 0) {
+#pragma unroll
+      for (int e = 0; e < (2 * N - 1) * N; ++e) sE[e] = m.E[e];
+    }
+    if (tid < nc) smk[tid] = mask[c0 + tid];
+  }
   {
     double g[S::ITG];
 #pragma unroll
@@ -444,6 +573,17 @@ __global__ void __launch_bounds__(LeafCoop<N>::THREADS) __attribute__((amdgpu_wa
     }
   }
   __syncthreads();
+  const double* src = tu;
+  if (CON) {
+    // u <- C u, into ta
+#pragma unroll
+    for (int it = 0; it < S::ITG; ++it) {
+      const int e = tid + it * TH, cl = e / NP, j = e % NP;
+      if (cl < nc) ta[e] = CellCon<N>(smk[cl]).forward(sE, tu + cl * NP, j);
+    }
+    __syncthreads();
+    src = ta;
+  }
   const int nline = nc * NL;
   // lines along z
 #pragma unroll
@@ -454,7 +594,7 @@ __global__ void __launch_bounds__(LeafCoop<N>::THREADS) __attribute__((amdgpu_wa
       const int o = cl * NP + p;  // (px, py, z = 0)
       double v[N];
 #pragma unroll
-      for (int z = 0; z < N; ++z) v[z] = tu[o + z * NL];
+      for (int z = 0; z < N; ++z) v[z] = src[o + z * NL];
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         double a = 0.0, b = 0.0;
@@ -524,12 +664,23 @@ __global__ void __launch_bounds__(LeafCoop<N>::THREADS) __attribute__((amdgpu_wa
     }
   }
   __syncthreads();
+  const double* res = ta;
+  if (CON) {
+    // v <- C^T v, into tb
+#pragma unroll
+    for (int it = 0; it < S::ITG; ++it) {
+      const int e = tid + it * TH, cl = e / NP, j = e % NP;
+      if (cl < nc) tb[e] = CellCon<N>(smk[cl]).transpose(sE, ta + cl * NP, j);
+    }
+    __syncthreads();
+    res = tb;
+  }
 #pragma unroll
   for (int it = 0; it < S::ITG; ++it) {
     const int e = tid + it * TH, j = e / CB, cl = e % CB;
     if (e < CB * NP && cl < nc) {
       const int64_t c = c0 + cl;
-      E[slot[(int64_t)j * n_cells + c]] = (scale ? scale[c] : scale0) * ta[cl * NP + j];
+      E[slot[(int64_t)j * n_cells + c]] = (scale ? scale[c] : scale0) * res[cl * NP + j];
     }
   }
 }
