@@ -30,6 +30,12 @@ CASES = {
     "fichera-q3": (recipe("fichera", 1, 2, "corner+random"), 3),
     "fichera-q4": (recipe("fichera", 1, 1, "corner+random"), 4),
     "cube-q2": (recipe("cube", 2, 2, "corner"), 2),
+    # degenerate meshes: no refinement (one level, coarse solve only), no
+    # free DoF at all, one family smaller than a cooperative workgroup
+    "cube-q1-g0": (recipe("cube", 0, 0, "corner"), 1),
+    "fichera-q2-g0": (recipe("fichera", 0, 0, "corner"), 2),
+    "lshape-q2-g0": (recipe("lshape", 0, 0, "corner"), 2),
+    "cube-q3-g1": (recipe("cube", 1, 0, "corner"), 3),
 }
 
 

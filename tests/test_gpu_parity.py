@@ -147,6 +147,38 @@ def test_solve_variable_coefficient_q3():
     assert st == 0 and its == it and rel(host(u), x) <= 1e-10
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("case", ["cube-q1-g0", "fichera-q2-g0", "lshape-q2-g0", "cube-q3-g1"])
+def test_degenerate_meshes(case, prec):
+    """No free DoF (every node on the boundary), a single level (the V-cycle
+    is the exact coarse solve: one CG iteration in FP64), one family smaller
+    than a cooperative workgroup (degree 3)."""
+    op, P = _pair(case, prec=prec)
+    f = gi.rhs_nodal("noise", op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.ones(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    uh = host(u)
+    assert st == 0 and ok
+    if prec == 64:
+        assert its == it
+    else:
+        assert its <= it + 1
+    if np.linalg.norm(x) == 0.0:
+        assert its == 0 and np.abs(uh).max() == 0.0
+    else:
+        assert rel(uh, x) <= (1e-10 if prec == 64 else 1e-8)
+    r = np.zeros(op.n_dofs)
+    r[op.free] = np.random.default_rng(3).standard_normal(int(op.free.sum()))
+    z = torch.zeros_like(u)
+    P.vcycle(dev(r), z)
+    zh, zr = host(z), op.mg.vcycle(r)
+    if np.linalg.norm(zr) == 0.0:
+        assert np.abs(zh).max() == 0.0
+    else:
+        assert rel(zh, zr) <= (1e-11 if prec == 64 else 1e-5)
+
+
 def test_zero_rhs_and_default_rhs():
     op, P = _pair("lshape-q1")
     u = torch.ones(op.n_dofs, dtype=torch.float64, device="cuda")
