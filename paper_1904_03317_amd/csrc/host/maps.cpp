@@ -154,10 +154,36 @@ struct Ctx {
 };
 
 struct HangRec {
-  int64_t start = 0;   // masters in the pools
+  int64_t start = 0;   // masters in the pools of chunk `part`
   int32_t nm = 0;
   int32_t id = -1;     // hanging id (first touch), -1 until numbered
+  int32_t part = 0;
 };
+
+// fn(chunk, begin, end) over [0, n) cut into nch contiguous chunks, on nt
+// threads (this one included); the first exception is rethrown after all
+// chunks finished.
+template <class F>
+void chunked(int64_t n, int nch, int nt, F&& fn) {
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  auto work = [&] {
+    for (int c = next++; c < nch; c = next++) {
+      try {
+        fn(c, n * c / nch, n * (c + 1) / nch);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!err) err = std::current_exception();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < std::min(nt, nch); ++t) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
 
 }  // namespace
 
@@ -174,8 +200,10 @@ struct PhaseTimer {
 };
 }  // namespace
 
-Maps build_maps(const Forest& f, int k, const double* coeff) {
+Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   PhaseTimer T;
+  const int nthreads =
+      threads > 0 ? threads : (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
   Ctx C(f, k);
   const int dim = C.dim, n = C.n, npc = C.npc;
   Maps M;
@@ -323,16 +351,26 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
   // level-(l-1) leaf N (a neighbour of K's parent) and is not a node of N;
   // masters: N's nodes on the smallest entity holding it with nonzero
   // weight, z-major order; weights: N's tensor Lagrange basis at the node.
-  KeyMap hang(1024);
+  // Leaves are split into contiguous chunks worked on in parallel; each
+  // chunk records the hanging nodes it touches first, and the merge in leaf
+  // order keeps the record of the first leaf touching each node (the record
+  // a sequential pass over the leaves would make).
+  const int nch = nl < 4096 ? 1 : 4 * nthreads;
   std::vector<uint8_t> maybe_hang(nl, 0);   // leaf touches a coarser leaf
-  std::vector<HangRec> hrec;
-  std::vector<u128> hpool_m;
-  std::vector<double> hpool_w;
-  {
+  struct HangPart {
+    std::vector<u128> key;
+    std::vector<HangRec> rec;
+    std::vector<u128> pm;
+    std::vector<double> pw;
+  };
+  std::vector<HangPart> hparts(nch);
+  chunked(nl, nch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+    HangPart& H = hparts[ch];
+    KeyMap lh(1024);
     std::array<int, 3> offs[26];
     uint64_t last_parent = ~0ull;
     int nn = 0;
-    for (int64_t ci = 0; ci < nl; ++ci) {
+    for (int64_t ci = cb; ci < ce; ++ci) {
       const Cell& K = leaves[ci].c;
       if (K.level == 0) continue;
       Cell P = C.parent_of(K);
@@ -360,7 +398,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
               int jl[3] = {lists[0][jx], lists[1][jy], lists[2][jz]};
               uint32_t hc[3] = {kc[0][jl[0]], kc[1][jl[1]], dim == 3 ? kc[2][jl[2]] : 0};
               const u128 key = make_key(hc, dim);
-              if (hang.get(key) >= 0) continue;
+              if (lh.get(key) >= 0) continue;
               // per axis: fixed N index, or varying with the N basis weights
               int fixedJ[3] = {0, 0, 0};
               double w[3][5];
@@ -387,7 +425,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
               int rc[3];
               for (int i = 0; i < 3; ++i) rc[i] = (i < dim && fixedJ[i] < 0) ? n : 1;
               HangRec r;
-              r.start = (int64_t)hpool_m.size();
+              r.start = (int64_t)H.pm.size();
               for (int a2 = 0; a2 < rc[2]; ++a2)
                 for (int a1 = 0; a1 < rc[1]; ++a1)
                   for (int a0 = 0; a0 < rc[0]; ++a0) {
@@ -403,78 +441,158 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
                       }
                     }
                     uint32_t mc[3] = {nc[0][J[0]], nc[1][J[1]], dim == 3 ? nc[2][J[2]] : 0};
-                    hpool_m.push_back(make_key(mc, dim));
-                    hpool_w.push_back(ww);
+                    H.pm.push_back(make_key(mc, dim));
+                    H.pw.push_back(ww);
                   }
-              r.nm = (int)((int64_t)hpool_m.size() - r.start);
-              hang.get_or_insert(key, (int32_t)hrec.size());
-              hrec.push_back(r);
+              r.nm = (int)((int64_t)H.pm.size() - r.start);
+              lh.get_or_insert(key, (int32_t)H.rec.size());
+              H.rec.push_back(r);
+              H.key.push_back(key);
             }
       }
     }
+  });
+  T.mark("hanging (chunks)");
+  size_t n_rec = 0, n_pool = 0;
+  for (const HangPart& H : hparts) {
+    n_rec += H.rec.size();
+    n_pool += H.pm.size();
+  }
+  KeyMap hang(n_rec + 64);
+  std::vector<HangRec> hrec;
+  hrec.reserve(n_rec);
+  for (int ch = 0; ch < nch; ++ch) {
+    HangPart& H = hparts[ch];
+    for (size_t i = 0; i < H.rec.size(); ++i) {
+      const int32_t nxt = (int32_t)hrec.size();
+      if (hang.get_or_insert(H.key[i], nxt) != nxt) continue;
+      HangRec r = H.rec[i];
+      r.part = ch;
+      hrec.push_back(r);
+    }
+    H.key = std::vector<u128>();
+    H.rec = std::vector<HangRec>();
   }
 
   T.mark("hanging");
   // ---------------------------------------------------------- leaf numbering
+  // First touch over the leaves in order.  Each chunk numbers the nodes it
+  // touches in its own first-touch order; merging the chunks in leaf order
+  // then gives every node the id of the sequential pass (a node new to
+  // chunk c is numbered in the order of its first touch inside c, which is
+  // its first touch overall).  Hanging-node ids follow the same rule.
   KeyMap dofs(size_t(nl) * (dim == 3 ? k * k * k : k * k) + 64);
   std::vector<u128> dof_keys;
   std::vector<int8_t> dof_minlevel;
   std::vector<int32_t> hang_order;
   M.leaf_cellmap.resize(size_t(nl) * npc);
   {
-    int32_t next = 0;
-    for (int64_t ci = 0; ci < nl; ++ci) {
-      const Cell& K = leaves[ci].c;
-      uint32_t kc[3][5];
-      C.cell_codes(K, kc);
-      for (int li = 0; li < npc; ++li) {
-        u128 key = C.node_key(kc, li);
-        int32_t h = (hrec.empty() || !maybe_hang[ci]) ? -1 : hang.get(key);
-        if (h >= 0) {
-          if (hrec[h].id < 0) {
-            hrec[h].id = (int32_t)hang_order.size();
-            hang_order.push_back(h);
+    struct NumPart {
+      std::vector<u128> key;
+      std::vector<int8_t> minlev;
+      std::vector<int32_t> hfirst;
+      std::vector<int32_t> remap;
+    };
+    std::vector<NumPart> parts(nch);
+    // cell map entries: local node id (>= 0) or -(hanging record + 1)
+    chunked(nl, nch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+      NumPart& Q = parts[ch];
+      KeyMap lm(size_t(ce - cb) * (dim == 3 ? k * k * k : k * k) + 64);
+      KeyMap lhs(64);
+      for (int64_t ci = cb; ci < ce; ++ci) {
+        const Cell& K = leaves[ci].c;
+        uint32_t kc[3][5];
+        C.cell_codes(K, kc);
+        for (int li = 0; li < npc; ++li) {
+          u128 key = C.node_key(kc, li);
+          int32_t h = (hrec.empty() || !maybe_hang[ci]) ? -1 : hang.get(key);
+          if (h >= 0) {
+            if (lhs.get(u128(h)) < 0) {
+              lhs.get_or_insert(u128(h), 0);
+              Q.hfirst.push_back(h);
+            }
+            M.leaf_cellmap[size_t(ci) * npc + li] = -(h + 1);
+            continue;
           }
-          M.leaf_cellmap[size_t(ci) * npc + li] = -(hrec[h].id + 1);
-          continue;
+          const int32_t nxt = (int32_t)Q.key.size();
+          int32_t id = lm.get_or_insert(key, nxt);
+          if (id == nxt) {
+            Q.key.push_back(key);
+            Q.minlev.push_back(K.level);
+          } else if (K.level < Q.minlev[id]) {
+            Q.minlev[id] = K.level;
+          }
+          M.leaf_cellmap[size_t(ci) * npc + li] = id;
         }
-        int32_t id = dofs.get_or_insert(key, next);
+      }
+    });
+    T.mark("numbering (chunks)");
+    int32_t next = 0;
+    for (NumPart& Q : parts) {
+      Q.remap.resize(Q.key.size());
+      for (size_t i = 0; i < Q.key.size(); ++i) {
+        int32_t id = dofs.get_or_insert(Q.key[i], next);
         if (id == next) {
           ++next;
-          dof_keys.push_back(key);
-          dof_minlevel.push_back(K.level);
-        } else if (K.level < dof_minlevel[id]) {
-          dof_minlevel[id] = K.level;
+          dof_keys.push_back(Q.key[i]);
+          dof_minlevel.push_back(Q.minlev[i]);
+        } else if (Q.minlev[i] < dof_minlevel[id]) {
+          dof_minlevel[id] = Q.minlev[i];
         }
-        M.leaf_cellmap[size_t(ci) * npc + li] = id;
+        Q.remap[i] = id;
       }
+      for (int32_t h : Q.hfirst)
+        if (hrec[h].id < 0) {
+          hrec[h].id = (int32_t)hang_order.size();
+          hang_order.push_back(h);
+        }
+      Q.key = std::vector<u128>();
+      Q.minlev = std::vector<int8_t>();
     }
+    T.mark("numbering (merge)");
+    chunked(nl, nch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+      const std::vector<int32_t>& rm = parts[ch].remap;
+      for (size_t i = size_t(cb) * npc; i < size_t(ce) * npc; ++i) {
+        const int32_t v = M.leaf_cellmap[i];
+        M.leaf_cellmap[i] = v >= 0 ? rm[v] : -(hrec[-v - 1].id + 1);
+      }
+    });
     M.n_dofs = next;
   }
   T.mark("leaf numbering");
   M.n_hanging = (int64_t)hang_order.size();
   M.dirichlet.resize(M.n_dofs);
-  for (int64_t i = 0; i < M.n_dofs; ++i) M.dirichlet[i] = C.on_boundary(dof_keys[i]) ? 1 : 0;
-  M.con_off.assign(1, 0);
-  for (int32_t h : hang_order) {
-    const HangRec& r = hrec[h];
-    double sw = 0.0;
-    for (int q = 0; q < r.nm; ++q) {
-      int32_t id = dofs.get(hpool_m[r.start + q]);
-      if (id < 0) fail(-8, "constraint master is not a DoF (constraint chain)");
-      M.con_mas.push_back(id);
-      M.con_w.push_back(hpool_w[r.start + q]);
-      sw += hpool_w[r.start + q];
-    }
-    if (std::fabs(sw - 1.0) > 1e-12) fail(-8, "constraint weights do not sum to one");
-    M.con_off.push_back((int64_t)M.con_mas.size());
+  chunked(M.n_dofs, nch, nthreads, [&](int, int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) M.dirichlet[i] = C.on_boundary(dof_keys[i]) ? 1 : 0;
+  });
+  {
+    const int64_t H = M.n_hanging;
+    M.con_off.assign(H + 1, 0);
+    for (int64_t i = 0; i < H; ++i) M.con_off[i + 1] = M.con_off[i] + hrec[hang_order[i]].nm;
+    M.con_mas.resize(M.con_off[H]);
+    M.con_w.resize(M.con_off[H]);
+    chunked(H, nch, nthreads, [&](int, int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        const HangRec& r = hrec[hang_order[i]];
+        double sw = 0.0;
+        const HangPart& H = hparts[r.part];
+        for (int q = 0; q < r.nm; ++q) {
+          int32_t id = dofs.get(H.pm[r.start + q]);
+          if (id < 0) fail(-8, "constraint master is not a DoF (constraint chain)");
+          M.con_mas[M.con_off[i] + q] = id;
+          M.con_w[M.con_off[i] + q] = H.pw[r.start + q];
+          sw += H.pw[r.start + q];
+        }
+        if (std::fabs(sw - 1.0) > 1e-12) fail(-8, "constraint weights do not sum to one");
+      }
+    });
   }
   // in-cell constraints: masks and parent-arranged DoF ids
   M.leaf_mask.assign(nl, 0);
   M.leaf_cellmap_parent = M.leaf_cellmap;
-  {
+  chunked(nl, nch, nthreads, [&](int, int64_t cb, int64_t ce) {
     std::array<int, 3> offs[26];
-    for (int64_t ci = 0; ci < nl; ++ci) {
+    for (int64_t ci = cb; ci < ce; ++ci) {
       if (!maybe_hang[ci]) continue;
       const Cell& K = leaves[ci].c;
       const Cell P = C.parent_of(K);
@@ -534,9 +652,9 @@ Maps build_maps(const Forest& f, int k, const double* coeff) {
         M.leaf_cellmap_parent[size_t(ci) * npc + li] = id;
       }
     }
-    for (auto v : M.leaf_cellmap_parent)
-      if (v < 0) fail(-8, "hanging node outside an in-cell constraint");
-  }
+  });
+  for (auto v : M.leaf_cellmap_parent)
+    if (v < 0) fail(-8, "hanging node outside an in-cell constraint");
   dofs = KeyMap(16);
   T.mark("dirichlet+constraints");
 

@@ -56,6 +56,8 @@ struct Maps {
   std::vector<LevelLayout> layouts;  // device layout of levels >= 1
 };
 
-Maps build_maps(const Forest& f, int k, const double* coeff);
+// threads: host threads for the leaf-mesh phases (0: the hardware's, at
+// most 16); the result does not depend on it.
+Maps build_maps(const Forest& f, int k, const double* coeff, int threads = 0);
 
 }  // namespace gmg
