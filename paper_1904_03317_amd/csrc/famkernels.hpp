@@ -17,6 +17,10 @@
 // each sums its present position slots in a fixed order and applies the
 // same epilogue.  No atomics in global memory, no index arrays per node;
 // all loads of an epilogue are issued before their values are used.
+//
+// In 3D at k >= 3 a cell's values no longer fit one lane: the cooperative
+// kernels (*_coop) share each cell's 1D line contractions among the threads
+// of a workgroup through LDS and keep the same patch epilogues and slots.
 #pragma once
 #include "dispatch.hpp"
 #include "kernels.hpp"
@@ -102,9 +106,10 @@ struct Geo {
   static __device__ __forceinline__ int cpos(uint32_t c) { return (int)((c >> 23) & 7u); }
 };
 
-// Families per workgroup: LDS holds the input and output patches, the
-// entity bases of FB families and the position codes (80 KB, or 160 KB for
-// k >= 3, of the 160 KB of a gfx950 CU).
+// Families per workgroup of the lane-per-cell kernels (k <= 2, and 2D): LDS
+// holds the input and output patches, the entity bases of FB families and
+// the position codes (at most 80 KB at k <= 2, 160 KB at k >= 3 in 2D, of the
+// 160 KB of a gfx950 CU).
 template <int DIM, int K, typename T>
 struct FamShape {
   using G = Geo<DIM, K>;
@@ -122,9 +127,6 @@ struct FamShape {
   static constexpr int fb_raw = fb_lds < fb_cap ? fb_lds : fb_cap;
   static constexpr int FB = fb_raw >= 64 ? 64 : fb_raw >= 32 ? 32 : fb_raw >= 16 ? 16 : fb_raw >= 8 ? 8 : 4;
   static constexpr int THREADS = FB * CPF;
-  // sibling sum by lane moves (FP32 atomic adds in LDS measured several
-  // times slower; kept as the alternative for FP64)
-  static constexpr bool SHUFFLE = true;
   // entity positions handled per round of the output epilogue (registers)
   static constexpr int CH = 5;
   static constexpr int ITI = (G::NI * FB + THREADS - 1) / THREADS;
@@ -525,8 +527,6 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   EpiOps<T, S::ITI> iops;
   epi_load<T, EPI, S::ITI, false>(ep, inode, iops);
   stage_bases<DIM, K, T>(v, f0, sgb, sex, bq, bc, bo);
-  if constexpr (!S::SHUFFLE)
-    for (int e = tid; e < FB * MFP; e += S::THREADS) sout[e] = T(0);
   __syncthreads();
   if (EPI != kEpiDiag) {
     gather_patch<DIM, K, T>(f0, nf, xin, sgb, bq, bc, sin);
@@ -562,15 +562,12 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
     const T sc = fl < nf ? T(v.scale ? v.scale[f * CPF + cid] : v.scale0) : T(0);
 #pragma unroll
     for (int j = 0; j < NP; ++j) w[j] *= sc;
-    if constexpr (S::SHUFFLE) {
-      family_sum<DIM, N, T>(cid, w);
+    // sibling sum by lane moves (floating-point atomic adds in LDS measured
+    // several times slower)
+    family_sum<DIM, N, T>(cid, w);
 #pragma unroll
-      for (int j = 0; j < NP; ++j)
-        if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = w[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < NP; ++j) atomicAdd(&sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)], w[j]);
-    }
+    for (int j = 0; j < NP; ++j)
+      if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = w[j];
   }
   __syncthreads();
   patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
