@@ -199,7 +199,7 @@ def main():
                     help="add the C5 job (Q3 checkerboard, G global refinements) as request 128 of the stream")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (it has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
