@@ -152,13 +152,15 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
             ids.append(S.submit(big[0], big[1], coeff=big[2]))
         else:
             ids.append(S.submit(m, opts))
-    lat, its, dofs, status, nd = [], [], 0.0, [], []
+    lat, its, dofs, status, nd, stages = [], [], 0.0, [], [], []
     end = start
     for i in ids:
         S.wait(i, 1200)
         r = S.result(i)
         t = r["timing"]
         lat.append(t["finished"] - t["arrival"])
+        stages.append((t["setup_done"] - t["arrival"], t["admitted"] - t["setup_done"], t["bound"] - t["admitted"],
+                       t["finished"] - t["bound"]))
         its.append(r["iterations"])
         dofs += len(r["u"])
         nd.append(len(r["u"]))
@@ -169,6 +171,11 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
     S.close()
     lat = np.array(lat)
     span = end - start
+    stg = np.array(stages)
+    slow = lat >= np.percentile(lat, 99)
+    stage_names = ("host_setup", "wait_admission", "device_setup", "solve_and_copy_back")
+    breakdown = {"p50_s": {k: float(np.percentile(stg[:, i], 50)) for i, k in enumerate(stage_names)},
+                 "mean_s_slowest_1pct": {k: float(stg[slow, i].mean()) for i, k in enumerate(stage_names)}}
     big_info = None
     if big is not None:
         big_info = {"request": 128, "latency_s": float(lat[128]), "dofs": nd[128], "cg_iterations": its[128],
@@ -179,7 +186,7 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
             "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
             "cg_iterations_min": int(min(its)), "failed": int(sum(1 for s in status if s != 0)),
             "slots": slots, "host_threads": threads, "arena_peak_gb": st["arena_peak"] / 2 ** 30,
-            "large_job": big_info,
+            "large_job": big_info, "latency_stages": breakdown,
             "latency_includes": "queueing + host set-up + device set-up + solve + copy-back"}
 
 

@@ -1,6 +1,8 @@
 #include "layout.hpp"
 
+#include <exception>
 #include <string>
+#include <thread>
 
 #include "common.hpp"
 #include "maps.hpp"
@@ -166,7 +168,20 @@ void build_layouts(Maps& M) {
   M.layouts[0].n_dofs = M.levels[0].n_dofs;
   M.layouts[0].perm.resize(M.levels[0].n_dofs);
   for (int64_t i = 0; i < M.levels[0].n_dofs; ++i) M.layouts[0].perm[i] = (int32_t)i;
-  for (int l = 1; l <= L; ++l) build_level(M, M.levels[l], M.layouts[l]);
+  // levels are independent: one thread each (first exception rethrown)
+  std::vector<std::thread> th;
+  std::vector<std::exception_ptr> err(L + 1);
+  for (int l = 1; l <= L; ++l)
+    th.emplace_back([&M, &err, l] {
+      try {
+        build_level(M, M.levels[l], M.layouts[l]);
+      } catch (...) {
+        err[l] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
   const int nf = 1 << M.dim;
   for (int l = 1; l < L; ++l) {
     LevelLayout& Y = M.layouts[l];

@@ -121,7 +121,8 @@ struct Server {
   std::vector<Request*> running;
   std::map<uint64_t, std::unique_ptr<Request>> all;
   std::vector<std::thread> workers;
-  int maps_threads = 1;            // host threads per request's map build
+  int host_cpus = 1;               // host threads for map builds, shared by the workers
+  std::atomic<int> building{0};    // map builds in progress
   std::thread sched;
   std::atomic<bool> stop{false};
   uint64_t next_id = 1;
@@ -173,8 +174,15 @@ void worker_loop(Server* S) {
         P->opt = r->opt;
         P->kt = kernel_table(r->mesh->dim(), r->opt.degree);
         if (!P->kt) fail(GMG_E_INVAL, "no kernels for this dimension/degree");
-        P->maps = std::make_shared<const Maps>(
-            build_maps(*r->mesh, r->opt.degree, r->coeff.empty() ? nullptr : r->coeff.data(), S->maps_threads));
+        // the host threads are shared among the map builds in progress when
+        // this one starts (the maps do not depend on the thread count)
+        const int active = ++S->building;
+        struct Done {
+          std::atomic<int>& n;
+          ~Done() { --n; }
+        } done{S->building};
+        P->maps = std::make_shared<const Maps>(build_maps(
+            *r->mesh, r->opt.degree, r->coeff.empty() ? nullptr : r->coeff.data(), std::max(1, S->host_cpus / active)));
         const FE1D& fe = P->maps->fe;
         for (int i = 0; i < 25; ++i) {
           P->m64.M[i] = fe.M[i];
@@ -358,8 +366,7 @@ int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int3
       SRV_HIPCHECK(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
       S.slot_free.push_back(max_slots - 1 - i);
     }
-    // the workers build maps concurrently: each takes its share of the host
-    S.maps_threads = std::max(1, (int)std::min(16u, std::thread::hardware_concurrency()) / host_threads);
+    S.host_cpus = std::max(1, (int)std::min(16u, std::thread::hardware_concurrency()));
     for (int i = 0; i < host_threads; ++i) S.workers.emplace_back(gmg::worker_loop, &S);
     S.sched = std::thread(gmg::scheduler_loop, &S);
     *out = h.release();
