@@ -260,6 +260,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
         KeyMap& lmap = lmaps[l];
     LevelData& D = M.levels[l];
     D.level = l;
+    const auto t_level = std::chrono::steady_clock::now();
     {
       int64_t s = side_of(l);
       uint64_t last = ~0ull;
@@ -280,49 +281,79 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
     D.n_cells = (int64_t)D.cells.size();
     lmap.reset(size_t(D.n_cells) * (dim == 3 ? k * k * k : k * k) + 64);
     D.cellmap.resize(size_t(D.n_cells) * npc);
+    // first touch over the level cells, in chunks merged in cell order (as
+    // the leaf numbering)
+    const int lch = D.n_cells < 4096 ? 1 : 4 * nthreads;
+    std::vector<std::vector<u128>> ckeys(lch);
+    std::vector<std::vector<int32_t>> cremap(lch);
+    chunked(D.n_cells, lch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+      KeyMap lm(size_t(ce - cb) * (dim == 3 ? k * k * k : k * k) + 64);
+      std::vector<u128>& ck = ckeys[ch];
+      for (int64_t ci = cb; ci < ce; ++ci) {
+        uint32_t kc[3][5];
+        C.cell_codes(D.cells[ci], kc);
+        for (int li = 0; li < npc; ++li) {
+          u128 key = C.node_key(kc, li);
+          const int32_t nxt = (int32_t)ck.size();
+          int32_t id = lm.get_or_insert(key, nxt);
+          if (id == nxt) ck.push_back(key);
+          D.cellmap[size_t(ci) * npc + li] = id;
+        }
+      }
+    });
     int32_t next = 0;
     std::vector<u128> lkeys;
-    for (int64_t ci = 0; ci < D.n_cells; ++ci) {
-      uint32_t kc[3][5];
-      C.cell_codes(D.cells[ci], kc);
-      for (int li = 0; li < npc; ++li) {
-        u128 key = C.node_key(kc, li);
-        int32_t id = lmap.get_or_insert(key, next);
+    for (int ch = 0; ch < lch; ++ch) {
+      cremap[ch].resize(ckeys[ch].size());
+      for (size_t i = 0; i < ckeys[ch].size(); ++i) {
+        int32_t id = lmap.get_or_insert(ckeys[ch][i], next);
         if (id == next) {
           ++next;
-          lkeys.push_back(key);
+          lkeys.push_back(ckeys[ch][i]);
         }
-        D.cellmap[size_t(ci) * npc + li] = id;
+        cremap[ch][i] = id;
       }
+      ckeys[ch] = std::vector<u128>();
     }
+    chunked(D.n_cells, lch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+      for (size_t i = size_t(cb) * npc; i < size_t(ce) * npc; ++i) D.cellmap[i] = cremap[ch][D.cellmap[i]];
+    });
     D.n_dofs = next;
     D.flags.assign(D.n_dofs, kFlagS);
     if (l >= 1) {
-      std::array<int, 3> offs[26];
-      uint64_t last_parent = ~0ull;
-      int nn = 0;
-      for (int64_t ci = 0; ci < D.n_cells; ++ci) {
-        const Cell& K = D.cells[ci];
-        Cell P = C.parent_of(K);
-        uint64_t pk = f.key(P);
-        if (pk != last_parent) {
-          nn = C.leaf_neighbours(P, offs);
-          last_parent = pk;
+      // interface nodes: chunks collect them, the marking is sequential
+      std::vector<std::vector<int32_t>> inode(lch);
+      chunked(D.n_cells, lch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
+        std::array<int, 3> offs[26];
+        uint64_t last_parent = ~0ull;
+        int nn = 0;
+        for (int64_t ci = cb; ci < ce; ++ci) {
+          const Cell& K = D.cells[ci];
+          Cell P = C.parent_of(K);
+          uint64_t pk = f.key(P);
+          if (pk != last_parent) {
+            nn = C.leaf_neighbours(P, offs);
+            last_parent = pk;
+          }
+          for (int q = 0; q < nn; ++q) {
+            int lists[3][5], cnt[3];
+            if (!C.touch(K, P, offs[q], lists, cnt)) continue;
+            for (int jz = 0; jz < cnt[2]; ++jz)
+              for (int jy = 0; jy < cnt[1]; ++jy)
+                for (int jx = 0; jx < cnt[0]; ++jx) {
+                  int li = lists[0][jx] + n * (lists[1][jy] + n * lists[2][jz]);
+                  inode[ch].push_back(D.cellmap[size_t(ci) * npc + li]);
+                }
+          }
         }
-        for (int q = 0; q < nn; ++q) {
-          int lists[3][5], cnt[3];
-          if (!C.touch(K, P, offs[q], lists, cnt)) continue;
-          for (int jz = 0; jz < cnt[2]; ++jz)
-            for (int jy = 0; jy < cnt[1]; ++jy)
-              for (int jx = 0; jx < cnt[0]; ++jx) {
-                int li = lists[0][jx] + n * (lists[1][jy] + n * lists[2][jz]);
-                D.flags[D.cellmap[size_t(ci) * npc + li]] = kFlagI;
-              }
-        }
-      }
+      });
+      for (const auto& v : inode)
+        for (int32_t i : v) D.flags[i] = kFlagI;
     }
-    for (int64_t i = 0; i < D.n_dofs; ++i)
-      if (C.on_boundary(lkeys[i])) D.flags[i] = kFlagD;
+    chunked(D.n_dofs, lch, nthreads, [&](int, int64_t b0, int64_t e0) {
+      for (int64_t i = b0; i < e0; ++i)
+        if (C.on_boundary(lkeys[i])) D.flags[i] = kFlagD;
+    });
     for (int64_t i = 0; i < D.n_dofs; ++i)
       if (D.flags[i] == kFlagI) D.ilist.push_back((int32_t)i);
     for (int64_t ci = 0; ci < D.n_cells; ++ci) {
@@ -332,6 +363,10 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
           break;
         }
     }
+    if (T.on)
+      std::fprintf(stderr, "[gmg maps] level %d: %lld cells, %lld nodes, %.3f s\n", l, (long long)D.n_cells,
+                   (long long)D.n_dofs,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_level).count());
       });
     } catch (...) {
       std::lock_guard<std::mutex> lk(level_mu);
@@ -677,13 +712,16 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
     LevelData& D = M.levels[l];
     KeyMap& lmap = lmaps[l];
     // copy map for the leaf DoFs owned by this level
-    for (int64_t b = bstart[l]; b < bstart[l + 1]; ++b) {
-      int64_t i = bucket[b];
-      int32_t id = lmap.get(dof_keys[i]);
-      if (id < 0 || D.flags[id] == kFlagI) fail(-8, "copy map: leaf DoF not an S/D node of its level");
-      M.copy_level[i] = (int8_t)l;
-      M.copy_index[i] = id;
-    }
+    const int fch = bstart[l + 1] - bstart[l] < 65536 ? 1 : 4 * nthreads;
+    chunked(bstart[l + 1] - bstart[l], fch, nthreads, [&](int, int64_t b0, int64_t e0) {
+      for (int64_t b = bstart[l] + b0; b < bstart[l] + e0; ++b) {
+        int64_t i = bucket[b];
+        int32_t id = lmap.get(dof_keys[i]);
+        if (id < 0 || D.flags[id] == kFlagI) fail(-8, "copy map: leaf DoF not an S/D node of its level");
+        M.copy_level[i] = (int8_t)l;
+        M.copy_index[i] = id;
+      }
+    });
     lmap = KeyMap(16);
     // families and transfer maps
     if (l >= 1) {
@@ -695,41 +733,47 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
       D.parent.resize(D.n_fam);
       D.famap.assign(size_t(D.n_fam) * M.mf, -1);
       D.own.assign(size_t(D.n_fam) * M.own_words, 0u);
-      std::vector<int32_t> first(D.n_dofs, -1);
-      for (int64_t fi = 0; fi < D.n_fam; ++fi) {
-        Cell P = C.parent_of(D.cells[fi * nf]);
-        uint64_t pk = f.key(P);
-        auto it = std::lower_bound(Pl.keys.begin(), Pl.keys.end(), pk);
-        if (it == Pl.keys.end() || *it != pk) fail(-8, "family parent not found");
-        D.parent[fi] = (int32_t)(it - Pl.keys.begin());
-        for (int cid = 0; cid < nf; ++cid) {
-          const Cell& ch = D.cells[fi * nf + cid];
-          for (int i = 0; i < dim; ++i)
-            if (ch.a[i] != P.a[i] + ((cid >> i) & 1) * side_of(l))
-              fail(-8, "family children out of order");
-          for (int li = 0; li < npc; ++li) {
-            int jx = li % n, jy = (li / n) % n, jz = li / (n * n);
-            int fx = (cid & 1) * k + jx, fy = ((cid >> 1) & 1) * k + jy;
-            int fz = dim == 3 ? ((cid >> 2) & 1) * k + jz : 0;
-            int fidx = fx + m2 * (fy + m2 * fz);
-            int32_t v = D.cellmap[size_t(fi * nf + cid) * npc + li];
-            int32_t& slot = D.famap[size_t(fi) * M.mf + fidx];
-            if (slot >= 0 && slot != v) fail(-8, "inconsistent family map");
-            slot = v;
+      // parents, family maps and the complete-layer check per family (in
+      // chunks), then ownership by the first family touching each node
+      const int pch = D.n_fam < 1024 ? 1 : 4 * nthreads;
+      chunked(D.n_fam, pch, nthreads, [&](int, int64_t f0, int64_t f1) {
+        for (int64_t fi = f0; fi < f1; ++fi) {
+          Cell P = C.parent_of(D.cells[fi * nf]);
+          uint64_t pk = f.key(P);
+          auto it = std::lower_bound(Pl.keys.begin(), Pl.keys.end(), pk);
+          if (it == Pl.keys.end() || *it != pk) fail(-8, "family parent not found");
+          D.parent[fi] = (int32_t)(it - Pl.keys.begin());
+          for (int cid = 0; cid < nf; ++cid) {
+            const Cell& ch = D.cells[fi * nf + cid];
+            for (int i = 0; i < dim; ++i)
+              if (ch.a[i] != P.a[i] + ((cid >> i) & 1) * side_of(l))
+                fail(-8, "family children out of order");
+            for (int li = 0; li < npc; ++li) {
+              int jx = li % n, jy = (li / n) % n, jz = li / (n * n);
+              int fx = (cid & 1) * k + jx, fy = ((cid >> 1) & 1) * k + jy;
+              int fz = dim == 3 ? ((cid >> 2) & 1) * k + jz : 0;
+              int fidx = fx + m2 * (fy + m2 * fz);
+              int32_t v = D.cellmap[size_t(fi * nf + cid) * npc + li];
+              int32_t& slot = D.famap[size_t(fi) * M.mf + fidx];
+              if (slot >= 0 && slot != v) fail(-8, "inconsistent family map");
+              slot = v;
+            }
           }
+          // complete-layer rule: parent nodes touched by the transfer are S or D
+          for (int li = 0; li < npc; ++li)
+            if (Pl.flags[Pl.cellmap[size_t(D.parent[fi]) * npc + li]] == kFlagI)
+              fail(-8, "complete-layer rule violated");
         }
+      });
+      std::vector<uint8_t> seen(D.n_dofs, 0);
+      for (int64_t fi = 0; fi < D.n_fam; ++fi)
         for (int q = 0; q < M.mf; ++q) {
           int32_t v = D.famap[size_t(fi) * M.mf + q];
-          if (first[v] < 0) {
-            first[v] = (int32_t)fi;
+          if (!seen[v]) {
+            seen[v] = 1;
             D.own[size_t(fi) * M.own_words + q / 32] |= 1u << (q % 32);
           }
         }
-        // complete-layer rule: parent nodes touched by the transfer are S or D
-        for (int li = 0; li < npc; ++li)
-          if (Pl.flags[Pl.cellmap[size_t(D.parent[fi]) * npc + li]] == kFlagI)
-            fail(-8, "complete-layer rule violated");
-      }
     }
     });
   T.mark("levels done");

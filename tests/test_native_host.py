@@ -33,10 +33,11 @@ def test_maps_bit_exact(case):
     compare_maps(P, discretize(f, k))
 
 
-# above 4096 leaves the leaf-mesh phases run in parallel chunks merged in
-# leaf order: these meshes (4.5e3 and 6.3e3 leaves) check that the merge
-# reproduces the sequential first-touch numbering and constraint records
-@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C5", 2)])
+# above 4096 leaves (level cells; 1024 families) the set-up phases run in
+# parallel chunks merged in order: these meshes (4.5e3 to 4.3e4 leaves)
+# check that the merges reproduce the sequential first-touch numbering,
+# constraint records, flags and family ownership
+@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C5", 2), ("C2", 3)])
 def test_workload_maps_bit_exact(name, g):
     w = gi.workload(name, g=g)
     m, P, _ = library_problem(w.recipe, w.degree)
