@@ -178,9 +178,12 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
                  "mean_s_slowest_1pct": {k: float(stg[slow, i].mean()) for i, k in enumerate(stage_names)}}
     big_info = None
     if big is not None:
+        lo, so = np.delete(lat, 128), np.delete(stg, 128, axis=0)
+        slow_o = lo >= np.percentile(lo, 99)
         big_info = {"request": 128, "latency_s": float(lat[128]), "dofs": nd[128], "cg_iterations": its[128],
-                    "p50_s_others": float(np.percentile(np.delete(lat, 128), 50)),
-                    "p99_s_others": float(np.percentile(np.delete(lat, 128), 99))}
+                    "stages_s": {k: float(stg[128, i]) for i, k in enumerate(stage_names)},
+                    "p50_s_others": float(np.percentile(lo, 50)), "p99_s_others": float(np.percentile(lo, 99)),
+                    "mean_s_slowest_1pct_others": {k: float(so[slow_o, i].mean()) for i, k in enumerate(stage_names)}}
     return {"requests": n_req, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "arrival_rate_rps": rate, "throughput_rps": n_req / span,
             "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
