@@ -52,6 +52,13 @@ class KeyMap {
       i = (i + 1) & mask_;
     }
   }
+  // replace the value of a present key
+  void set(u128 k, int32_t v) {
+    size_t i = hash128(k) & mask_;
+    while (vals_[i] >= 0 && keys_[i] != k) i = (i + 1) & mask_;
+    if (vals_[i] < 0) fail(-8, "key map: key absent");
+    vals_[i] = v;
+  }
   // insert (k, v) if absent; returns the stored value
   int32_t get_or_insert(u128 k, int32_t v) {
     if (2 * (size_ + 1) > keys_.size()) grow();
@@ -86,6 +93,22 @@ class KeyMap {
   std::vector<u128> keys_;
   std::vector<int32_t> vals_;
   size_t mask_ = 0, size_ = 0;
+};
+
+// KeyMap in 16 parts chosen by the top bits of the hash (the slot index uses
+// the low bits), so that threads can fill the parts in parallel.
+class PKeyMap {
+ public:
+  static constexpr int P = 16;
+  static int part_of(u128 k) { return (int)(hash128(k) >> 60); }
+  int32_t get(u128 k) const { return m_[part_of(k)].get(k); }
+  KeyMap& part(int p) { return m_[p]; }
+  void clear() {
+    for (auto& m : m_) m = KeyMap(16);
+  }
+
+ private:
+  KeyMap m_[P];
 };
 
 // uint64 -> uint8 map (0 = absent), linear probing, grows at 50% load.

@@ -160,6 +160,67 @@ struct HangRec {
   int32_t part = 0;
 };
 
+// Global first-touch ids of keys listed per chunk (chunks in order; inside
+// a chunk in its first-touch order, without repeats): remap[c][i] is the id
+// of key ck[c][i], keys lists the keys by id and M maps key -> id.  The id
+// of a key is the rank of its first occurrence in chunk order, as a
+// sequential pass would number it.  Parallel over the parts of M: every
+// occurrence of a key falls in the same part.
+template <class F>
+void chunked(int64_t n, int nch, int nt, F&& fn);
+
+void merge_first_touch(const std::vector<std::vector<u128>>& ck, int nt, PKeyMap& M, std::vector<u128>& keys,
+                       std::vector<std::vector<int32_t>>& remap) {
+  const int nch = (int)ck.size();
+  constexpr int P = PKeyMap::P;
+  std::vector<std::vector<int32_t>> bk(size_t(nch) * P);
+  chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
+    for (size_t i = 0; i < ck[c].size(); ++i) bk[size_t(c) * P + PKeyMap::part_of(ck[c][i])].push_back((int32_t)i);
+  });
+  // per part, in chunk order: the first occurrence of each key, and for
+  // every later one a reference (c0 << 32 | i0) to it
+  std::vector<std::vector<int64_t>> ref(nch);
+  for (int c = 0; c < nch; ++c) ref[c].assign(ck[c].size(), -1);
+  std::vector<std::vector<int64_t>> firsts(P);
+  chunked(P, P, nt, [&](int p, int64_t, int64_t) {
+    size_t n = 0;
+    for (int c = 0; c < nch; ++c) n += bk[size_t(c) * P + p].size();
+    KeyMap& m = M.part(p);
+    m = KeyMap(n + 64);
+    std::vector<int64_t>& fs = firsts[p];
+    for (int c = 0; c < nch; ++c)
+      for (int32_t i : bk[size_t(c) * P + p]) {
+        const int32_t nxt = (int32_t)fs.size();
+        const int32_t v = m.get_or_insert(ck[c][i], nxt);
+        if (v == nxt)
+          fs.push_back((int64_t(c) << 32) | uint32_t(i));
+        else
+          ref[c][i] = fs[v];
+      }
+  });
+  bk = std::vector<std::vector<int32_t>>();
+  // ids in chunk order
+  keys.clear();
+  remap.assign(nch, std::vector<int32_t>());
+  int32_t next = 0;
+  for (int c = 0; c < nch; ++c) {
+    remap[c].assign(ck[c].size(), -1);
+    for (size_t i = 0; i < ck[c].size(); ++i)
+      if (ref[c][i] < 0) {
+        remap[c][i] = next++;
+        keys.push_back(ck[c][i]);
+      }
+  }
+  chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
+    for (size_t i = 0; i < ck[c].size(); ++i)
+      if (ref[c][i] >= 0) remap[c][i] = remap[ref[c][i] >> 32][uint32_t(ref[c][i])];
+  });
+  chunked(P, P, nt, [&](int p, int64_t, int64_t) {
+    KeyMap& m = M.part(p);
+    for (int64_t f : firsts[p]) m.set(ck[f >> 32][uint32_t(f)], remap[f >> 32][uint32_t(f)]);
+  });
+}
+
 // fn(chunk, begin, end) over [0, n) cut into nch contiguous chunks, on nt
 // threads (this one included); the first exception is rethrown after all
 // chunks finished.
@@ -232,7 +293,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   // while this thread numbers the leaf mesh.
   const int L = f.max_level();
   M.levels.resize(L + 1);
-  std::vector<KeyMap> lmaps(L + 1, KeyMap(16));
+  std::vector<PKeyMap> lmaps(L + 1);
   std::exception_ptr level_error;
   std::mutex level_mu;
   auto parallel_levels = [&](auto&& fn) {
@@ -257,7 +318,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   level_threads.emplace_back([&] {
     try {
       parallel_levels([&](int l) {
-        KeyMap& lmap = lmaps[l];
+        PKeyMap& lmap = lmaps[l];
     LevelData& D = M.levels[l];
     D.level = l;
     const auto t_level = std::chrono::steady_clock::now();
@@ -279,7 +340,6 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
       }
     }
     D.n_cells = (int64_t)D.cells.size();
-    lmap.reset(size_t(D.n_cells) * (dim == 3 ? k * k * k : k * k) + 64);
     D.cellmap.resize(size_t(D.n_cells) * npc);
     // first touch over the level cells, in chunks merged in cell order (as
     // the leaf numbering)
@@ -301,20 +361,10 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
         }
       }
     });
-    int32_t next = 0;
     std::vector<u128> lkeys;
-    for (int ch = 0; ch < lch; ++ch) {
-      cremap[ch].resize(ckeys[ch].size());
-      for (size_t i = 0; i < ckeys[ch].size(); ++i) {
-        int32_t id = lmap.get_or_insert(ckeys[ch][i], next);
-        if (id == next) {
-          ++next;
-          lkeys.push_back(ckeys[ch][i]);
-        }
-        cremap[ch][i] = id;
-      }
-      ckeys[ch] = std::vector<u128>();
-    }
+    merge_first_touch(ckeys, nthreads, lmap, lkeys, cremap);
+    ckeys = std::vector<std::vector<u128>>();
+    const int32_t next = (int32_t)lkeys.size();
     chunked(D.n_cells, lch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
       for (size_t i = size_t(cb) * npc; i < size_t(ce) * npc; ++i) D.cellmap[i] = cremap[ch][D.cellmap[i]];
     });
@@ -516,7 +566,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   // then gives every node the id of the sequential pass (a node new to
   // chunk c is numbered in the order of its first touch inside c, which is
   // its first touch overall).  Hanging-node ids follow the same rule.
-  KeyMap dofs(size_t(nl) * (dim == 3 ? k * k * k : k * k) + 64);
+  PKeyMap dofs;
   std::vector<u128> dof_keys;
   std::vector<int8_t> dof_minlevel;
   std::vector<int32_t> hang_order;
@@ -562,28 +612,28 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
       }
     });
     T.mark("numbering (chunks)");
-    int32_t next = 0;
-    for (NumPart& Q : parts) {
-      Q.remap.resize(Q.key.size());
-      for (size_t i = 0; i < Q.key.size(); ++i) {
-        int32_t id = dofs.get_or_insert(Q.key[i], next);
-        if (id == next) {
-          ++next;
-          dof_keys.push_back(Q.key[i]);
-          dof_minlevel.push_back(Q.minlev[i]);
-        } else if (Q.minlev[i] < dof_minlevel[id]) {
-          dof_minlevel[id] = Q.minlev[i];
-        }
-        Q.remap[i] = id;
+    {
+      std::vector<std::vector<u128>> ck(nch);
+      std::vector<std::vector<int32_t>> rm;
+      for (int ch = 0; ch < nch; ++ch) ck[ch].swap(parts[ch].key);
+      merge_first_touch(ck, nthreads, dofs, dof_keys, rm);
+      ck = std::vector<std::vector<u128>>();
+      // smallest level of the leaves containing each node
+      dof_minlevel.assign(dof_keys.size(), INT8_MAX);
+      for (int ch = 0; ch < nch; ++ch) {
+        NumPart& Q = parts[ch];
+        for (size_t i = 0; i < rm[ch].size(); ++i)
+          if (Q.minlev[i] < dof_minlevel[rm[ch][i]]) dof_minlevel[rm[ch][i]] = Q.minlev[i];
+        Q.remap.swap(rm[ch]);
+        Q.minlev = std::vector<int8_t>();
+        for (int32_t h : Q.hfirst)
+          if (hrec[h].id < 0) {
+            hrec[h].id = (int32_t)hang_order.size();
+            hang_order.push_back(h);
+          }
       }
-      for (int32_t h : Q.hfirst)
-        if (hrec[h].id < 0) {
-          hrec[h].id = (int32_t)hang_order.size();
-          hang_order.push_back(h);
-        }
-      Q.key = std::vector<u128>();
-      Q.minlev = std::vector<int8_t>();
     }
+    const int32_t next = (int32_t)dof_keys.size();
     T.mark("numbering (merge)");
     chunked(nl, nch, nthreads, [&](int ch, int64_t cb, int64_t ce) {
       const std::vector<int32_t>& rm = parts[ch].remap;
@@ -690,7 +740,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   });
   for (auto v : M.leaf_cellmap_parent)
     if (v < 0) fail(-8, "hanging node outside an in-cell constraint");
-  dofs = KeyMap(16);
+  dofs.clear();
   T.mark("dirichlet+constraints");
 
   // ---------------------------------------------------------- levels (rest)
@@ -710,7 +760,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   M.copy_index.resize(M.n_dofs);
   parallel_levels([&](int l) {
     LevelData& D = M.levels[l];
-    KeyMap& lmap = lmaps[l];
+    PKeyMap& lmap = lmaps[l];
     // copy map for the leaf DoFs owned by this level
     const int fch = bstart[l + 1] - bstart[l] < 65536 ? 1 : 4 * nthreads;
     chunked(bstart[l + 1] - bstart[l], fch, nthreads, [&](int, int64_t b0, int64_t e0) {
@@ -722,7 +772,7 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
         M.copy_index[i] = id;
       }
     });
-    lmap = KeyMap(16);
+    lmap.clear();
     // families and transfer maps
     if (l >= 1) {
       const LevelData& Pl = M.levels[l - 1];
