@@ -199,18 +199,26 @@ void merge_first_touch(const std::vector<std::vector<u128>>& ck, int nt, PKeyMap
       }
   });
   bk = std::vector<std::vector<int32_t>>();
-  // ids in chunk order
-  keys.clear();
+  // ids in chunk order: first occurrences counted per chunk, numbered
+  // from the chunk's prefix
+  std::vector<int64_t> base(nch + 1, 0);
+  chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
+    int64_t n = 0;
+    for (size_t i = 0; i < ck[c].size(); ++i) n += ref[c][i] < 0;
+    base[c + 1] = n;
+  });
+  for (int c = 0; c < nch; ++c) base[c + 1] += base[c];
+  keys.assign(base[nch], u128(0));
   remap.assign(nch, std::vector<int32_t>());
-  int32_t next = 0;
-  for (int c = 0; c < nch; ++c) {
+  chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
     remap[c].assign(ck[c].size(), -1);
+    int64_t id = base[c];
     for (size_t i = 0; i < ck[c].size(); ++i)
       if (ref[c][i] < 0) {
-        remap[c][i] = next++;
-        keys.push_back(ck[c][i]);
+        remap[c][i] = (int32_t)id;
+        keys[id++] = ck[c][i];
       }
-  }
+  });
   chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
     for (size_t i = 0; i < ck[c].size(); ++i)
       if (ref[c][i] >= 0) remap[c][i] = remap[ref[c][i] >> 32][uint32_t(ref[c][i])];
