@@ -108,7 +108,7 @@ class PKeyMap {
   }
 
  private:
-  KeyMap m_[P];
+  std::vector<KeyMap> m_ = std::vector<KeyMap>(P, KeyMap(16));
 };
 
 // uint64 -> uint8 map (0 = absent), linear probing, grows at 50% load.

@@ -173,6 +173,9 @@ void merge_first_touch(const std::vector<std::vector<u128>>& ck, int nt, PKeyMap
                        std::vector<std::vector<int32_t>>& remap) {
   const int nch = (int)ck.size();
   constexpr int P = PKeyMap::P;
+  size_t total = 0;
+  for (const auto& c : ck) total += c.size();
+  if (total < 100000) nt = 1;  // small meshes: no threads (their start-up costs more than the work)
   std::vector<std::vector<int32_t>> bk(size_t(nch) * P);
   chunked(nch, nch, nt, [&](int c, int64_t, int64_t) {
     for (size_t i = 0; i < ck[c].size(); ++i) bk[size_t(c) * P + PKeyMap::part_of(ck[c][i])].push_back((int32_t)i);
