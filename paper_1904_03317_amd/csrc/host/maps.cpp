@@ -160,15 +160,37 @@ struct HangRec {
   int32_t part = 0;
 };
 
+// fn(chunk, begin, end) over [0, n) cut into nch contiguous chunks, on nt
+// threads (this one included); the first exception is rethrown after all
+// chunks finished.
+template <class F>
+void chunked(int64_t n, int nch, int nt, F&& fn) {
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  auto work = [&] {
+    for (int c = next++; c < nch; c = next++) {
+      try {
+        fn(c, n * c / nch, n * (c + 1) / nch);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!err) err = std::current_exception();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < std::min(nt, nch); ++t) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
+
 // Global first-touch ids of keys listed per chunk (chunks in order; inside
 // a chunk in its first-touch order, without repeats): remap[c][i] is the id
 // of key ck[c][i], keys lists the keys by id and M maps key -> id.  The id
 // of a key is the rank of its first occurrence in chunk order, as a
 // sequential pass would number it.  Parallel over the parts of M: every
 // occurrence of a key falls in the same part.
-template <class F>
-void chunked(int64_t n, int nch, int nt, F&& fn);
-
 void merge_first_touch(const std::vector<std::vector<u128>>& ck, int nt, PKeyMap& M, std::vector<u128>& keys,
                        std::vector<std::vector<int32_t>>& remap) {
   const int nch = (int)ck.size();
@@ -232,30 +254,6 @@ void merge_first_touch(const std::vector<std::vector<u128>>& ck, int nt, PKeyMap
   });
 }
 
-// fn(chunk, begin, end) over [0, n) cut into nch contiguous chunks, on nt
-// threads (this one included); the first exception is rethrown after all
-// chunks finished.
-template <class F>
-void chunked(int64_t n, int nch, int nt, F&& fn) {
-  std::atomic<int> next{0};
-  std::exception_ptr err;
-  std::mutex mu;
-  auto work = [&] {
-    for (int c = next++; c < nch; c = next++) {
-      try {
-        fn(c, n * c / nch, n * (c + 1) / nch);
-      } catch (...) {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!err) err = std::current_exception();
-      }
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < std::min(nt, nch); ++t) th.emplace_back(work);
-  work();
-  for (auto& x : th) x.join();
-  if (err) std::rethrow_exception(err);
-}
 
 }  // namespace
 
@@ -549,11 +547,8 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
     }
   });
   T.mark("hanging (chunks)");
-  size_t n_rec = 0, n_pool = 0;
-  for (const HangPart& H : hparts) {
-    n_rec += H.rec.size();
-    n_pool += H.pm.size();
-  }
+  size_t n_rec = 0;
+  for (const HangPart& H : hparts) n_rec += H.rec.size();
   KeyMap hang(n_rec + 64);
   std::vector<HangRec> hrec;
   hrec.reserve(n_rec);
