@@ -18,7 +18,7 @@ sys.path.insert(0, os.path.join(HERE, "cpuemu"))
 
 # (case, precision of the multigrid levels)
 EMU_CASES = [("fichera-q1", 64), ("cube-q2", 64), ("lshape-q1", 32), ("fichera-q2", 32), ("fichera-q3", 64),
-             ("fichera-q4", 32),
+             ("fichera-q4", 32), ("lshape-q4", 32),
              # degenerate: no free DoF, one level only, one family at degree 3
              ("cube-q1-g0", 64), ("fichera-q2-g0", 64), ("cube-q3-g1", 32)]
 

@@ -53,7 +53,7 @@ def test_leaf_operator_and_rhs(case):
 
 
 @pytest.mark.parametrize("prec,tol", [(64, 1e-13), (32, 2e-6)])
-@pytest.mark.parametrize("case", ["lshape-q1", "fichera-q2", "fichera-q3", "fichera-q4"])
+@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q4", "fichera-q2", "fichera-q3", "fichera-q4"])
 def test_level_operators(case, prec, tol):
     op, P = _pair(case, prec=prec, coeff="checker" if "fichera" in case else "one")
     d = op.disc
@@ -84,7 +84,8 @@ def test_level_operators(case, prec, tol):
             assert np.abs(got).max() == 0.0
 
 
-@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "fichera-q1", "fichera-q2", "fichera-q3", "fichera-q4"])
+@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "lshape-q4", "fichera-q1", "fichera-q2", "fichera-q3",
+                                  "fichera-q4"])
 def test_lambda_and_vcycle_fp64(case):
     op, P = _pair(case, coeff="checker" if "fichera" in case else "one")
     info = P.info()
