@@ -450,16 +450,25 @@ struct CellCon {
     double s = 0.0;
     if (e < 3) {
       const int A = e, Pa = P(A), Qa = Q(A);
+      double wp[N], wq[N];
 #pragma unroll
-      for (int Jq = 0; Jq < N; ++Jq)
+      for (int J = 0; J < N; ++J) {
+        wp[J] = emb(sE, bb[Pa], p[Pa], J);
+        wq[J] = emb(sE, bb[Qa], p[Qa], J);
+      }
+#pragma unroll
+      for (int Jq = 0; Jq < N; ++Jq) {
+        double t = 0.0;
 #pragma unroll
         for (int Jp = 0; Jp < N; ++Jp) {
           int q[3];
           q[A] = JB[A];
           q[Pa] = Jp;
           q[Qa] = Jq;
-          s += emb(sE, bb[Pa], p[Pa], Jp) * emb(sE, bb[Qa], p[Qa], Jq) * c[lid(q)];
+          t += wp[Jp] * c[lid(q)];
         }
+        s += wq[Jq] * t;
+      }
     } else {
       const int A = e - 3;
 #pragma unroll
@@ -493,16 +502,25 @@ struct CellCon {
       if (!active(e) || !contains(e, J)) continue;
       if (e < 3) {
         const int A = e, Pa = P(A), Qa = Q(A);
+        double wp[N], wq[N];
 #pragma unroll
-        for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a) {
+          wp[a] = emb(sE, bb[Pa], a, J[Pa]);
+          wq[a] = emb(sE, bb[Qa], a, J[Qa]);
+        }
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          double t = 0.0;
 #pragma unroll
           for (int a = 0; a < N; ++a) {
             int q[3];
             q[A] = JB[A];
             q[Pa] = a;
             q[Qa] = b;
-            if (claim(q) == e) s += emb(sE, bb[Pa], a, J[Pa]) * emb(sE, bb[Qa], b, J[Qa]) * c[lid(q)];
+            if (claim(q) == e) t += wp[a] * c[lid(q)];
           }
+          s += wq[b] * t;
+        }
       } else {
         const int A = e - 3;
 #pragma unroll
