@@ -162,3 +162,16 @@ def test_clone_keeps_maps():
     assert P32.info().mg_precision == 32 and P32.workspace_bytes() < P64.workspace_bytes()
     with pytest.raises(gmg.GMGError):
         P64.clone(gmg.options(degree=k + 1))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it exits with a message
+    before touching a device."""
+    import os
+    import subprocess
+    import sys
+
+    from helpers import ROOT
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
