@@ -73,3 +73,52 @@ def compare_maps(P, d):
         assert np.array_equal(P.array("LEVEL_FLAGS", l), lev.flags)
         if l:
             assert np.array_equal(P.array("LEVEL_PARENT", l), lev.parent_index)
+
+
+def _abs_ref(dim, k, mass):
+    """Cell matrix assembled from the absolute values of the 1D factors: a
+    majorant of the size of every product the tensor-product evaluation
+    forms, so that (|A|-majorant |x|)_i bounds the rounding of row i."""
+    from oracle import basis
+    M = np.abs(basis.mass_1d(k))
+    K = np.abs(basis.stiff_1d(k))
+    if mass:
+        return np.kron(np.kron(M, M), M) if dim == 3 else np.kron(M, M)
+    if dim == 2:
+        return np.kron(M, K) + np.kron(K, M)
+    return np.kron(np.kron(M, M), K) + np.kron(np.kron(M, K), M) + np.kron(np.kron(K, M), M)
+
+
+def leaf_row_scale(op, x, mass=False):
+    """Row scales of the constrained leaf operator (or mass matrix) applied
+    to x: |C|^T A_abs |C| |x| with the cell majorant above; Dirichlet rows 0."""
+    import scipy.sparse as sp
+    from oracle.assemble import _assemble, _extended, cell_h, constraint_matrix
+    d = op.disc
+    leaf, dim, k = d.leaf, d.forest.dim, d.k
+    N, H = leaf.n_dofs, len(leaf.hkeys)
+    h = cell_h(leaf.cells, dim)
+    sc = h ** dim if mass else np.asarray(op.coeff) * h ** (dim - 2)
+    Aa = _assemble(_extended(leaf.cellmap, N), sc, _abs_ref(dim, k, mass), N + H)
+    C = abs(constraint_matrix(leaf))
+    s = C.T @ (Aa @ (C @ np.abs(x)))
+    s[~op.free] = 0.0
+    return s
+
+
+def level_row_scale(d, l, lcoeff, x):
+    from oracle.assemble import _assemble
+    from oracle.forest import side
+    lev = d.levels[l]
+    dim, k = d.forest.dim, d.k
+    h = side(l) / float(1 << 20)
+    Aa = _assemble(lev.cellmap, lcoeff * h ** (dim - 2), _abs_ref(dim, k, False), lev.n_dofs)
+    return Aa @ np.abs(x)
+
+
+def row_err(got, want, scale):
+    """largest |got_i - want_i| / scale_i over the rows with a nonzero scale;
+    rows with a zero scale must match exactly"""
+    nz = scale > 0
+    assert np.all(got[~nz] == want[~nz])
+    return float((np.abs(got - want)[nz] / scale[nz]).max()) if nz.any() else 0.0

@@ -1,13 +1,18 @@
 """GPU parity: the HIP path through the C ABI against the oracle on the same
-seeded inputs.  Tolerances: FP64 operators 1e-13 relative (rounding order of
-atomic scatter), FP32 operators 2e-6, FP64 V-cycle 1e-11, FP64 solve 1e-10
-relative solution error at equal iteration counts; maps are compared
-bit-exactly on the host (test_native_host)."""
+seeded inputs, element by element.  Tolerances: operator outputs row by row
+against the row scale (|A| |x|)_i, where |A| is the operator assembled from
+the absolute values of the 1D factors (a majorant of every product the
+tensor-product evaluation forms), FP64 1e-13 and FP32 2e-6 (the two sides
+form the same products in a different order, so they differ by a few dozen
+units of rounding of the row scale at most); FP64 V-cycle 1e-11 and FP64
+solve 1e-10 relative, both in the 2-norm
+and entry by entry against the largest entry; maps are compared bit-exactly
+on the host (test_native_host)."""
 import numpy as np
 import pytest
 
 import gmg_inputs as gi
-from helpers import CASES, library_problem, oracle_problem
+from helpers import CASES, leaf_row_scale, level_row_scale, library_problem, oracle_problem, row_err
 from oracle.assemble import level_coefficients, level_matrix
 
 pytestmark = pytest.mark.gpu
@@ -28,6 +33,16 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def rel_inf(a, b):
+    """largest entry-wise difference against the largest entry"""
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def close(a, b, tol):
+    """2-norm and entry-wise relative differences both within tol"""
+    return rel(a, b) <= tol and rel_inf(a, b) <= tol
+
+
 def _pair(case, prec=64, coeff="one", **kw):
     rec, k = CASES[case]
     op, _ = oracle_problem(rec, k, coeff_kind=coeff)
@@ -45,11 +60,11 @@ def test_leaf_operator_and_rhs(case):
     x[~op.free] = 0
     y = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
     P.apply_leaf(dev(x), y)
-    assert rel(host(y), op.A @ x) <= 1e-13
+    assert row_err(host(y), op.A @ x, leaf_row_scale(op, x)) <= 1e-13
     f = 1.0 + rng.standard_normal(op.n_dofs)
     b = torch.zeros_like(y)
     P.rhs(dev(f), b)
-    assert rel(host(b), op.rhs(f)) <= 1e-13
+    assert row_err(host(b), op.rhs(f), leaf_row_scale(op, f, mass=True)) <= 1e-13
 
 
 @pytest.mark.parametrize("prec,tol", [(64, 1e-13), (32, 2e-6)])
@@ -71,17 +86,15 @@ def test_level_operators(case, prec, tol):
         y = torch.zeros(lev.n_dofs, dtype=tdt, device="cuda")
         P.apply_level(l, 0, dev(xd, tdt), y)
         xr = x.astype(np.float32).astype(np.float64) if prec == 32 else x
-        assert rel(host(y).astype(np.float64)[perm], A @ xr) <= tol, l
+        assert row_err(host(y).astype(np.float64)[perm], A @ xr, level_row_scale(d, l, lc[l], xr)) <= tol, l
         # edge coupling A^{SI} x^I on S rows
         S, I = lev.flags == 0, lev.flags == 1
         want = np.zeros(lev.n_dofs)
         want[S] = A[S][:, I] @ xr[I]
         P.apply_level(l, 1, dev(xd, tdt), y)
         got = host(y).astype(np.float64)[perm]
-        if np.linalg.norm(want) > 0:
-            assert rel(got, want) <= tol, l
-        else:
-            assert np.abs(got).max() == 0.0
+        sc = np.where(S, level_row_scale(d, l, lc[l], np.where(I, xr, 0.0)), 0.0)
+        assert row_err(got, want, sc) <= tol, l
 
 
 @pytest.mark.parametrize("case", ["lshape-q1", "lshape-q2", "lshape-q4", "fichera-q1", "fichera-q2", "fichera-q3",
@@ -96,10 +109,10 @@ def test_lambda_and_vcycle_fp64(case):
     r[~op.free] = 0
     z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
     P.vcycle(dev(r), z)
-    assert rel(host(z), op.mg.vcycle(r)) <= 1e-11
+    assert close(host(z), op.mg.vcycle(r), 1e-11)
 
 
-@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q2"])
+@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q2", "fichera-q4", "lshape-q4", "fichera-q3"])
 def test_vcycle_fp32_close_to_fp64(case):
     op, P = _pair(case, prec=32)
     rng = np.random.default_rng(8)
@@ -107,7 +120,7 @@ def test_vcycle_fp32_close_to_fp64(case):
     r[~op.free] = 0
     z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
     P.vcycle(dev(r), z)
-    assert rel(host(z), op.mg.vcycle(r)) <= 1e-5
+    assert close(host(z), op.mg.vcycle(r), 1e-5)
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
@@ -120,11 +133,11 @@ def test_solve_fp64_matches_oracle_iterate(case, use_graph):
     st, its, h = P.solve(dev(f), u)
     assert st == 0 and ok
     assert its == it
-    assert rel(host(u), x) <= 1e-10
+    assert close(host(u), x, 1e-10)
     assert np.allclose(h, hist, rtol=1e-6, atol=1e-14)
 
 
-@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q1", "fichera-q3"])
+@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q1", "fichera-q3", "fichera-q4", "lshape-q4"])
 def test_solve_fp32_mg(case):
     op, P = _pair(case, prec=32)
     f = gi.rhs_nodal("noise", op.n_dofs)
@@ -136,7 +149,7 @@ def test_solve_fp32_mg(case):
     b = op.rhs(f)
     uh = host(u)
     assert np.linalg.norm(b - op.A @ uh) <= 1.0001e-10 * np.linalg.norm(b)
-    assert rel(uh, x) <= 1e-8
+    assert close(uh, x, 1e-8)
 
 
 def test_solve_variable_coefficient_q3():
@@ -145,7 +158,7 @@ def test_solve_variable_coefficient_q3():
     x, it, hist, ok = op.solve(f)
     u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
     st, its, h = P.solve(dev(f), u)
-    assert st == 0 and its == it and rel(host(u), x) <= 1e-10
+    assert st == 0 and its == it and close(host(u), x, 1e-10)
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -168,7 +181,7 @@ def test_degenerate_meshes(case, prec):
     if np.linalg.norm(x) == 0.0:
         assert its == 0 and np.abs(uh).max() == 0.0
     else:
-        assert rel(uh, x) <= (1e-10 if prec == 64 else 1e-8)
+        assert close(uh, x, 1e-10 if prec == 64 else 1e-8)
     r = np.zeros(op.n_dofs)
     r[op.free] = np.random.default_rng(3).standard_normal(int(op.free.sum()))
     z = torch.zeros_like(u)
@@ -177,7 +190,7 @@ def test_degenerate_meshes(case, prec):
     if np.linalg.norm(zr) == 0.0:
         assert np.abs(zh).max() == 0.0
     else:
-        assert rel(zh, zr) <= (1e-11 if prec == 64 else 1e-5)
+        assert close(zh, zr, 1e-11 if prec == 64 else 1e-5)
 
 
 def test_zero_rhs_and_default_rhs():
@@ -187,7 +200,7 @@ def test_zero_rhs_and_default_rhs():
     assert st == 0 and its == 0 and np.abs(host(u)).max() == 0.0
     st, its, h = P.solve(None, u)
     x, it, hist, ok = op.solve(np.ones(op.n_dofs))
-    assert its == it and rel(host(u), x) <= 1e-10
+    assert its == it and close(host(u), x, 1e-10)
 
 
 def test_not_converged_and_nan():
@@ -204,3 +217,48 @@ def test_not_converged_and_nan():
     with pytest.raises(gmg.GMGError) as e:
         P.solve(dev(f), u)
     assert e.value.code == -6
+
+
+def _pair_mf(case, prec):
+    """The Sec. 4.3 setting: eps coefficient (1 / 100 across min(x,y,z) = -1/2
+    in 3D), one undamped Jacobi smoothing step."""
+    from paper_1904_03317_amd import gmg
+    rec, k = CASES[case]
+    coeff = "eps" if rec.coarse == "fichera" else "one"
+    op, _ = oracle_problem(rec, k, coeff_kind=coeff, cheb_degree=1, smoother="jacobi", relax=1.0)
+    print(f"[gpu] MF case={case} k={k} prec={prec} N={op.n_dofs}", flush=True)
+    m, P, _ = library_problem(rec, k, coeff_kind=coeff, mg_precision=prec, cheb_degree=1,
+                              smoother=gmg.SMOOTHER_JACOBI, relax=1.0)
+    P.bind()
+    return op, P
+
+
+@pytest.mark.parametrize("case", ["fichera-q2", "lshape-q1", "fichera-q3"])
+def test_mf_jacobi_vcycle_and_solve_fp64(case):
+    op, P = _pair_mf(case, 64)
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal(op.n_dofs)
+    r[~op.free] = 0
+    z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    P.vcycle(dev(r), z)
+    assert close(host(z), op.mg.vcycle(r), 1e-11)
+    f = np.ones(op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    assert st == 0 and ok and its == it
+    assert close(host(u), x, 1e-10)
+
+
+@pytest.mark.parametrize("case", ["fichera-q2", "fichera-q4"])
+def test_mf_jacobi_solve_fp32(case):
+    op, P = _pair_mf(case, 32)
+    f = np.ones(op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(dev(f), u)
+    uh = host(u)
+    assert st == 0 and h[-1] <= 1e-10 and its <= it + 1
+    b = op.rhs(f)
+    assert np.linalg.norm(b - op.A @ uh) <= 1.0001e-10 * np.linalg.norm(b)
+    assert close(uh, x, 1e-8)
