@@ -2,14 +2,17 @@
 
 One step = one full solve (every kernel of the path: load vector, CG with
 one local-smoothing V-cycle per iteration, leaf operator with hanging nodes)
-on the 3D Fichera-corner Q2 workload (4 adaptive cycles of corner + 5%
-seeded random marking, about 2e7 DoFs), inputs resident in HBM.  `value` is
-the FP64-MG solve (FP64 throughout); the FP32-V-cycle solve on the same mesh
-is reported beside it.  Also reported: the roofline of the dominant kernel
-(the finest-level operator application) and the CPU oracle on a bounded
-sample of the same recipe.
+on the 3D Fichera-corner Q2 workload at about 1.5e8 DoFs (6 global
+refinements, then 4 adaptive cycles of corner + 5% seeded random marking;
+nodal right-hand side 1 + N(0, 0.1^2)), inputs resident in HBM.  `value` is
+the solve with the FP32 V-cycle inside FP64 CG; the FP64-throughout solve on
+the same mesh is reported beside it (`fp64_mg`).  Every timed solve must
+reach the tolerance.  Also reported: the roofline of the dominant unit (one
+Chebyshev step on the largest level), the serving stream alone and with a
+large Q3 job inside it, and the CPU oracle on a bounded sample of the same
+recipe.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--g G]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C3-Q2] [--g G]
 """
 import argparse
 import json
@@ -30,16 +33,22 @@ def log(*a):
 
 KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_03317_amd", "csrc",
                              "famkernels.hpp")
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "level_kernels_traffic.json")
+# committed counter summaries per workload (mesh recipe and global refinements)
+TRAFFIC_FILES = {("C2", 5): "level_kernels_traffic.json",
+                 ("C3-Q2", 6): "level_kernels_traffic_fichera_q2_g6.json"}
 
 
-def measured_traffic():
+def measured_traffic(name, g):
     """HBM bytes per launch of the level kernels from the committed counter
-    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy of known
-    size); empty when the kernel source has changed since it was taken."""
+    summary of this workload (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
+    copy of known size); empty when there is none or the kernel source has
+    changed since it was taken."""
     import hashlib
+    fn = TRAFFIC_FILES.get((name, g))
+    if fn is None:
+        return {}
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(os.path.join(ROOT, "profiles", fn)))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return {}
@@ -64,32 +73,57 @@ def roofline(r, traffic):
                       "traffic": traffic.get("apply_bytes_per_launch") if traffic else None}}
 
 
-def cpu_baseline(name="C2", min_seconds=12.0):
-    """The oracle (plain numpy/scipy, FP64, one thread) on the same recipe
-    at a reduced number of global refinements (2 for Q2, 1 for Q3/Q4): DoFs/s
-    of its CG solve, repeated until about min_seconds of solve time."""
+def wopts(w, prec):
+    """library options of a workload at a V-cycle precision"""
+    from paper_1904_03317_amd import gmg
+    return gmg.options(degree=w.degree, mg_precision=prec, cheb_degree=w.cheb_degree,
+                       smoother=gmg.SMOOTHER_JACOBI if w.smoother == "jacobi" else gmg.SMOOTHER_CHEBYSHEV)
+
+
+def _oracle_rate(name, g, min_seconds):
     from threadpoolctl import threadpool_limits
 
     import gmg_inputs as gi
     from oracle import problem
 
-    g_sample = 2 if gi.workload(name).degree == 2 else 1
-    w = gi.workload(name, g=g_sample)
+    w = gi.workload(name, g=g)
     with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
         f = problem.build_forest(w.recipe)
         coeff = gi.coeff_cells(w.coeff, *f.leaves_arrays()) if w.coeff != "one" else None
-        op = problem.setup(f, w.degree, coeff=coeff)
+        op = problem.setup(f, w.degree, coeff=coeff, cheb_degree=w.cheb_degree, smoother=w.smoother)
+        t_setup = time.perf_counter() - t0
         fn = gi.rhs_nodal(w.rhs, op.n_dofs)
         reps, t = 0, 0.0
-        while t < min_seconds or reps < 3:
+        while t < min_seconds or reps < 1:
             t0 = time.perf_counter()
             x, it, hist, ok = op.solve(fn)
             t += time.perf_counter() - t0
             reps += 1
-    return {"value": op.n_dofs * reps / t, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{name} recipe with g={g_sample} global refinements (N={op.n_dofs}, Q{w.degree}): oracle FP64 CG "
-                      f"solve ({it} iterations) repeated {reps} times, {t:.1f} s, set-up excluded, "
-                      f"BLAS limited to 1 thread"}
+    if not ok:
+        raise SystemExit(f"bench.py: the oracle did not converge on {name} g={g}")
+    log(f"cpu baseline: {name} g={g} N={op.n_dofs}: set-up {t_setup:.1f} s, {reps} solves in {t:.1f} s")
+    return dict(N=op.n_dofs, g=g, k=w.degree, its=it, reps=reps, t=t, rate=op.n_dofs * reps / t, setup_s=t_setup)
+
+
+def cpu_baseline(name="C3-Q2", min_seconds=8.0):
+    """The oracle (plain numpy/scipy, FP64, one thread) on the same recipe
+    at reduced numbers of global refinements (2 and 3 for Q2, 1 and 2 for
+    Q3/Q4): DoFs/s of its CG solve, each repeated for about min_seconds;
+    `value` is the larger sample."""
+    import gmg_inputs as gi
+
+    gs = (2, 3) if gi.workload(name).degree == 2 else (1, 2)
+    small = _oracle_rate(name, gs[0], min_seconds)
+    big = _oracle_rate(name, gs[1], min_seconds)
+    return {"value": big["rate"], "unit": "DoFs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{name} recipe (Q{big['k']}) with g={big['g']} global refinements (N={big['N']}): oracle "
+                      f"FP64 CG solve ({big['its']} iterations) repeated {big['reps']} times, {big['t']:.1f} s, "
+                      f"set-up ({big['setup_s']:.0f} s) "
+                      f"excluded, BLAS limited to 1 thread; with g={small['g']} (N={small['N']}): "
+                      f"{small['rate']:.3g} DoFs/s over {small['reps']} solves ({small['t']:.1f} s)",
+            "smaller_sample": {"g": small["g"], "dofs": small["N"], "value": small["rate"],
+                               "cg_iterations": small["its"]}}
 
 
 def build_request_meshes(ids, threads=8):
@@ -198,15 +232,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="C2", choices=["C2", "C3-Q2", "C3-Q4", "C5"],
-                    help="workload (C2: Fichera Q2 ~2e7 DoFs, FP64 throughout; C3: ~1e8 DoFs Q2/Q4 and C5: Q3 "
-                         "checkerboard, both with the FP32 V-cycle as the reported value)")
+    ap.add_argument("--config", default="C3-Q2", choices=["C2", "C3-Q2", "C3-Q4", "C5", "L43"],
+                    help="workload (C3-Q2, the default: Fichera Q2 1.5e8 DoFs; C3-Q4: 1.7e8 DoFs Q4; C5: Q3 "
+                         "checkerboard, 6.8e7 DoFs: the FP32 V-cycle inside FP64 CG is the reported value; "
+                         "C2: Fichera Q2 1.9e7 DoFs, FP64 throughout)")
     ap.add_argument("--g", type=int, default=None, help="global refinements (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
-    ap.add_argument("--serve-big", type=int, default=None, metavar="G",
-                    help="add the C5 job (Q3 checkerboard, G global refinements) as request 128 of the stream")
+    ap.add_argument("--serve-big", type=int, default=5, metavar="G",
+                    help="a second stream with the C5 job (Q3 checkerboard, G global refinements) as request 128 "
+                         "(negative: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU (it has no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -247,12 +283,12 @@ def main():
     del cal_a, cal_b
     results = {}
     t0 = time.perf_counter()
-    base = gmg.Problem(mesh, gmg.options(degree=w.degree, mg_precision=64), coeff=coeff)
+    base = gmg.Problem(mesh, wopts(w, 64), coeff=coeff)
     t_maps = time.perf_counter() - t0
     if trace:
         del os.environ["GMG_TRACE"]
     for prec in ([64] if args.no_fp32 else [64, 32]):
-        P = base.clone(gmg.options(degree=w.degree, mg_precision=prec))
+        P = base.clone(wopts(w, prec))
         t0 = time.perf_counter()
         P.bind("cuda")
         torch.cuda.synchronize()
@@ -262,14 +298,21 @@ def main():
         log(f"FP{prec}-MG: N={N} levels={info.n_levels} maps {t_maps:.1f}s bind {t_bind:.1f}s")
         f = torch.as_tensor(gi.rhs_nodal(w.rhs, N), device="cuda")
         u = torch.zeros(N, dtype=torch.float64, device="cuda")
+        def check(st, its, h, what):
+            if st != 0 or not (h[-1] <= 1e-10):
+                raise SystemExit(f"bench.py: FP{prec}-MG {what} did not reach 1e-10 (status {st}, {its} "
+                                 f"iterations, residual {h[-1]:.3e})")
+
         for i in range(args.warmup):
             st, its, h = P.solve(f, u)
+            check(st, its, h, f"warm-up solve {i}")
             log(f"  warmup {i}: status {st} its {its} res {h[-1]:.2e}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dev_t, vc_t, n_vc = 0.0, 0.0, 0
         for i in range(args.steps):
             st, its, h = P.solve(f, u)
+            check(st, its, h, f"timed solve {i}")
             tm = P.last_timing()
             dev_t += tm[0]
             vc_t += tm[1]
@@ -322,7 +365,9 @@ def main():
     prim = w.mg_precision if w.mg_precision in results else 64
     r = results[prim]
     value = r["N"] / (r["ms"] * 1e-3)
-    desc = {"C2": "Q2", "C3-Q2": "Q2", "C3-Q4": "Q4", "C5": "Q3, checkerboard a in {1, 100}"}[w.name]
+    desc = {"C2": "Q2", "C3-Q2": "Q2", "C3-Q4": "Q4", "C5": "Q3, checkerboard a in {1, 100}",
+            "L43": "Q2, eps = 1 if min(x,y,z) > -1/2 else 100, one undamped Jacobi smoothing step (Sec. 4.3 MF)"
+            }[w.name]
     out = {
         "metric": METRIC,
         "value": value,
@@ -344,7 +389,7 @@ def main():
                    "vcycle_dofs_per_s": r["N"] / (r["vcycle_ms"] * 1e-3),
                    "setup_maps_s": r["maps_s"], "setup_device_s": r["bind_s"]},
     }
-    traffic = measured_traffic() if w.name == "C2" and g_used == 5 else {}
+    traffic = measured_traffic(w.name, g_used)
     out["roofline"] = roofline(r, traffic.get(f"fp{prim}"))
     out["roofline"]["measured_copy_gbs"] = copy_gbs
     other = 32 if prim == 64 else 64
@@ -359,9 +404,15 @@ def main():
                                 "roofline": roofline(o, traffic.get(f"fp{other}"))}
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
-        out["serve"] = serve_leg(args.serve, big_g=args.serve_big)
+        out["serve"] = serve_leg(args.serve)
         log(f"serve: p50 {out['serve']['p50_s'] * 1e3:.1f} ms p99 {out['serve']['p99_s'] * 1e3:.1f} ms "
             f"{out['serve']['throughput_rps']:.1f} req/s")
+        if args.serve_big is not None and args.serve_big >= 0 and args.serve > 128:
+            log(f"serving stream with the C5 job (g={args.serve_big}) as request 128 ...")
+            sb = serve_leg(args.serve, big_g=args.serve_big)
+            out["serve_with_large_job"] = sb
+            log(f"serve + C5: p50 {sb['p50_s'] * 1e3:.1f} ms p99 {sb['p99_s'] * 1e3:.1f} ms; others p50 "
+                f"{sb['large_job']['p50_s_others'] * 1e3:.1f} ms p99 {sb['large_job']['p99_s_others'] * 1e3:.1f} ms")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w.name)
