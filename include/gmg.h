@@ -64,9 +64,9 @@ typedef struct gmg_problem_s* gmg_problem;
 typedef struct gmg_server_s* gmg_server;
 
 /* Solver options.  Defaults from gmg_options_default(): degree 2, FP32
- * V-cycle, Chebyshev degree 4 on [0.08, 1.2] * lambda_max (Sec. 4.1), 10
- * eigenvalue-estimate iterations (Sec. 4.1), rtol 1e-10 on the
- * unpreconditioned residual (Sec. 4.1, 4.3), max_iter 100. */
+ * V-cycle, Chebyshev smoother of degree 4 on [0.08, 1.2] * lambda_max
+ * (Sec. 4.1), 10 eigenvalue-estimate iterations (Sec. 4.1), rtol 1e-10 on
+ * the unpreconditioned residual (Sec. 4.1, 4.3), max_iter 100, relax 1. */
 typedef struct {
   int32_t degree;        /* k = 1..4 */
   int32_t mg_precision;  /* 32: FP32 V-cycle inside FP64 CG; 64: FP64 throughout */
@@ -79,7 +79,12 @@ typedef struct {
   int32_t use_graph;     /* 1: replay the V-cycle as a captured HIP graph */
   int32_t op_variant;    /* level operator form; 0 (the only value): sibling-family patches on
                             levels >= 1 in the entity layout (GMG_ARR_LEVEL_PERM) */
+  int32_t smoother;      /* GMG_SMOOTHER_CHEBYSHEV (Sec. 4.1) or GMG_SMOOTHER_JACOBI: cheb_degree
+                            steps of x += relax D^{-1} (g - A x) (Sec. 4.3 "MF": one step, relax 1) */
+  double relax;          /* Jacobi relaxation factor, 0 < relax <= 2 */
 } gmg_options;
+
+enum { GMG_SMOOTHER_CHEBYSHEV = 0, GMG_SMOOTHER_JACOBI = 1 };
 
 void gmg_options_default(gmg_options* opts);
 const char* gmg_last_error(void);
@@ -124,7 +129,7 @@ typedef struct {
   int64_t n_free;        /* non-Dirichlet leaf DoFs */
   int64_t level_dofs[24];
   int64_t level_cells[24];
-  double lambda_max[24]; /* eigenvalue estimates, valid after gmg_problem_bind */
+  double lambda_max[24]; /* eigenvalue estimates, valid after gmg_problem_bind (Chebyshev smoother) */
   size_t workspace_bytes;
 } gmg_info;
 int gmg_problem_info(gmg_problem p, gmg_info* out);
@@ -246,7 +251,11 @@ typedef struct {
 } gmg_server_stats_t;
 
 enum { GMG_REQ_QUEUED = 0, GMG_REQ_SETUP = 1, GMG_REQ_READY = 2, GMG_REQ_BINDING = 3, GMG_REQ_RUNNING = 4,
-       GMG_REQ_DONE = 5, GMG_REQ_FAILED = 6 };
+       GMG_REQ_DONE = 5, GMG_REQ_FAILED = 6, GMG_REQ_WAIT_RHS = 7 };
+
+/* n_f value of gmg_server_submit: the right-hand side follows later through
+ * gmg_server_set_rhs */
+#define GMG_RHS_LATER ((int64_t)-1)
 
 /* d_arena: device memory owned by the caller (256-byte aligned) that holds
  * the workspaces of resident requests; arena_bytes is the HBM budget.
@@ -254,11 +263,27 @@ enum { GMG_REQ_QUEUED = 0, GMG_REQ_SETUP = 1, GMG_REQ_READY = 2, GMG_REQ_BINDING
  * host set-up and device binding (1..64).  Uses the current device. */
 int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int32_t host_threads,
                       gmg_server* out);
-/* Queue a solve with nodal right-hand side f = f_value.  The server takes
- * the mesh (the handle is invalid afterwards).  cell_coeff: [n_leaves] or
- * NULL (copied).  A request larger than the arena fails with GMG_E_BUDGET. */
+/* Queue a solve (the problem of Sec. 2.1 on the request's own mesh).  The
+ * server takes the mesh (the handle is invalid afterwards).  cell_coeff:
+ * [n_leaves] or NULL for 1 (copied).  Right-hand side, the nodal values f_h
+ * (Sec. 2.1 load vector b = C^T M C f_h, as gmg_solve), one of:
+ *   f_nodal_host = [n_f] values in canonical leaf DoF order (copied); the
+ *     request fails with GMG_E_INVAL when its DoF count differs from n_f;
+ *   f_nodal_host = NULL, n_f = 0: f = 1;
+ *   f_nodal_host = NULL, n_f = GMG_RHS_LATER: the caller supplies it with
+ *     gmg_server_set_rhs once gmg_server_request_dofs reports the DoF count
+ *     (the request waits in state GMG_REQ_WAIT_RHS after its host set-up,
+ *     without holding a slot or arena memory).
+ * A request larger than the arena fails with GMG_E_BUDGET. */
 int gmg_server_submit(gmg_server s, gmg_mesh mesh, const gmg_options* opts, const double* cell_coeff,
-                      double f_value, uint64_t* request_id);
+                      const double* f_nodal_host, int64_t n_f, uint64_t* request_id);
+/* DoF count of a request whose host set-up is done (GMG_E_STATE before). */
+int gmg_server_request_dofs(gmg_server s, uint64_t request_id, int64_t* n_dofs);
+/* Nodal right-hand side of a request submitted with GMG_RHS_LATER: [n_f]
+ * values in canonical leaf DoF order (copied).  GMG_E_STATE if the request
+ * takes none or already has one; GMG_E_INVAL if n_f differs from its DoF
+ * count (when known; otherwise the request fails after its host set-up). */
+int gmg_server_set_rhs(gmg_server s, uint64_t request_id, const double* f_nodal_host, int64_t n_f);
 int gmg_server_poll(gmg_server s, uint64_t request_id, int32_t* state, int32_t* status);
 /* Block until the request is done or failed; GMG_E_STATE on timeout. */
 int gmg_server_wait(gmg_server s, uint64_t request_id, double timeout_s);

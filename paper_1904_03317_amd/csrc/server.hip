@@ -8,7 +8,9 @@
 // device.  Requests leave when their residual reaches the tolerance and
 // their memory and slot go to the next ones (continuous batching at CG
 // iteration granularity).  All kernels are deterministic, so a result does
-// not depend on what else was resident.
+// not depend on what else was resident.  A finished solution is copied back
+// into a pinned host buffer of the request on its slot stream; the scheduler
+// keeps ticking the other requests and completes the copy on a later tick.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +42,8 @@ namespace gmg {
     if (e_ != hipSuccess) gmg::fail(GMG_E_HIP, std::string(#x ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-enum ReqState { kQueued = 0, kSetup = 1, kReady = 2, kBinding = 3, kRunning = 4, kDone = 5, kFailed = 6 };
+enum ReqState { kQueued = 0, kSetup = 1, kReady = 2, kBinding = 3, kRunning = 4, kDone = 5, kFailed = 6,
+                kWaitRhs = 7 };
 
 struct Request {
   uint64_t id = 0;
@@ -50,16 +53,26 @@ struct Request {
   std::unique_ptr<Forest> mesh;
   gmg_options opt{};
   std::vector<double> coeff;
-  double f_value = 1.0;
+  // nodal right-hand side in canonical leaf DoF order; empty means f = 1
+  std::vector<double> f_host;
+  bool rhs_later = false;  // given by gmg_server_set_rhs (rhs_given once it was)
+  bool rhs_given = false;
+  int64_t n_dofs = -1;     // known after host set-up
   std::unique_ptr<Problem> P;
   size_t ws_bytes = 0, arena_off = 0;
   int slot = -1;
   double* d_f = nullptr;   // inside the workspace tail: f (nodal) and u
   double* d_u = nullptr;
   gmg_timing t{};
-  std::vector<double> u_host;
+  double* u_pin = nullptr;        // pinned host copy of the solution
+  hipEvent_t copied = nullptr;    // recorded after the copy-back
+  bool copying = false;
   int iterations = 0;
   std::vector<double> hist;
+  ~Request() {
+    if (u_pin) (void)hipHostFree(u_pin);
+    if (copied) (void)hipEventDestroy(copied);
+  }
 };
 
 // first-fit allocator over the arena (offsets), 256-byte granularity
@@ -119,6 +132,7 @@ struct Server {
   std::deque<Request*> ready_q;    // maps built, waiting for admission
   std::deque<Request*> bind_q;     // admitted, waiting for device set-up
   std::vector<Request*> running;
+  std::vector<Request*> copying;   // solution copy-back in flight
   std::map<uint64_t, std::unique_ptr<Request>> all;
   std::vector<std::thread> workers;
   int host_cpus = 1;               // host threads for map builds, shared by the workers
@@ -146,6 +160,23 @@ void fail_request(Server& S, Request* r, int code, const std::string& msg) {
   r->error = msg;
   r->t.finished = S.now();
   ++S.failed;
+}
+
+// ready requests are admitted in arrival order
+void push_ready(Server& S, Request* r) {
+  r->state = kReady;
+  auto it = S.ready_q.begin();
+  while (it != S.ready_q.end() && (*it)->id < r->id) ++it;
+  S.ready_q.insert(it, r);
+}
+
+// hand the arena range and slot of a request back once nothing of it is in
+// flight on its slot stream (errors of that wait are not the request's any more)
+void release_slot(Server& S, Request* r) {
+  (void)hipStreamSynchronize(S.streams[r->slot]);
+  (void)hipGetLastError();
+  S.arena.release(r->arena_off, r->ws_bytes);
+  S.slot_free.push_back(r->slot);
 }
 
 void worker_loop(Server* S) {
@@ -199,13 +230,19 @@ void worker_loop(Server* S) {
         r->P = std::move(P);
         r->mesh.reset();
         r->ws_bytes = request_bytes(*r->P);
+        r->n_dofs = r->P->maps->n_dofs;
         r->t.setup_done = S->now();
         if (r->ws_bytes > S->arena.size()) {
           fail_request(*S, r, GMG_E_BUDGET, "request needs more device memory than the arena holds");
           S->cv_done.notify_all();
+        } else if (!r->f_host.empty() && (int64_t)r->f_host.size() != r->n_dofs) {
+          fail_request(*S, r, GMG_E_INVAL, "right-hand side length differs from the request's DoF count");
+          S->cv_done.notify_all();
+        } else if (r->rhs_later && !r->rhs_given) {
+          r->state = kWaitRhs;  // gmg_server_set_rhs moves it on
+          S->cv_done.notify_all();
         } else {
-          r->state = kReady;
-          S->ready_q.push_back(r);
+          push_ready(*S, r);
         }
       } else {
         // device set-up on the request's slot stream
@@ -218,7 +255,13 @@ void worker_loop(Server* S) {
         size_t tail = (P.ws_need + 255) & ~size_t(255);
         r->d_f = reinterpret_cast<double*>(base + tail);
         r->d_u = reinterpret_cast<double*>(base + tail + ((size_t(N) * 8 + 255) & ~size_t(255)));
-        set_constant(r->d_f, N, r->f_value, s);
+        if (r->f_host.empty())
+          set_constant(r->d_f, N, 1.0, s);
+        else
+          SRV_HIPCHECK(hipMemcpyAsync(r->d_f, r->f_host.data(), size_t(N) * sizeof(double), hipMemcpyHostToDevice, s));
+        if (!r->u_pin) SRV_HIPCHECK(hipHostMalloc((void**)&r->u_pin, std::max<size_t>(1, size_t(N)) * sizeof(double),
+                                                  hipHostMallocDefault));
+        if (!r->copied) SRV_HIPCHECK(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));
         apply_leaf(P, r->d_f, P.cb, true, s);
         cg_start(P, P.cb, r->d_u, s, false);
         std::lock_guard<std::mutex> lk(S->mu);
@@ -228,18 +271,12 @@ void worker_loop(Server* S) {
       }
     } catch (const Error& e) {
       std::lock_guard<std::mutex> lk(S->mu);
-      if (bind_job) {
-        S->arena.release(r->arena_off, r->ws_bytes);
-        S->slot_free.push_back(r->slot);
-      }
+      if (bind_job) release_slot(*S, r);
       fail_request(*S, r, e.code, e.what());
       S->cv_done.notify_all();
     } catch (const std::exception& e) {
       std::lock_guard<std::mutex> lk(S->mu);
-      if (bind_job) {
-        S->arena.release(r->arena_off, r->ws_bytes);
-        S->slot_free.push_back(r->slot);
-      }
+      if (bind_job) release_slot(*S, r);
       fail_request(*S, r, GMG_E_INVAL, e.what());
       S->cv_done.notify_all();
     }
@@ -271,10 +308,34 @@ void scheduler_loop(Server* S) {
         }
       }
     }
-    std::vector<Request*> run;
+    std::vector<Request*> run, cop;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       run = S->running;
+      cop = S->copying;
+    }
+    // copy-backs that have completed: the request is done, its memory and
+    // slot go to the next ones
+    for (Request* r : cop) {
+      hipError_t e = hipEventQuery(r->copied);
+      if (e == hipErrorNotReady) continue;
+      idle = false;
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->copying.erase(std::find(S->copying.begin(), S->copying.end(), r));
+      release_slot(*S, r);
+      r->t.finished = S->now();
+      if (e != hipSuccess) {
+        r->status = GMG_E_HIP;
+        r->error = std::string("copying the solution back failed: ") + hipGetErrorString(e);
+        r->state = kFailed;
+        ++S->failed;
+      } else {
+        r->state = kDone;
+        ++S->completed;
+        S->dofs_done += (double)r->n_dofs;
+      }
+      r->P.reset();   // drop host maps and device views; the arena range is free
+      S->cv_done.notify_all();
     }
     for (Request* r : run) {
       bool done = false;
@@ -294,31 +355,30 @@ void scheduler_loop(Server* S) {
       hipStream_t s = S->streams[r->slot];
       r->iterations = P.cg.it;
       r->hist.assign(P.cg.hist.begin(), P.cg.hist.begin() + P.cg.it + 1);
-      r->u_host.resize(P.maps->n_dofs);
       if (status >= 0) {
-        hipError_t e1 = hipMemcpyAsync(r->u_host.data(), r->d_u, P.maps->n_dofs * sizeof(double),
-                                       hipMemcpyDeviceToHost, s);
-        hipError_t e2 = hipStreamSynchronize(s);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-          status = GMG_E_HIP;
-          err = "copying the solution back failed";
+        // enqueue the copy-back and finish the request on a later tick
+        hipError_t e1 = hipMemcpyAsync(r->u_pin, r->d_u, P.maps->n_dofs * sizeof(double), hipMemcpyDeviceToHost, s);
+        hipError_t e2 = e1 == hipSuccess ? hipEventRecord(r->copied, s) : e1;
+        if (e2 == hipSuccess) {
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->running.erase(std::find(S->running.begin(), S->running.end(), r));
+          r->status = status;
+          r->copying = true;
+          S->copying.push_back(r);
+          continue;
         }
+        status = GMG_E_HIP;
+        err = std::string("copying the solution back failed: ") + hipGetErrorString(e2);
       }
       std::lock_guard<std::mutex> lk(S->mu);
       S->running.erase(std::find(S->running.begin(), S->running.end(), r));
-      S->arena.release(r->arena_off, r->ws_bytes);
-      S->slot_free.push_back(r->slot);
+      release_slot(*S, r);
       r->t.finished = S->now();
       r->status = status;
       r->error = err;
-      r->state = status >= 0 ? kDone : kFailed;
-      if (status >= 0) {
-        ++S->completed;
-        S->dofs_done += (double)P.maps->n_dofs;
-      } else {
-        ++S->failed;
-      }
-      r->P.reset();   // drop host maps and device views; the arena range is free
+      r->state = kFailed;
+      ++S->failed;
+      r->P.reset();
       S->cv_done.notify_all();
     }
     if (idle) std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -375,17 +435,22 @@ int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int3
 }
 
 int gmg_server_submit(gmg_server h, gmg_mesh mesh, const gmg_options* opts, const double* cell_coeff,
-                      double f_value, uint64_t* request_id) {
+                      const double* f_nodal_host, int64_t n_f, uint64_t* request_id) {
   return sguard([&] {
     if (!h || !mesh || !opts || !request_id) gmg::fail(GMG_E_INVAL, "null argument");
     if (opts->degree < 1 || opts->degree > 4 || (opts->mg_precision != 32 && opts->mg_precision != 64) ||
         opts->cheb_degree < 1 || opts->max_iter < 1 || !(opts->rtol > 0) || opts->eig_iters < 1 ||
-        !(opts->cheb_lo > 0) || !(opts->cheb_hi > opts->cheb_lo))
+        !(opts->cheb_lo > 0) || !(opts->cheb_hi > opts->cheb_lo) ||
+        (opts->smoother != GMG_SMOOTHER_CHEBYSHEV && opts->smoother != GMG_SMOOTHER_JACOBI) ||
+        !(opts->relax > 0 && opts->relax <= 2))
       gmg::fail(GMG_E_INVAL, "invalid options");
+    if (f_nodal_host ? n_f < 1 : (n_f != 0 && n_f != GMG_RHS_LATER))
+      gmg::fail(GMG_E_INVAL, "right-hand side: an array with its length, or NULL with 0 or GMG_RHS_LATER");
     Server& S = *h->S;
     auto r = std::make_unique<gmg::Request>();
     r->opt = *opts;
-    r->f_value = f_value;
+    if (f_nodal_host) r->f_host.assign(f_nodal_host, f_nodal_host + n_f);
+    r->rhs_later = !f_nodal_host && n_f == GMG_RHS_LATER;
     const int64_t nl = (int64_t)mesh->f->leaves().size();
     if (cell_coeff) r->coeff.assign(cell_coeff, cell_coeff + nl);
     r->mesh = std::move(mesh->f);
@@ -397,6 +462,37 @@ int gmg_server_submit(gmg_server h, gmg_mesh mesh, const gmg_options* opts, cons
     S.setup_q.push_back(r.get());
     S.all[r->id] = std::move(r);
     S.cv_work.notify_all();
+    return 0;
+  });
+}
+
+int gmg_server_request_dofs(gmg_server h, uint64_t id, int64_t* n_dofs) {
+  return sguard([&] {
+    if (!h || !n_dofs) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    if (it->second->n_dofs < 0) gmg::fail(GMG_E_STATE, "host set-up of the request not finished");
+    *n_dofs = it->second->n_dofs;
+    return 0;
+  });
+}
+
+int gmg_server_set_rhs(gmg_server h, uint64_t id, const double* f_nodal_host, int64_t n_f) {
+  return sguard([&] {
+    if (!h || !f_nodal_host || n_f < 1) gmg::fail(GMG_E_INVAL, "invalid right-hand side");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(id);
+    if (it == S.all.end()) gmg::fail(GMG_E_INVAL, "unknown request id");
+    gmg::Request* r = it->second.get();
+    if (!r->rhs_later || r->rhs_given) gmg::fail(GMG_E_STATE, "the request takes no (further) right-hand side");
+    if (r->n_dofs >= 0 && n_f != r->n_dofs)
+      gmg::fail(GMG_E_INVAL, "right-hand side length differs from the request's DoF count");
+    r->f_host.assign(f_nodal_host, f_nodal_host + n_f);
+    r->rhs_given = true;
+    if (r->state == gmg::kWaitRhs) gmg::push_ready(S, r);
     return 0;
   });
 }
@@ -444,8 +540,8 @@ int gmg_server_result(gmg_server h, uint64_t id, double* u_host, int64_t* n_dofs
       return r->status;
     }
     if (r->state != gmg::kDone) gmg::fail(GMG_E_STATE, "request not finished");
-    if (n_dofs) *n_dofs = (int64_t)r->u_host.size();
-    if (u_host) std::memcpy(u_host, r->u_host.data(), r->u_host.size() * sizeof(double));
+    if (n_dofs) *n_dofs = r->n_dofs;
+    if (u_host && r->n_dofs > 0) std::memcpy(u_host, r->u_pin, size_t(r->n_dofs) * sizeof(double));
     if (iterations) *iterations = r->iterations;
     if (history) std::memcpy(history, r->hist.data(), r->hist.size() * sizeof(double));
     if (t) *t = r->t;
@@ -473,7 +569,7 @@ int gmg_server_stats(gmg_server h, gmg_server_stats_t* o) {
     Server& S = *h->S;
     std::lock_guard<std::mutex> lk(S.mu);
     o->queued = (int64_t)(S.setup_q.size() + S.ready_q.size());
-    o->running = (int64_t)(S.running.size() + S.bind_q.size());
+    o->running = (int64_t)(S.running.size() + S.bind_q.size() + S.copying.size());
     o->completed = S.completed;
     o->failed = S.failed;
     o->arena_used = S.arena.used();
@@ -499,7 +595,7 @@ int gmg_server_destroy(gmg_server h) {
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   }
-  delete h;
+  delete h;  // requests free their pinned buffers and events
   return 0;
 }
 

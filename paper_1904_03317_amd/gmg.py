@@ -26,7 +26,10 @@ class gmg_options(C.Structure):
     _fields_ = [("degree", C.c_int32), ("mg_precision", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double), ("eig_iters", C.c_int32),
                 ("rtol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32),
-                ("op_variant", C.c_int32)]
+                ("op_variant", C.c_int32), ("smoother", C.c_int32), ("relax", C.c_double)]
+
+
+SMOOTHER_CHEBYSHEV, SMOOTHER_JACOBI = 0, 1
 
 
 class gmg_info(C.Structure):
@@ -48,7 +51,8 @@ class gmg_server_stats(C.Structure):
                 ("arena_bytes", C.c_size_t), ("dofs_done", C.c_double), ("clock", C.c_double)]
 
 
-REQ_STATES = ["QUEUED", "SETUP", "READY", "BINDING", "RUNNING", "DONE", "FAILED"]
+REQ_STATES = ["QUEUED", "SETUP", "READY", "BINDING", "RUNNING", "DONE", "FAILED", "WAIT_RHS"]
+RHS_LATER = -1
 
 
 class GMGError(RuntimeError):
@@ -87,7 +91,9 @@ def configure(L):
         "gmg_vcycle": (C.c_int, [vp, vp, vp, vp]),
         "gmg_problem_last_timing": (C.c_int, [vp, C.POINTER(dbl)]),
         "gmg_server_create": (C.c_int, [vp, C.c_size_t, i32, i32, C.POINTER(vp)]),
-        "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, dbl, C.POINTER(C.c_uint64)]),
+        "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, vp, i64, C.POINTER(C.c_uint64)]),
+        "gmg_server_request_dofs": (C.c_int, [vp, C.c_uint64, C.POINTER(i64)]),
+        "gmg_server_set_rhs": (C.c_int, [vp, C.c_uint64, vp, i64]),
         "gmg_server_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(i32), C.POINTER(i32)]),
         "gmg_server_wait": (C.c_int, [vp, C.c_uint64, dbl]),
         "gmg_server_result": (C.c_int, [vp, C.c_uint64, vp, C.POINTER(i64), C.POINTER(i32), vp,
@@ -126,7 +132,8 @@ def exported_symbols():
             "gmg_problem_create", "gmg_problem_clone", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
             "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle",
-            "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_poll",
+            "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_request_dofs",
+            "gmg_server_set_rhs", "gmg_server_poll",
             "gmg_server_wait", "gmg_server_result", "gmg_server_release", "gmg_server_stats",
             "gmg_server_destroy"]
 
@@ -310,14 +317,39 @@ class Server:
                                        C.byref(h)))
         self.h = h
 
-    def submit(self, mesh: Mesh, opts=None, coeff=None, f_value=1.0):
-        """Queue a solve; the server takes the mesh."""
+    def submit(self, mesh: Mesh, opts=None, coeff=None, f=None, rhs_later=False):
+        """Queue a solve; the server takes the mesh.  f: nodal right-hand side
+        in canonical leaf DoF order, or None for f = 1; rhs_later: supply it
+        with set_rhs once request_dofs reports the DoF count."""
         opts = opts if opts is not None else options()
         c = None if coeff is None else np.ascontiguousarray(np.asarray(coeff, np.float64))
+        fa = None if f is None else np.ascontiguousarray(np.asarray(f, np.float64))
+        n_f = len(fa) if fa is not None else (RHS_LATER if rhs_later else 0)
         rid = C.c_uint64()
-        _check(lib().gmg_server_submit(self.h, mesh.h, C.byref(opts), _ptr(c), float(f_value), C.byref(rid)))
+        _check(lib().gmg_server_submit(self.h, mesh.h, C.byref(opts), _ptr(c), _ptr(fa), n_f, C.byref(rid)))
         mesh.h = None
         return rid.value
+
+    def request_dofs(self, rid, timeout=600.0):
+        """DoF count of a request, waiting for its host set-up."""
+        import time
+        n = C.c_int64()
+        t0 = time.perf_counter()
+        while True:
+            code = lib().gmg_server_request_dofs(self.h, rid, C.byref(n))
+            if code == 0:
+                return n.value
+            if code != -8 or time.perf_counter() - t0 > timeout:
+                _check(code)
+                raise GMGError(-8, "timeout waiting for the host set-up of the request")
+            state, status = self.poll(rid)
+            if state == "FAILED":
+                raise GMGError(status, "request failed")
+            time.sleep(0.001)
+
+    def set_rhs(self, rid, f):
+        fa = np.ascontiguousarray(np.asarray(f, np.float64))
+        _check(lib().gmg_server_set_rhs(self.h, rid, _ptr(fa), len(fa)))
 
     def poll(self, rid):
         st, status = C.c_int32(), C.c_int32()

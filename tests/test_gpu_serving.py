@@ -90,3 +90,88 @@ def test_not_converged_reported_per_request():
     assert ra["status"] == gmg.GMG_NOT_CONVERGED and ra["iterations"] == 2
     assert rb["status"] == 0 and rb["history"][-1] <= 1e-10
     S.close()
+
+
+def _oracle_of(r, scale):
+    """The oracle's problem on the same request mesh (same recipe, same seed)."""
+    from oracle import problem
+    from oracle.forest import Forest
+    spec = gi.request_spec(r)
+    spec.target_dofs = min(spec.target_dofs, 6e4) * scale
+    f = gi.build_request_mesh(spec, lambda d, o: Forest(d, o), lambda fo, fl: fo.refine(fl),
+                              lambda fo: fo.leaves_arrays())
+    return problem.setup(f, 2)
+
+
+def _solo(r, opts, f, scale):
+    from paper_1904_03317_amd import gmg
+    P = gmg.Problem(_mesh(r, scale), opts).bind()
+    u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(torch.as_tensor(f, device="cuda"), u)
+    torch.cuda.synchronize()
+    P.close()
+    return st, its, u.cpu().numpy()
+
+
+def test_nodal_rhs_served_equals_solo_and_oracle():
+    """Served requests with their own nodal right-hand side (the seeded noisy
+    f = 1 + N(0, 0.1^2) per leaf DoF), given at submission or after the host
+    set-up reported the DoF count: each equals its solo solve bitwise and the
+    oracle's CG iterate (FP64 V-cycle: equal iteration counts and 1e-10; FP32
+    V-cycle: at most one more iteration, true residual 1e-10, 1e-8)."""
+    from paper_1904_03317_amd import gmg
+    scale = 1.0 / 3.0
+    S = gmg.Server(arena_bytes=1 << 30, max_slots=3, host_threads=2)
+    cases = []
+    for r, prec, later in [(5, 64, True), (6, 32, True), (7, 64, False), (8, 32, False)]:
+        opts = gmg.options(degree=2, mg_precision=prec)
+        op = _oracle_of(r, scale)
+        fn = gi.rhs_nodal("noise", op.n_dofs, seed=9000 + r)
+        if later:
+            rid = S.submit(_mesh(r, scale), opts, rhs_later=True)
+            assert S.request_dofs(rid) == op.n_dofs
+            assert S.poll(rid)[0] in ("WAIT_RHS", "SETUP", "QUEUED")
+            S.set_rhs(rid, fn)
+        else:
+            rid = S.submit(_mesh(r, scale), opts, f=fn)
+        cases.append((rid, r, prec, opts, op, fn))
+    for rid, r, prec, opts, op, fn in cases:
+        S.wait(rid, 300)
+        res = S.result(rid)
+        s0, its0, u0 = _solo(r, opts, fn, scale)
+        x, it, hist, ok = op.solve(fn)
+        print(f"[gpu] request {r} FP{prec}-MG: N={op.n_dofs} served its {res['iterations']} solo {its0} "
+              f"oracle {it}", flush=True)
+        assert res["status"] == 0 and s0 == 0 and ok
+        assert res["iterations"] == its0 and np.array_equal(res["u"], u0)
+        u = res["u"]
+        d = np.abs(u - x).max() / np.abs(x).max()
+        if prec == 64:
+            assert res["iterations"] == it
+            assert np.linalg.norm(u - x) <= 1e-10 * np.linalg.norm(x) and d <= 1e-10
+        else:
+            assert res["iterations"] <= it + 1
+            b = op.rhs(fn)
+            assert np.linalg.norm(b - op.A @ u) <= 1.0001e-10 * np.linalg.norm(b)
+            assert np.linalg.norm(u - x) <= 1e-8 * np.linalg.norm(x) and d <= 1e-8
+        S.release(rid)
+    S.close()
+
+
+def test_rhs_length_mismatch_fails_the_request():
+    from paper_1904_03317_amd import gmg
+    S = gmg.Server(arena_bytes=1 << 30, max_slots=2, host_threads=1)
+    rid = S.submit(_mesh(4, 0.2), gmg.options(degree=2), f=np.ones(7))
+    S.wait(rid, 120)
+    state, status = S.poll(rid)
+    assert state == "FAILED" and status == -1
+    rid = S.submit(_mesh(4, 0.2), gmg.options(degree=2), rhs_later=True)
+    n = S.request_dofs(rid)
+    with pytest.raises(gmg.GMGError):
+        S.set_rhs(rid, np.ones(n + 1))
+    S.set_rhs(rid, np.ones(n))
+    with pytest.raises(gmg.GMGError):
+        S.set_rhs(rid, np.ones(n))
+    S.wait(rid, 120)
+    assert S.result(rid)["status"] == 0
+    S.close()
