@@ -131,6 +131,7 @@ class Workload:
     coeff: str = "one"        # "one" | "checker"
     mg_precision: int = 64
     cheb_degree: int = 4
+    smoother: str = "chebyshev"   # "chebyshev" | "jacobi" (undamped, Sec. 4.3)
     notes: str = ""
 
 
@@ -152,6 +153,12 @@ def workload(name, g=None):
     if name == "C5":
         return Workload("C5", MeshRecipe("fichera", 5 if g is None else g, 4, "corner+random"), 3,
                         coeff="checker", mg_precision=32)
+    if name == "L43":
+        # the paper's Laplace comparison (Sec. 4.3): Fichera corner, eps in
+        # {1, 100}, f = 1, Q2, "MF" preconditioner (one undamped FP32 Jacobi
+        # step per level); mesh from the C2 recipe unless refined adaptively
+        return Workload("L43", MeshRecipe("fichera", 4 if g is None else g, 4, "corner+random"), 2,
+                        coeff="eps", mg_precision=32, cheb_degree=1, smoother="jacobi")
     raise KeyError(name)
 
 
@@ -167,11 +174,16 @@ def rhs_nodal(kind, n_dofs, seed=SEED_NOISE):
 def coeff_cells(kind, levels, anchors):
     """Cell-constant coefficient a_K per leaf.  'checker': blocks of side 1/4
     tiling [-1,1]^d; a = 100 where the sum of block indices of the cell centre
-    is odd, else 1 (exact integer evaluation)."""
+    is odd, else 1 (exact integer evaluation).  'eps': the Fichera-corner
+    coefficient of the paper's Laplace comparison (Sec. 4.3), 1 where
+    min(x, y, z) > -1/2 and 100 elsewhere, at the cell centre (exact: the
+    plane x = -1/2 is a cell face on every level >= 1)."""
     n = len(levels)
     if kind == "one":
         return np.ones(n)
     c2 = _centres_x2(levels, anchors)               # units of 2^-21
+    if kind == "eps":
+        return np.where((c2 > -(1 << 20)).all(axis=1), 1.0, 100.0)
     blk = (c2 + (1 << 21)) >> 19                   # floor(4 * (x + 1))
     odd = (blk.sum(axis=1) & 1).astype(bool)
     return np.where(odd, 100.0, 1.0)

@@ -9,6 +9,9 @@ Readings of the paper used here:
 * lambda_max: 10 Jacobi-preconditioned CG steps on A^S from the start vector
   (i mod 12) - 5.5 on the S rows (i = level DoF index), largest eigenvalue of
   the Lanczos tridiagonal matrix built from the CG coefficients.
+* The "MF" smoother of Sec. 4.3 (one Jacobi step without damping): m steps
+  of x += omega D^{-1} (g - A x) on V^S, omega = 1; from a zero start the
+  first step needs no product.
 * Coarse solve: exact, by a dense Cholesky factorisation of A_0^S.
 * CG: x0 = 0, stop when ||r_k||_2 <= rtol ||b||_2 (unpreconditioned,
   recursively updated residual).
@@ -92,6 +95,20 @@ def chebyshev(A, dinv, g, lam, m, x0=None, lo=0.08, hi=1.2):
     return x
 
 
+def jacobi(A, dinv, g, omega, m, x0=None):
+    """m steps of point Jacobi with relaxation omega for A x = g (Sec. 4.3
+    smoother: omega = 1, one step).  With x0=None the start is zero."""
+    if x0 is None:
+        x = omega * (dinv * g)
+        first = 2
+    else:
+        x = x0.copy()
+        first = 1
+    for _ in range(first, m + 1):
+        x = x + omega * (dinv * (g - A @ x))
+    return x
+
+
 class LevelOps:
     def __init__(self, lev, Ahat, dtype):
         S = np.nonzero(lev.flags == FLAG_S)[0]
@@ -114,8 +131,10 @@ class LocalSmoothingMG:
     hierarchy on the coarsest level that holds them as S nodes."""
 
     def __init__(self, disc, coeff, cheb_degree=4, lo=0.08, hi=1.2, eig_iters=10,
-                 dtype=np.float64):
+                 dtype=np.float64, smoother="chebyshev", relax=1.0):
         self.disc, self.m, self.lo, self.hi, self.dtype = disc, cheb_degree, lo, hi, dtype
+        assert smoother in ("chebyshev", "jacobi")
+        self.smoother, self.relax = smoother, relax
         lcoeff = level_coefficients(disc, coeff)
         self.ops, self.lam, self.P = [], [], [None]
         for l, lev in enumerate(disc.levels):
@@ -137,6 +156,12 @@ class LocalSmoothingMG:
         self.copy_level, self.copy_index = disc.copy_level, disc.copy_index
         self.leaf_free = disc.leaf.dirichlet == 0
 
+    def smooth(self, l, A, dinv, g, x0=None):
+        """m smoothing steps on level l (V^S rows), from zero or from x0."""
+        if self.smoother == "jacobi":
+            return jacobi(A, dinv, g, self.dtype(self.relax), self.m, x0=x0)
+        return chebyshev(A, dinv, g, self.lam[l], self.m, x0=x0, lo=self.lo, hi=self.hi)
+
     def vcycle(self, r):
         dt = self.dtype
         L = len(self.ops) - 1
@@ -149,8 +174,7 @@ class LocalSmoothingMG:
             o = self.ops[l]
             xl = np.zeros(o.n, dtype=dt)
             if len(o.S):
-                xl[o.S] = chebyshev(o.A_S, o.dinv, d[l][o.S], self.lam[l], self.m,
-                                    lo=self.lo, hi=self.hi)
+                xl[o.S] = self.smooth(l, o.A_S, o.dinv, d[l][o.S])
             t = np.zeros(o.n, dtype=dt)
             t[o.S] = d[l][o.S] - o.A_S @ xl[o.S]
             t[o.I] = d[l][o.I] - o.A_IS @ xl[o.S]
@@ -168,8 +192,7 @@ class LocalSmoothingMG:
             x[l][~o.free] = 0
             if len(o.S):
                 g = d[l][o.S] - o.A_SI @ x[l][o.I]
-                x[l][o.S] = chebyshev(o.A_S, o.dinv, g, self.lam[l], self.m, x0=x[l][o.S],
-                                      lo=self.lo, hi=self.hi)
+                x[l][o.S] = self.smooth(l, o.A_S, o.dinv, g, x0=x[l][o.S])
         z = np.zeros(len(r))
         for i in fr:
             z[i] = float(x[self.copy_level[i]][self.copy_index[i]])
@@ -321,8 +344,7 @@ class FullSpaceMG:
         ASS = A[S][:, S]
         rhs = g[S] - A[S][:, notS] @ x[notS]
         x = x.copy()
-        x[S] = chebyshev(ASS, dinv, rhs, self.ref.lam[l], self.ref.m,
-                         x0=None if zero_start else x[S], lo=self.ref.lo, hi=self.ref.hi)
+        x[S] = self.ref.smooth(l, ASS, dinv, rhs, x0=None if zero_start else x[S])
         return x
 
     def _vc(self, l, g):

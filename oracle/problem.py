@@ -57,7 +57,7 @@ def mask_dirichlet(A, free):
 
 
 def setup(forest: Forest, k: int, coeff=None, cheb_degree=4, mg_dtype=np.float64,
-          eig_iters=10, lo=0.08, hi=1.2) -> OracleProblem:
+          eig_iters=10, lo=0.08, hi=1.2, smoother="chebyshev", relax=1.0) -> OracleProblem:
     disc = discretize(forest, k)
     n_leaves = len(disc.leaf.cells)
     coeff = np.ones(n_leaves) if coeff is None else np.asarray(coeff, dtype=np.float64)
@@ -65,7 +65,7 @@ def setup(forest: Forest, k: int, coeff=None, cheb_degree=4, mg_dtype=np.float64
     free = disc.leaf.dirichlet == 0
     A = mask_dirichlet(A, free)
     mg = LocalSmoothingMG(disc, coeff, cheb_degree=cheb_degree, lo=lo, hi=hi,
-                          eig_iters=eig_iters, dtype=mg_dtype)
+                          eig_iters=eig_iters, dtype=mg_dtype, smoother=smoother, relax=relax)
     return OracleProblem(disc, A, M.tocsr(), free, mg, coeff)
 
 
