@@ -15,9 +15,6 @@
 struct gmg_mesh_s {
   std::unique_ptr<gmg::Forest> f;
 };
-struct gmg_problem_s {
-  gmg::Problem P;
-};
 
 namespace gmg {
 namespace {
@@ -66,6 +63,8 @@ void gmg_options_default(gmg_options* o) {
   o->max_iter = 100;
   o->use_graph = 1;
   o->op_variant = 0;
+  o->smoother = GMG_SMOOTHER_CHEBYSHEV;
+  o->relax = 1.0;
 }
 
 const char* gmg_last_error(void) { return gmg::g_last_error.c_str(); }
@@ -135,6 +134,8 @@ int gmg_problem_create(gmg_mesh m, const gmg_options* opts, const double* coeff,
     REQUIRE(opts->rtol > 0 && opts->max_iter >= 1, "rtol > 0 and max_iter >= 1 required");
     REQUIRE(m->f->max_level() < 24, "too many levels");
     REQUIRE(opts->op_variant == 0, "op_variant must be 0");
+    REQUIRE(opts->smoother == GMG_SMOOTHER_CHEBYSHEV || opts->smoother == GMG_SMOOTHER_JACOBI, "unknown smoother");
+    REQUIRE(opts->relax > 0 && opts->relax <= 2, "0 < relax <= 2 required");
     auto p = std::make_unique<gmg_problem_s>();
     gmg::Problem& P = p->P;
     P.opt = *opts;
@@ -167,6 +168,8 @@ int gmg_problem_clone(gmg_problem src, const gmg_options* opts, gmg_problem* out
     REQUIRE(opts->cheb_lo > 0 && opts->cheb_hi > opts->cheb_lo, "0 < cheb_lo < cheb_hi required");
     REQUIRE(opts->eig_iters >= 1 && opts->eig_iters <= 100, "eig_iters must be 1..100");
     REQUIRE(opts->rtol > 0 && opts->max_iter >= 1, "rtol > 0 and max_iter >= 1 required");
+    REQUIRE(opts->smoother == GMG_SMOOTHER_CHEBYSHEV || opts->smoother == GMG_SMOOTHER_JACOBI, "unknown smoother");
+    REQUIRE(opts->relax > 0 && opts->relax <= 2, "0 < relax <= 2 required");
     auto p = std::make_unique<gmg_problem_s>();
     gmg::Problem& P = p->P;
     P.opt = *opts;

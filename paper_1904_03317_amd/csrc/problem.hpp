@@ -71,7 +71,10 @@ struct Problem {
 
 size_t plan_workspace(Problem& P, char* base);
 void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s);
-void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s);
+// E: the operator slots to use (null: the problem's own, in its workspace)
+void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s, double* E = nullptr);
+// doubles of operator slots the leaf operator needs
+int64_t leaf_slots(const Problem& P);
 void vcycle(Problem& P, const double* r, double* z, hipStream_t s);
 int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s);
 void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed);
@@ -80,3 +83,7 @@ void set_constant(double* p, int64_t n, double v, hipStream_t s);
 void apply_level_hook(Problem& P, int level, int variant, const void* x, void* y, hipStream_t s);
 
 }  // namespace gmg
+
+struct gmg_problem_s {
+  gmg::Problem P;
+};

@@ -551,7 +551,7 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     else
       hipLaunchKernelGGL(dev::make_dinv<double>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n, diag, V.v.flags,
                          (double*)P.ldinv + V.off);
-    V.lam = l >= 1 ? estimate_lambda(P, l, s) : 1.0;
+    V.lam = l >= 1 && P.opt.smoother == GMG_SMOOTHER_CHEBYSHEV ? estimate_lambda(P, l, s) : 1.0;
   }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
@@ -566,11 +566,15 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
 // leaf operator q = C^T A C p with Dirichlet rows zero (or the mass matrix):
 // hanging-node constraints applied inside the cells (pass 1), per-DoF sums
 // (pass 2)
-void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s) {
+void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s, double* E) {
   const int64_t N = P.maps->n_dofs;
-  P.kt->leaf_e(P.leaf, x, P.E, mass, P.m64, s);
-  hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, P.E, P.leaf.dir, y);
+  if (!E) E = P.E;
+  P.kt->leaf_e(P.leaf, x, E, mass, P.m64, s);
+  hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, (const double*)E,
+                     P.leaf.dir, y);
 }
+
+int64_t leaf_slots(const Problem& P) { return P.maps->n_leaves * P.maps->npc; }
 
 
 struct Cheb {
@@ -585,13 +589,32 @@ static Cheb cheb_of(const Problem& P, int l) {
   return c;
 }
 
-// Chebyshev smoothing steps on level l >= 1 (Sec. 4.1 smoother): steps
-// first..m of the semi-iteration on D^{-1} A^S, each an operator application
-// whose two passes perform the vector update as their epilogue.
-// Pre-smoothing enters with step 1 already done (from x = 0, no operator
-// needed); post-smoothing starts at step 1 from the prolongated x, whose
-// interface values stay fixed (D^{-1} = 0 there) so that every residual
-// includes A^{SI} x^I.
+// Coefficients of smoothing step j (1-based) on level l, a step being
+// d = c1 d + c2 D^{-1} (g - A x), x += d.  Chebyshev (Sec. 4.1): the
+// three-term semi-iteration on D^{-1} A^S over [lo, hi] lambda_max; Jacobi
+// (Sec. 4.3): c1 = 0, c2 = relax.
+struct StepCoef {
+  double c1, c2;
+};
+static StepCoef step_coef(const Problem& P, int l, int j) {
+  if (P.opt.smoother == GMG_SMOOTHER_JACOBI) return {0.0, P.opt.relax};
+  const Cheb c = cheb_of(P, l);
+  double rho_old = 1.0 / c.sigma, c1 = 0.0, c2 = 1.0 / c.theta;
+  for (int i = 2; i <= j; ++i) {
+    const double rho = 1.0 / (2.0 * c.sigma - rho_old);
+    c1 = rho * rho_old;
+    c2 = 2.0 * rho / c.delta;
+    rho_old = rho;
+  }
+  return {c1, c2};
+}
+
+// Smoothing steps first..m on level l >= 1 (Sec. 4.1 / 4.3 smoother on
+// D^{-1} A^S), each an operator application whose two passes perform the
+// vector update as their epilogue.  Pre-smoothing enters with step 1
+// already done (from x = 0, no operator needed); post-smoothing starts at
+// step 1 from the prolongated x, whose interface values stay fixed
+// (D^{-1} = 0 there) so that every residual includes A^{SI} x^I.
 template <typename T>
 static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
   DevLevel& V = P.lv[l];
@@ -603,20 +626,11 @@ static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
   ep.g = (T*)P.lg + o;
   ep.dinv = (const T*)P.ldinv + o;
   ep.flags = V.v.flags;
-  const Cheb c = cheb_of(P, l);
-  double rho_old = 1.0 / c.sigma;
   const LevelOps<T>& op = ops<T>(P);
-  for (int j = 1; j <= P.opt.cheb_degree; ++j) {
-    double c1 = 0.0, c2 = 1.0 / c.theta;
-    if (j >= 2) {
-      const double rho = 1.0 / (2.0 * c.sigma - rho_old);
-      c1 = rho * rho_old;
-      c2 = 2.0 * rho / c.delta;
-      rho_old = rho;
-    }
-    if (j < first) continue;
-    ep.c1 = T(c1);
-    ep.c2 = T(c2);
+  for (int j = first; j <= P.opt.cheb_degree; ++j) {
+    const StepCoef c = step_coef(P, l, j);
+    ep.c1 = T(c.c1);
+    ep.c2 = T(c.c2);
     op.op(V.v, dev::kEpiCheb, ep.x, ep, E, mats<T>(P), s);
     op.sum(V.v, dev::kEpiCheb, E, ep, s);
   }
@@ -641,7 +655,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
     // first pre-smoothing step on the finest level: x = D^{-1} g / theta
     DevLevel& V = P.lv[L];
     hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(V.v.n_dofs)), dim3(dev::kBlock), 0, s, V.v.n_dofs, X + V.off,
-                       Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0), T(1.0 / cheb_of(P, L).theta), 1);
+                       Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0), T(step_coef(P, L, 1).c2), 1);
   }
   for (int l = L; l >= 1; --l) {
     DevLevel& V = P.lv[l];
@@ -668,7 +682,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
       ep.g = G + W.off;
       ep.dinv = Di + W.off;
       ep.flags = W.v.flags;
-      ep.c2 = T(1.0 / cheb_of(P, l - 1).theta);
+      ep.c2 = T(step_coef(P, l - 1, 1).c2);
       ep.smooth = 1;
       op.restrict_fc(V.v, W.v, R + V.off, ep, (T*)P.rbuf, E, mats<T>(P), s);
       op.sum(W.v, dev::kEpiRStart, E, ep, s);

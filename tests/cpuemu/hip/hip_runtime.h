@@ -23,6 +23,8 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 #define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(emu::dyn_shared());
 
 struct dim3 {
@@ -34,7 +36,7 @@ typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorNotReady = 600, hipErrorInvalidValue = 1 };
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice,
                      hipMemcpyDefault };
-enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0 };
+enum { hipStreamNonBlocking = 1, hipHostMallocDefault = 0, hipEventDisableTiming = 2 };
 enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
 
 namespace emu {
@@ -261,6 +263,15 @@ inline hipError_t hipStreamDestroy(hipStream_t s) {
 }
 inline hipError_t hipEventCreate(hipEvent_t* e) {
   *e = new emu::Event();
+  return hipSuccess;
+}
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) {
+  *e = new emu::Event();
+  return hipSuccess;
+}
+// device memory is host memory here: a device variable's address is its own
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
   return hipSuccess;
 }
 inline hipError_t hipEventDestroy(hipEvent_t e) {
