@@ -219,16 +219,16 @@ def test_not_converged_and_nan():
     assert e.value.code == -6
 
 
-def _pair_mf(case, prec):
+def _pair_mf(case, prec, relax=1.0):
     """The Sec. 4.3 setting: eps coefficient (1 / 100 across min(x,y,z) = -1/2
-    in 3D), one undamped Jacobi smoothing step."""
+    in 3D), one Jacobi smoothing step (undamped: relax 1)."""
     from paper_1904_03317_amd import gmg
     rec, k = CASES[case]
     coeff = "eps" if rec.coarse == "fichera" else "one"
-    op, _ = oracle_problem(rec, k, coeff_kind=coeff, cheb_degree=1, smoother="jacobi", relax=1.0)
-    print(f"[gpu] MF case={case} k={k} prec={prec} N={op.n_dofs}", flush=True)
+    op, _ = oracle_problem(rec, k, coeff_kind=coeff, cheb_degree=1, smoother="jacobi", relax=relax)
+    print(f"[gpu] MF case={case} k={k} prec={prec} relax={relax} N={op.n_dofs}", flush=True)
     m, P, _ = library_problem(rec, k, coeff_kind=coeff, mg_precision=prec, cheb_degree=1,
-                              smoother=gmg.SMOOTHER_JACOBI, relax=1.0)
+                              smoother=gmg.SMOOTHER_JACOBI, relax=relax)
     P.bind()
     return op, P
 
@@ -250,9 +250,14 @@ def test_mf_jacobi_vcycle_and_solve_fp64(case):
     assert close(host(u), x, 1e-10)
 
 
-@pytest.mark.parametrize("case", ["fichera-q2", "fichera-q4"])
-def test_mf_jacobi_solve_fp32(case):
-    op, P = _pair_mf(case, 32)
+# The undamped step of Sec. 4.3 (a Q2 setting) needs lambda_max(D^-1 A^S) < 2
+# to be a convergent smoother; at Q4 it is 2.04 on level 1 of the Fichera
+# mesh with one global refinement, the V-cycle is then not positive definite
+# and CG may break down, so degree 4 runs with relax 0.6 (the FP32
+# cooperative transfer shape of degree 4 is exercised either way).
+@pytest.mark.parametrize("case,relax", [("fichera-q2", 1.0), ("fichera-q3", 1.0), ("fichera-q4", 0.6)])
+def test_mf_jacobi_solve_fp32(case, relax):
+    op, P = _pair_mf(case, 32, relax)
     f = np.ones(op.n_dofs)
     x, it, hist, ok = op.solve(f)
     u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
