@@ -219,6 +219,23 @@ int gmg_apply_level(gmg_problem p, int level, int variant, const void* d_in, voi
                     hipStream_t stream);
 int gmg_vcycle(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * V-cycle as gmg_vcycle, with its work memory (level vectors x, g, t, d,
+ * operator slots, restricted family values) in a fixed device array of the
+ * library, GMG_NOALLOC_SCRATCH_BYTES per GPU, created when the library's
+ * code is loaded on a GPU and held until the process ends.  The call
+ * allocates nothing (no hipMalloc/hipFree, no allocating library routine);
+ * the problem must be bound, with the current device the one it was bound
+ * on.  The array starts every call cleared (a fill kernel on `stream`), so
+ * the result equals gmg_vcycle's.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other threads) race and give
+ * wrong results; serialise them.  Errors: GMG_E_INVAL when the problem's
+ * work memory exceeds GMG_NOALLOC_SCRATCH_BYTES (the message gives the size
+ * needed), GMG_E_STATE (not bound, other device), GMG_E_HIP. */
+#define GMG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gmg_vcycle_noalloc(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream);
+
 /* Seconds of device time of the last gmg_solve* on this problem (events on
  * the caller's stream): [0] whole solve, [1] sum of V-cycles, [2] number of
  * V-cycles. */

@@ -321,6 +321,14 @@ int gmg_vcycle(gmg_problem p, const double* r, double* z, hipStream_t s) {
   });
 }
 
+int gmg_vcycle_noalloc(gmg_problem p, const double* r, double* z, hipStream_t s) {
+  return guard([&] {
+    REQUIRE(p && r && z, "null argument");
+    gmg::vcycle_noalloc(p->P, r, z, s);
+    return 0;
+  });
+}
+
 int gmg_problem_last_timing(gmg_problem p, double* out3) {
   return guard([&] {
     REQUIRE(p && out3, "null argument");

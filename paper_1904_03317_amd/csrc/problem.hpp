@@ -20,6 +20,15 @@ struct DevLevel {
   double lam = 1.0;    // lambda_max estimate of D^{-1} A^S
 };
 
+// Work memory of one V-cycle: level vectors x, g, t, d (concatenated over
+// levels, mg precision), operator slots of the level passes, restricted
+// parent-cell values of the fine families of one level.
+struct VWork {
+  void *lx = nullptr, *lg = nullptr, *lt = nullptr, *ld = nullptr;
+  double* E = nullptr;
+  char* rbuf = nullptr;
+};
+
 // state of an asynchronous CG solve
 struct CgState {
   bool running = false, pending = false, timed = false;
@@ -59,6 +68,8 @@ struct Problem {
   int n0 = 0;
   double* eig = nullptr;   // 5 FP64 vectors of the largest level
   int64_t max_level_dofs = 0;
+  int64_t e_levels = 0;    // operator slots the level passes need (E holds at least these)
+  int64_t fam_max = 0;     // largest family count of a level >= 1
   double* host = nullptr;  // pinned scalars
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -76,6 +87,9 @@ void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s
 // doubles of operator slots the leaf operator needs
 int64_t leaf_slots(const Problem& P);
 void vcycle(Problem& P, const double* r, double* z, hipStream_t s);
+// V-cycle with its work memory in the library's fixed device scratch array
+// (no allocation); GMG_E_INVAL when the problem needs more than it holds
+void vcycle_noalloc(Problem& P, const double* r, double* z, hipStream_t s);
 int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s);
 void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed);
 bool cg_poll(Problem& P, bool block);

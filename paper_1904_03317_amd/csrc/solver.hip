@@ -199,12 +199,14 @@ size_t plan_workspace(Problem& P, char* base) {
   P.cp = pl.take<double>(N);
   P.cq = pl.take<double>(N);
   P.cb = pl.take<double>(N);
+  P.e_levels = e_max;
   e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
   if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
   P.E = pl.take<double>(e_max);
   // restricted parent-cell values of the fine families of one level
   int64_t fam_max = 0;
   for (int l = 1; l <= L; ++l) fam_max = std::max<int64_t>(fam_max, M.levels[l].n_fam);
+  P.fam_max = fam_max;
   P.rbuf = pl.take<char>(size_t(fam_max) * M.npc * esz);
   P.scal = pl.take<double>(dev::kNumScalars + 8);
   // dot partials: the fixed dot grid, or one per block of the fused kernels
@@ -616,14 +618,14 @@ static StepCoef step_coef(const Problem& P, int l, int j) {
 // step 1 from the prolongated x, whose interface values stay fixed
 // (D^{-1} = 0 there) so that every residual includes A^{SI} x^I.
 template <typename T>
-static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
+static void smooth_steps(Problem& P, const VWork& W, int l, int first, hipStream_t s) {
   DevLevel& V = P.lv[l];
   const int64_t o = V.off;
-  T* E = (T*)P.E;
+  T* E = (T*)W.E;
   dev::Epi<T> ep;
-  ep.x = (T*)P.lx + o;
-  ep.d = (T*)P.ld + o;
-  ep.g = (T*)P.lg + o;
+  ep.x = (T*)W.lx + o;
+  ep.d = (T*)W.ld + o;
+  ep.g = (T*)W.lg + o;
   ep.dinv = (const T*)P.ldinv + o;
   ep.flags = V.v.flags;
   const LevelOps<T>& op = ops<T>(P);
@@ -642,12 +644,12 @@ static void smooth_steps(Problem& P, int l, int first, hipStream_t s) {
 // I rows is restricted; after prolongation the interface values enter the
 // post-smoothing residuals through A^{SI}.
 template <typename T>
-static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool dot_rz) {
+static void vcycle_t(Problem& P, const VWork& Wk, const double* r, double* z, hipStream_t s, bool dot_rz) {
   const Maps& M = *P.maps;
   const int L = (int)P.lv.size() - 1;
   const int64_t N = M.n_dofs;
-  T *X = (T*)P.lx, *G = (T*)P.lg, *R = (T*)P.lt, *Dd = (T*)P.ld, *Di = (T*)P.ldinv;
-  T* E = (T*)P.E;
+  T *X = (T*)Wk.lx, *G = (T*)Wk.lg, *R = (T*)Wk.lt, *Dd = (T*)Wk.ld, *Di = (T*)P.ldinv;
+  T* E = (T*)Wk.E;
   const LevelOps<T>& op = ops<T>(P);
   fill_dev(G, P.n_total, T(0), s);
   hipLaunchKernelGGL(dev::copy_to_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, r, G);
@@ -662,7 +664,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
     const int64_t n = V.v.n_dofs;
     // residual r = g - A x on S and I rows (0 on D rows)
     if (V.n_S > 0) {
-      smooth_steps<T>(P, l, 2, s);
+      smooth_steps<T>(P, Wk, l, 2, s);
       dev::Epi<T> ep;
       ep.y = R + V.off;
       ep.g = G + V.off;
@@ -684,7 +686,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
       ep.flags = W.v.flags;
       ep.c2 = T(step_coef(P, l - 1, 1).c2);
       ep.smooth = 1;
-      op.restrict_fc(V.v, W.v, R + V.off, ep, (T*)P.rbuf, E, mats<T>(P), s);
+      op.restrict_fc(V.v, W.v, R + V.off, ep, (T*)Wk.rbuf, E, mats<T>(P), s);
       op.sum(W.v, dev::kEpiRStart, E, ep, s);
     } else {
       op.restrict0(V.v, R + V.off, E, mats<T>(P), s);
@@ -697,7 +699,7 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
   for (int l = 1; l <= L; ++l) {
     DevLevel& V = P.lv[l];
     op.prolong(V.v, P.lv[l - 1].v, X + P.lv[l - 1].off, X + V.off, mats<T>(P), s);
-    if (V.n_S > 0) smooth_steps<T>(P, l, 1, s);
+    if (V.n_S > 0) smooth_steps<T>(P, Wk, l, 1, s);
   }
   if (dot_rz)  // partial sums of r.z for the CG (the dot's grid)
     hipLaunchKernelGGL(dev::copy_from_levels_dot<T>, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P.copy,
@@ -706,16 +708,99 @@ static void vcycle_t(Problem& P, const double* r, double* z, hipStream_t s, bool
     hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.copy, X, z);
 }
 
-static void vcycle_any(Problem& P, const double* r, double* z, hipStream_t s, bool dot_rz = false) {
+// the V-cycle work memory inside the problem's workspace
+static VWork own_work(const Problem& P) {
+  VWork W;
+  W.lx = P.lx;
+  W.lg = P.lg;
+  W.lt = P.lt;
+  W.ld = P.ld;
+  W.E = P.E;
+  W.rbuf = P.rbuf;
+  return W;
+}
+
+static void vcycle_any(Problem& P, const VWork& W, const double* r, double* z, hipStream_t s,
+                       bool dot_rz = false) {
   if (P.opt.mg_precision == 32)
-    vcycle_t<float>(P, r, z, s, dot_rz);
+    vcycle_t<float>(P, W, r, z, s, dot_rz);
   else
-    vcycle_t<double>(P, r, z, s, dot_rz);
+    vcycle_t<double>(P, W, r, z, s, dot_rz);
 }
 
 void vcycle(Problem& P, const double* r, double* z, hipStream_t s) {
   if (!P.bound) fail(GMG_E_STATE, "problem not bound");
-  vcycle_any(P, r, z, s);
+  vcycle_any(P, own_work(P), r, z, s);
+  HIPCHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// Work memory of gmg_vcycle_noalloc, for callers that cannot allocate device
+// memory: one array per GPU, created when the library's code is loaded on
+// that GPU and held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): the device address comes from hipGetSymbolAddress, looked up once
+// per device with that device current.
+static __device__ __align__(256) char scratch[GMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+// device address of the scratch array on the current device
+static char* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(GMG_E_INVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      fail(GMG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = (char*)ptr;
+  }
+  return g_scratch[device];
+}
+
+// the V-cycle work memory carved from base (256-byte aligned pieces); with
+// base == nullptr only the size is computed
+static size_t carve_work(const Problem& P, char* base, VWork* W) {
+  const size_t esz = P.opt.mg_precision == 32 ? 4 : 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  VWork w;
+  w.lx = take(size_t(P.n_total) * esz);
+  w.lg = take(size_t(P.n_total) * esz);
+  w.lt = take(size_t(P.n_total) * esz);
+  w.ld = take(size_t(P.n_total) * esz);
+  w.E = (double*)take(size_t(P.e_levels) * sizeof(double));
+  w.rbuf = take(size_t(P.fam_max) * P.maps->npc * esz);
+  if (W) *W = w;
+  return off;
+}
+
+void vcycle_noalloc(Problem& P, const double* r, double* z, hipStream_t s) {
+  if (!P.bound) fail(GMG_E_STATE, "problem not bound");
+  int device = -1;
+  HIPCHECK(hipGetDevice(&device));
+  if (device != P.device) fail(GMG_E_STATE, "the current device is not the one the problem is bound on");
+  const size_t need = carve_work(P, nullptr, nullptr);
+  if (need > GMG_NOALLOC_SCRATCH_BYTES)
+    fail(GMG_E_INVAL, "V-cycle work memory of this problem (" + std::to_string(need) +
+                          " bytes) exceeds the fixed scratch (" + std::to_string((size_t)GMG_NOALLOC_SCRATCH_BYTES) +
+                          " bytes)");
+  char* base = scratch_on(device);
+  VWork W;
+  carve_work(P, base, &W);
+  // the array keeps the previous call's contents: start from zero level
+  // vectors as a freshly bound problem does (a fill kernel, no memset node)
+  fill_dev((double*)base, int64_t(need / sizeof(double)), 0.0, s);
+  vcycle_any(P, W, r, z, s);
   HIPCHECK(hipGetLastError());
 }
 
@@ -723,7 +808,7 @@ void vcycle(Problem& P, const double* r, double* z, hipStream_t s) {
 // fixed CG buffers r -> z when enabled
 static void precondition(Problem& P, hipStream_t s) {
   if (!P.opt.use_graph) {
-    vcycle_any(P, P.cr, P.cz, s, true);
+    vcycle_any(P, own_work(P), P.cr, P.cz, s, true);
     return;
   }
   if (!P.graph) {
@@ -731,7 +816,7 @@ static void precondition(Problem& P, hipStream_t s) {
     HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g;
     HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    vcycle_any(P, P.cr, P.cz, cs, true);
+    vcycle_any(P, own_work(P), P.cr, P.cz, cs, true);
     HIPCHECK(hipStreamEndCapture(cs, &g));
     HIPCHECK(hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0));
     HIPCHECK(hipGraphDestroy(g));
@@ -753,7 +838,7 @@ static void level_hook(Problem& P, int l, int variant, const T* x, T* y, hipStre
     if (l < 1) fail(GMG_E_INVAL, "smoothing step needs a level >= 1");
     const int keep = P.opt.cheb_degree;
     P.opt.cheb_degree = 2;
-    smooth_steps<T>(P, l, 2, s);
+    smooth_steps<T>(P, own_work(P), l, 2, s);
     P.opt.cheb_degree = keep;
     return;
   }

@@ -89,6 +89,7 @@ def configure(L):
         "gmg_apply_leaf": (C.c_int, [vp, vp, vp, vp]),
         "gmg_apply_level": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp]),
         "gmg_vcycle": (C.c_int, [vp, vp, vp, vp]),
+        "gmg_vcycle_noalloc": (C.c_int, [vp, vp, vp, vp]),
         "gmg_problem_last_timing": (C.c_int, [vp, C.POINTER(dbl)]),
         "gmg_server_create": (C.c_int, [vp, C.c_size_t, i32, i32, C.POINTER(vp)]),
         "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, vp, i64, C.POINTER(C.c_uint64)]),
@@ -131,7 +132,7 @@ def exported_symbols():
             "gmg_mesh_num_leaves", "gmg_mesh_leaves", "gmg_mesh_dim", "gmg_mesh_destroy",
             "gmg_problem_create", "gmg_problem_clone", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
-            "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle",
+            "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle", "gmg_vcycle_noalloc",
             "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_request_dofs",
             "gmg_server_set_rhs", "gmg_server_poll",
             "gmg_server_wait", "gmg_server_result", "gmg_server_release", "gmg_server_stats",
@@ -287,6 +288,11 @@ class Problem:
 
     def vcycle(self, r, z, stream=None):
         _check(lib().gmg_vcycle(self.h, _ptr(r), _ptr(z), _stream(stream)))
+
+    def vcycle_noalloc(self, r, z, stream=None):
+        """gmg_vcycle with the work memory in the library's fixed scratch
+        array (allocates nothing)"""
+        _check(lib().gmg_vcycle_noalloc(self.h, _ptr(r), _ptr(z), _stream(stream)))
 
     def last_timing(self):
         out = (C.c_double * 3)()

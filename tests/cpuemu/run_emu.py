@@ -136,6 +136,14 @@ def main():
         check(L.gmg_vcycle(P, ptr(r), ptr(z), None))
         zr = op.mg.vcycle(r)
         out["vcycle_rel"] = rel(z, zr)
+        # the same V-cycle with its work memory in the fixed scratch array,
+        # twice (the second call finds the first call's contents)
+        z2 = np.full(N, np.nan)
+        check(L.gmg_vcycle_noalloc(P, ptr(r), ptr(z2), None))
+        eq = bool(np.array_equal(z2, z))
+        z2[:] = np.nan
+        check(L.gmg_vcycle_noalloc(P, ptr(r), ptr(z2), None))
+        out["noalloc_equal"] = eq and bool(np.array_equal(z2, z))
     if "solve" in checks:
         fn = gi.rhs_nodal("noise", N)
         x, it, hist, ok = op.solve(fn)

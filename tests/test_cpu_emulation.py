@@ -66,5 +66,6 @@ def test_emulated_kernels_match_oracle(emu_results, case, prec):
     else:
         # FP32 level operators and V-cycle: single-precision rounding
         assert r["level_rel"] <= 2e-6 and r["edge_rel"] <= 2e-6 and r["vcycle_rel"] <= 1e-5
+    assert r["noalloc_equal"]
     assert r["status"] == 0 and r["its"] == r["its_oracle"]
     assert r["solve_rel"] <= 1e-10
