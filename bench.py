@@ -63,7 +63,7 @@ def roofline(r, traffic):
     a = 6 * esz * nl / r["t_cheb"] / 1e9
     a_apply = 2 * esz * nl / r["t_apply"] / 1e9
     t_bytes = traffic.get("cheb_bytes_per_launch") if traffic else None
-    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+    out = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
             "traffic": t_bytes,
             "kernel": f"Chebyshev step on level {r['lmax']} ({nl} DoFs, {r['level_cells']} cells): "
                       f"pass 1 + pass 2, {6 * esz} B/DoF algorithmic, 512 MB cache flush before each launch",
@@ -71,6 +71,80 @@ def roofline(r, traffic):
             "apply": {"achieved": a_apply, "frac": a_apply / HBM_PEAK_GBS, "t_launch_us": r["t_apply"] * 1e6,
                       "bytes_per_dof": 2 * esz,
                       "traffic": traffic.get("apply_bytes_per_launch") if traffic else None}}
+    if "t_leaf" in r:
+        a_leaf = 16 * r["N"] / r["t_leaf"] / 1e9
+        out["leaf"] = {"achieved": a_leaf, "frac": a_leaf / HBM_PEAK_GBS, "t_launch_us": r["t_leaf"] * 1e6,
+                       "bytes_per_dof": 16, "kernel": "FP64 leaf operator q = C^T A C p with hanging nodes "
+                                                      "(read p, write q), 512 MB cache flush before each launch"}
+    return out
+
+
+def unit_timings(P, info, prec, leaf, reps=20):
+    """Device time per launch, HIP events on the stream the library launches
+    on (the current stream), of the solve's units on the largest level: the
+    operator y = A x and one Chebyshev step (each pass 1 fam_op + pass 2
+    fam_sum); with leaf, also the FP64 leaf operator q = C^T A C p (once per
+    CG iteration).  A 512 MB buffer is written before every timed launch so
+    that the vectors do not stay in the 256 MB Infinity Cache between
+    launches."""
+    import numpy as np
+    import torch
+
+    lmax = int(np.argmax(list(info.level_dofs)[:info.n_levels]))
+    nl = int(info.level_dofs[lmax])
+    tdt = torch.float64 if prec == 64 else torch.float32
+    x = torch.randn(nl, dtype=tdt, device="cuda")
+    y = torch.zeros(nl, dtype=tdt, device="cuda")
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+
+    def timed(launch):
+        for _ in range(3):
+            launch()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            flush.fill_(1.0)
+            a.record(stream)
+            launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in ev) / reps * 1e-3
+
+    t_apply = timed(lambda: P.apply_level(lmax, 0, x, y))
+    t_cheb = timed(lambda: P.apply_level(lmax, 2, x, y))
+    log(f"  level {lmax} ({nl} DoFs): operator {t_apply * 1e6:.1f} us, Chebyshev step {t_cheb * 1e6:.1f} us")
+    out = dict(lmax=lmax, level_dofs=nl, level_cells=int(info.level_cells[lmax]), t_apply=t_apply, t_cheb=t_cheb,
+               esz=8 if prec == 64 else 4)
+    if leaf:
+        N = info.n_dofs
+        p = torch.randn(N, dtype=torch.float64, device="cuda")
+        q = torch.zeros(N, dtype=torch.float64, device="cuda")
+        out["t_leaf"] = timed(lambda: P.apply_leaf(p, q))
+        log(f"  leaf operator ({N} DoFs, {info.n_leaves} cells): {out['t_leaf'] * 1e6:.1f} us")
+    return out
+
+
+def kernels_only(w, mesh, coeff):
+    """--kernels: set-up and the unit timings only (no solves), for counter
+    runs under rocprofv3; one JSON line."""
+    from paper_1904_03317_amd import gmg
+
+    base = gmg.Problem(mesh, wopts(w, 64), coeff=coeff)
+    out = {"mode": "kernels", "workload": w.name, "g": w.recipe.globals_}
+    for prec in (64, 32):
+        P = base.clone(wopts(w, prec)).bind("cuda")
+        info = P.info()
+        r = unit_timings(P, info, prec, leaf=prec == 64)
+        nl, esz = r["level_dofs"], r["esz"]
+        out[f"fp{prec}"] = {"level": r["lmax"], "level_dofs": nl, "apply_us": r["t_apply"] * 1e6,
+                            "cheb_step_us": r["t_cheb"] * 1e6,
+                            "cheb_step_frac": 6 * esz * nl / r["t_cheb"] / 1e9 / HBM_PEAK_GBS,
+                            "apply_frac": 2 * esz * nl / r["t_apply"] / 1e9 / HBM_PEAK_GBS}
+        if "t_leaf" in r:
+            out["leaf"] = {"dofs": info.n_dofs, "cells": info.n_leaves, "us": r["t_leaf"] * 1e6,
+                           "frac": 16 * info.n_dofs / r["t_leaf"] / 1e9 / HBM_PEAK_GBS}
+        P.close()
+    print(json.dumps(out), flush=True)
 
 
 def wopts(w, prec):
@@ -238,6 +312,8 @@ def main():
                          "C2: Fichera Q2 1.9e7 DoFs, FP64 throughout)")
     ap.add_argument("--g", type=int, default=None, help="global refinements (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernels", action="store_true",
+                    help="only the unit timings of the largest level and the leaf operator (for counter runs)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-big", type=int, default=5, metavar="G",
@@ -264,6 +340,15 @@ def main():
     mesh = gmg.build_mesh(w.recipe)
     log(f"{w.name}: mesh {mesh.n_leaves} leaves ({time.perf_counter() - t0:.1f} s)")
     coeff = gi.coeff_cells(w.coeff, *mesh.leaves()) if w.coeff != "one" else None
+
+    if args.kernels:
+        # the calibration copy first, as in the full run
+        cal_a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        torch.empty_like(cal_a).copy_(cal_a)
+        torch.cuda.synchronize()
+        del cal_a
+        kernels_only(w, mesh, coeff)
+        return
 
     # calibration copy of a known size for the HBM traffic counters
     # (FETCH_SIZE / WRITE_SIZE of this copy divided by 256 MiB is the scale),
@@ -320,44 +405,12 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         log(f"  timed: {args.steps} solves, {wall / args.steps * 1e3:.2f} ms/solve, its {its}, res {h[-1]:.2e}")
-        # dominant kernel: the operator application y = A x on the largest
-        # level (pass 1 fam_op + pass 2 fam_sum), HIP events on the stream
-        # the library launches on (the current stream)
-        lmax = int(np.argmax(list(info.level_dofs)[:info.n_levels]))
-        nl = int(info.level_dofs[lmax])
-        tdt = torch.float64 if prec == 64 else torch.float32
-        x = torch.randn(nl, dtype=tdt, device="cuda")
-        y = torch.zeros(nl, dtype=tdt, device="cuda")
-        stream = torch.cuda.current_stream()
-        # 512 MB written between repetitions: the level's vectors do not stay
-        # in the 256 MB Infinity Cache from one launch to the next
-        flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
-
-        def timed(variant, reps=20):
-            for _ in range(3):
-                P.apply_level(lmax, variant, x, y)
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-            for a, b in ev:
-                flush.fill_(1.0)
-                a.record(stream)
-                P.apply_level(lmax, variant, x, y)
-                b.record(stream)
-            torch.cuda.synchronize()
-            return sum(a.elapsed_time(b) for a, b in ev) / reps * 1e-3
-
-        # y = A x (operator apply) and one Chebyshev step of the smoother
-        # (the solve's dominant unit), each = pass 1 fam_op + pass 2 fam_sum
-        t_apply = timed(0)
-        t_cheb = timed(2)
-        log(f"  level {lmax} ({nl} DoFs): operator {t_apply * 1e6:.1f} us, Chebyshev step {t_cheb * 1e6:.1f} us")
-        esz = 8 if prec == 64 else 4
         results[prec] = dict(N=N, levels=info.n_levels, its=its, res=float(h[-1]), status=st,
                              ms=wall / args.steps * 1e3, dev_ms=dev_t / args.steps * 1e3,
-                             vcycle_ms=vc_t / max(n_vc, 1) * 1e3, lmax=lmax, level_dofs=nl,
-                             level_cells=int(info.level_cells[lmax]), t_apply=t_apply, t_cheb=t_cheb,
-                             esz=esz, maps_s=t_maps, bind_s=t_bind, u=u.cpu().numpy())
+                             vcycle_ms=vc_t / max(n_vc, 1) * 1e3, maps_s=t_maps, bind_s=t_bind,
+                             u=u.cpu().numpy(), **unit_timings(P, info, prec, leaf=prec == 64))
         P.close()
-        del f, x, y, flush
+        del f
         torch.cuda.empty_cache()
 
     # the value is the workload's own precision (C2: FP64 throughout; C3, C5:

@@ -48,6 +48,22 @@ struct LeafView {
   const int32_t* slot = nullptr;    // SoA [npc][n_cells] slot in the node-major buffer
   const int32_t* soff = nullptr;    // [n_dofs + 1]
   const uint8_t* dir = nullptr;     // [n_dofs] Dirichlet flag
+  // tiles of 64 cells (all but 3D at degree >= 3; host/leaftiles.hpp):
+  // per tile the range of its nodes, counts of complete and partial nodes,
+  // first partial slot; node DoFs (~dof: complete Dirichlet node); per
+  // (position, cell) the tile-local node; the second-pass nodes and their
+  // slot lists
+  int64_t n_tiles = 0, n_part = 0, n_p2 = 0;
+  int32_t max_nodes = 0;
+  const int64_t* t_off = nullptr;   // [n_tiles + 1]
+  const int32_t* t_na = nullptr;    // [n_tiles]
+  const int32_t* t_nb = nullptr;    // [n_tiles]
+  const int32_t* t_pbase = nullptr; // [n_tiles]
+  const int32_t* t_node = nullptr;
+  const uint16_t* lmap = nullptr;   // SoA [npc][n_cells]
+  const int32_t* p2_dof = nullptr;  // [n_p2]
+  const int32_t* p2_off = nullptr;  // [n_p2 + 1]
+  const int32_t* p2_slot = nullptr;
 };
 
 template <typename T>
@@ -86,7 +102,12 @@ struct KernelTable {
   LevelOps<float> f32;
   LevelOps<double> f64;
   // pass 1 of the leaf operator (or mass matrix): cell results into slots
+  // (3D at degree >= 3)
   void (*leaf_e)(const LeafView&, const double* x, double* E, bool mass, const MatsH<double>&, hipStream_t);
+  // tiled leaf operator, pass 1: complete nodes into y, the rest into the
+  // slots E; with part, one partial sum of x.y per block; returns the grid
+  unsigned (*leaf_t)(const LeafView&, const double* x, double* y, double* E, double* part, bool mass,
+                     const MatsH<double>&, hipStream_t);
   // level 0: diagonal of the operator accumulated per node
   void (*diag0)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
 };

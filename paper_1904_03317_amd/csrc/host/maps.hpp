@@ -9,6 +9,7 @@
 #include "fe1d.hpp"
 #include "forest.hpp"
 #include "layout.hpp"
+#include "leaftiles.hpp"
 
 namespace gmg {
 
@@ -54,6 +55,7 @@ struct Maps {
   std::vector<int32_t> copy_index;    // [n_dofs]
   std::vector<LevelData> levels;
   std::vector<LevelLayout> layouts;  // device layout of levels >= 1
+  LeafTiles tiles;                   // tiled leaf operator (empty in 3D at degree >= 3)
 };
 
 // threads: host threads for the leaf-mesh phases (0: the hardware's, at

@@ -178,6 +178,26 @@ struct Inst {
                            E, to_dev(m));
     }
   }
+  static unsigned leaf_t(const LeafView& v, const double* x, double* y, double* E, double* part, bool mass,
+                         const MatsH<double>& m, hipStream_t s) {
+    if constexpr (DIM == 3 && K >= 3) {
+      fail(GMG_E_STATE, "tiled leaf operator not built for 3D degree >= 3");
+    } else {
+      if (!v.n_tiles) return 0;
+      const unsigned g = (unsigned)std::min<int64_t>(v.n_tiles, dev::kLeafBlocks);
+      const size_t lds = size_t(v.max_nodes) * sizeof(double);
+      if (mass)
+        hipLaunchKernelGGL((dev::leaf_tiles<DIM, N, true, false>), dim3(g), dim3(64), lds, s, v, x, y, E, part,
+                           to_dev(m));
+      else if (part)
+        hipLaunchKernelGGL((dev::leaf_tiles<DIM, N, false, true>), dim3(g), dim3(64), lds, s, v, x, y, E, part,
+                           to_dev(m));
+      else
+        hipLaunchKernelGGL((dev::leaf_tiles<DIM, N, false, false>), dim3(g), dim3(64), lds, s, v, x, y, E, part,
+                           to_dev(m));
+      return g;
+    }
+  }
   static void diag0(const LevelView& v, double* d, const MatsH<double>& m, hipStream_t s) {
     if (!v.n_cells) return;
     hipLaunchKernelGGL((dev::cell_diag<DIM, N>), dim3(grid_for(v.n_cells)), dim3(dev::kBlock), 0, s, v.n_cells,
@@ -189,7 +209,7 @@ struct Inst {
     return LevelOps<T>{&op<T>, &sum<T>, &restrict_fc<T>, &restrict0<T>, &prolong<T>, &cell_e<T>};
   }
   static const KernelTable* table() {
-    static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &diag0};
+    static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &leaf_t, &diag0};
     return &t;
   }
 };

@@ -9,6 +9,8 @@
 
 #include <cstdint>
 
+#include "dispatch.hpp"
+
 namespace gmg {
 namespace dev {
 
@@ -20,6 +22,28 @@ struct Mats {
   T M[25];
   T K[25];
   T E[45];   // (2k+1) x (k+1), row-major
+};
+
+// The 1D matrices of degrees 1 and 2, whose Gauss-Lobatto nodes are the
+// equidistant ones, as compile-time constants (the rationals the host's
+// quadrature computes up to rounding): mass M_ij = int l_i l_j and
+// stiffness K_ij = int l_i' l_j' on [0, 1], embedding rows E (2k+1 child
+// nodes of the two halves by k+1 parent nodes).  Kernels that take them
+// keep no matrix entries in registers.
+template <int N>
+struct Exact1D;
+template <>
+struct Exact1D<2> {
+  static constexpr double M[4] = {2.0 / 6, 1.0 / 6, 1.0 / 6, 2.0 / 6};
+  static constexpr double K[4] = {1.0, -1.0, -1.0, 1.0};
+  static constexpr double E[6] = {1.0, 0.0, 0.5, 0.5, 0.0, 1.0};
+};
+template <>
+struct Exact1D<3> {
+  static constexpr double M[9] = {4.0 / 30, 2.0 / 30, -1.0 / 30, 2.0 / 30, 16.0 / 30, 2.0 / 30, -1.0 / 30, 2.0 / 30, 4.0 / 30};
+  static constexpr double K[9] = {7.0 / 3, -8.0 / 3, 1.0 / 3, -8.0 / 3, 16.0 / 3, -8.0 / 3, 1.0 / 3, -8.0 / 3, 7.0 / 3};
+  static constexpr double E[15] = {1.0,  0.0,    0.0,   0.375, 0.75, -0.125, 0.0, 1.0,
+                                   0.0, -0.125, 0.75, 0.375, 0.0,  0.0,    1.0};
 };
 
 // Consecutive hardware dispatch goes round-robin over the 8 XCDs, each with
@@ -43,8 +67,8 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
 // The tensor of a cell is stored x fastest.
 
 // y = (sum over directions of K in that direction, M elsewhere) x, 3D
-template <int N, typename T>
-__device__ __forceinline__ void laplace3(const Mats<T>& m, const T (&u)[N * N * N], T (&out)[N * N * N]) {
+template <int N, typename T, typename MT>
+__device__ __forceinline__ void laplace3(const MT& m, const T (&u)[N * N * N], T (&out)[N * N * N]) {
   T a[N * N * N], b[N * N * N];
 #pragma unroll
   for (int zy = 0; zy < N * N; ++zy) {
@@ -97,8 +121,8 @@ __device__ __forceinline__ void laplace3(const Mats<T>& m, const T (&u)[N * N * 
   }
 }
 
-template <int N, typename T>
-__device__ __forceinline__ void laplace2(const Mats<T>& m, const T (&u)[N * N], T (&out)[N * N]) {
+template <int N, typename T, typename MT>
+__device__ __forceinline__ void laplace2(const MT& m, const T (&u)[N * N], T (&out)[N * N]) {
   T a[N * N], b[N * N];
 #pragma unroll
   for (int y = 0; y < N; ++y)
@@ -125,8 +149,8 @@ __device__ __forceinline__ void laplace2(const Mats<T>& m, const T (&u)[N * N], 
 }
 
 // mass: out = (M x M [x M]) u
-template <int DIM, int N, typename T>
-__device__ __forceinline__ void mass_nd(const Mats<T>& m, T* u, T* out) {
+template <int DIM, int N, typename T, typename MT>
+__device__ __forceinline__ void mass_nd(const MT& m, T* u, T* out) {
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   T a[NP];
 #pragma unroll
@@ -368,6 +392,226 @@ __device__ __forceinline__ void constrain(const Mats<T>& m, uint32_t mask, T* u,
   constrain_from<DIM, N, T>(m, mask, c, u, fwd);
 }
 
+// ------------------------------------------------------------------ canonical in-cell constraints
+// The same in-cell constraints after a reflection of the cell that moves its
+// child position to 0 along every axis (lane-per-cell kernels).  The
+// constrained faces and edges of a leaf lie on its parent's boundary on the
+// child's side, so after the reflection they are the faces j_a = 0 and the
+// edges through the corner 0; the embedding rows of child position 0 are
+// then fixed (compile-time indices, no per-coefficient selects), which holds
+// because the 1D matrices of symmetric nodes are centro-symmetric:
+// E[2K - i][K - J] = E[i][J], and the cell operator and mass matrix are
+// invariant under reflections of the node order.
+
+// c ? a : b by bit masks (no select of addresses, which would move a
+// register array to scratch memory)
+__device__ __forceinline__ double bsel(bool c, double a, double b) {
+  const long long m = -(long long)c;
+  return __longlong_as_double((__double_as_longlong(a) & m) | (__double_as_longlong(b) & ~m));
+}
+
+// reverse the node order along every axis a with bit a of r set
+template <int DIM, int N>
+__device__ __forceinline__ void reflect_cell(uint32_t r, double* u) {
+  constexpr int K = N - 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const bool f = (r >> a) & 1u;
+    const int st = a == 0 ? 1 : a == 1 ? N : N * N;
+#pragma unroll
+    for (int p = 0; p < (DIM == 3 ? N * N * N : N * N); ++p) {
+      const int ja = (p / st) % N;
+      if (2 * ja < K) {
+        const int q = p + (K - 2 * ja) * st;
+        const double x = u[p], y = u[q];
+        u[p] = bsel(f, y, x);
+        u[q] = bsel(f, x, y);
+      }
+    }
+  }
+}
+
+// local index of position (ja, jb, jc) given along axes a, b, c
+template <int DIM, int N>
+__device__ constexpr int pos3(int a, int ja, int b, int jb, int c, int jc) {
+  int j[3] = {0, 0, 0};
+  j[a] = ja;
+  j[b] = jb;
+  if (DIM == 3) j[c] = jc;
+  return DIM == 3 ? j[0] + N * (j[1] + N * j[2]) : j[0] + N * j[1];
+}
+
+// Number of the canonical entities containing position p (zero
+// coordinates): faces a (j_a = 0, entity a, mask bit 3 + a), then in 3D
+// edges along a (the other two coordinates 0, entity 3 + a, bit 6 + a).
+template <int DIM, int N>
+__device__ constexpr bool on_entity(int e, int p) {
+  const int j0 = p % N, j1 = (p / N) % N, j2 = DIM == 3 ? p / (N * N) : 0;
+  const int j[3] = {j0, j1, j2};
+  if (e < DIM) return j[e] == 0;
+  const int a = e - 3;
+  return (a != 0 ? j[0] == 0 : true) && (a != 1 ? j[1] == 0 : true) && (a != 2 ? j[2] == 0 : true);
+}
+
+// u <- C u on a reflected cell (act: mask bits 3..8, entity order faces x,
+// y, z then edges x, y, z, the last active entity containing a position
+// giving its value, every entity reading the gathered values)
+template <int DIM, int N, typename MT>
+__device__ __forceinline__ void con_fwd_canon(const MT& m, uint32_t act, double* u) {
+  constexpr int K = N - 1, NP = DIM == 3 ? N * N * N : N * N, NE = DIM == 3 ? 6 : 2;
+  // gathered values of the positions on more than one entity
+  double o[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) cnt += on_entity<DIM, N>(e, p) ? 1 : 0;
+    if (cnt >= 2) o[p] = u[p];
+  }
+  auto src = [&](int p) -> double {
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) cnt += on_entity<DIM, N>(e, p) ? 1 : 0;
+    return cnt >= 2 ? o[p] : u[p];
+  };
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (!((act >> e) & 1u)) continue;
+    if (e < DIM) {
+      const int a = e, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      constexpr int NC = DIM == 3 ? N : 1;
+      double g[N * NC], t[N * NC];
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb)
+#pragma unroll
+        for (int jc = 0; jc < NC; ++jc) g[jb * NC + jc] = src(pos3<DIM, N>(a, 0, b, jb, c, jc));
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb)
+#pragma unroll
+        for (int jc = 0; jc < NC; ++jc) {
+          double s = 0.0;
+#pragma unroll
+          for (int J = 0; J < N; ++J) s += m.E[jb * N + J] * g[J * NC + jc];
+          t[jb * NC + jc] = s;
+        }
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb)
+#pragma unroll
+        for (int jc = 0; jc < NC; ++jc) {
+          double s = t[jb * NC + jc];
+          if (DIM == 3) {
+            s = 0.0;
+#pragma unroll
+            for (int J = 0; J < N; ++J) s += m.E[jc * N + J] * t[jb * NC + J];
+          }
+          u[pos3<DIM, N>(a, 0, b, jb, c, jc)] = s;
+        }
+    } else {
+      const int a = e - 3, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      double g[N];
+#pragma unroll
+      for (int J = 0; J < N; ++J) g[J] = src(pos3<DIM, N>(a, J, b, 0, c, 0));
+#pragma unroll
+      for (int ja = 0; ja < N; ++ja) {
+        double s = 0.0;
+#pragma unroll
+        for (int J = 0; J < N; ++J) s += m.E[ja * N + J] * g[J];
+        u[pos3<DIM, N>(a, ja, b, 0, c, 0)] = s;
+      }
+    }
+  }
+  (void)K;
+}
+
+// v <- C^T v on a reflected cell: every position of an active entity is
+// claimed by the first active entity containing it, whose transposed
+// embedding moves the claimed values to the entity's parent positions
+template <int DIM, int N, typename MT>
+__device__ __forceinline__ void con_bwd_canon(const MT& m, uint32_t act, double* v) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N, NE = DIM == 3 ? 6 : 2;
+  // the operator values of the positions on more than one entity
+  double o[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) cnt += on_entity<DIM, N>(e, p) ? 1 : 0;
+    if (cnt >= 2) o[p] = v[p];
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (!((act >> e) & 1u)) continue;
+    // claimed here: on this entity, on no earlier active one
+    auto claim = [&](int p) -> bool {
+      bool earlier = false;
+#pragma unroll
+      for (int f = 0; f < e; ++f)
+        if (on_entity<DIM, N>(f, p)) earlier = earlier || ((act >> f) & 1u);
+      return !earlier;
+    };
+    auto val = [&](int p) -> double {
+      int cnt = 0;
+#pragma unroll
+      for (int f = 0; f < DIM; ++f) cnt += on_entity<DIM, N>(f, p) ? 1 : 0;
+      return cnt >= 2 ? o[p] : v[p];
+    };
+    if (e < DIM) {
+      const int a = e, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      constexpr int NC = DIM == 3 ? N : 1;
+      double w[N * NC], t[N * NC];
+#pragma unroll
+      for (int jb = 0; jb < N; ++jb)
+#pragma unroll
+        for (int jc = 0; jc < NC; ++jc) {
+          const int p = pos3<DIM, N>(a, 0, b, jb, c, jc);
+          const bool cl = claim(p);
+          const double x = val(p);
+          w[jb * NC + jc] = bsel(cl, x, 0.0);
+          v[p] -= w[jb * NC + jc];
+        }
+#pragma unroll
+      for (int Jb = 0; Jb < N; ++Jb)
+#pragma unroll
+        for (int jc = 0; jc < NC; ++jc) {
+          double s = 0.0;
+#pragma unroll
+          for (int jb = 0; jb < N; ++jb) s += m.E[jb * N + Jb] * w[jb * NC + jc];
+          t[Jb * NC + jc] = s;
+        }
+#pragma unroll
+      for (int Jb = 0; Jb < N; ++Jb)
+#pragma unroll
+        for (int Jc = 0; Jc < NC; ++Jc) {
+          double s = t[Jb * NC + Jc];
+          if (DIM == 3) {
+            s = 0.0;
+#pragma unroll
+            for (int jc = 0; jc < N; ++jc) s += m.E[jc * N + Jc] * t[Jb * NC + jc];
+          }
+          v[pos3<DIM, N>(a, 0, b, Jb, c, Jc)] += s;
+        }
+    } else {
+      const int a = e - 3, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      double w[N];
+#pragma unroll
+      for (int ja = 0; ja < N; ++ja) {
+        const int p = pos3<DIM, N>(a, ja, b, 0, c, 0);
+        const bool cl = claim(p);
+        const double x = val(p);
+        w[ja] = bsel(cl, x, 0.0);
+        v[p] -= w[ja];
+      }
+#pragma unroll
+      for (int J = 0; J < N; ++J) {
+        double s = 0.0;
+#pragma unroll
+        for (int ja = 0; ja < N; ++ja) s += m.E[ja * N + J] * w[ja];
+        v[pos3<DIM, N>(a, J, b, 0, c, 0)] += s;
+      }
+    }
+  }
+}
+
 // Two-pass operator, pass 1: every (cell, local node) owns one slot of the
 // node-major buffer E (the slots of a node are contiguous), so the cell
 // results are written with plain stores and no two lanes ever write the same
@@ -398,6 +642,155 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
   const T s = T(scale ? scale[c] : scale0);
 #pragma unroll
   for (int j = 0; j < NP; ++j) E[slot[(int64_t)j * n_cells + c]] = s * v[j];
+}
+
+// Leaf operator q = C^T A C p (or the mass matrix) on tiles of 64
+// consecutive leaf cells, one wavefront (block) per tile at a time, the
+// tiles of a block contiguous.  Per tile: the values of all nodes the cells
+// touch are gathered once into LDS; each lane takes one cell (in-cell
+// constraints forward, operator, constraints transposed) and adds its
+// results into LDS position by position, the results of constrained
+// positions into the parent's nodes.  Only this wave adds into the tile's
+// LDS, its adds issue in a fixed order, and same-address adds within one
+// instruction are resolved by the LDS unit in a fixed order, so every sum is
+// formed in the same order on every run.  Then the tile's complete nodes
+// (all their contributions are in this tile) are written to q, Dirichlet
+// rows as zero, and the others to the tile's partial slots, which
+// leaf_pass2 sums.  DOT: one partial sum of p.q per block over the complete
+// nodes.
+
+// one leaf cell: in-cell constraints on the cell reflected to child
+// position 0 (a cell without constrained entities is neither reflected nor
+// constrained), operator or mass matrix, constraints transposed, reflected
+// back
+template <int DIM, int N, bool MASS, typename MT>
+__device__ __forceinline__ void leaf_cell(const MT& m, uint32_t mk, double* u, double* w) {
+  const uint32_t ce = (mk >> 3) & 0x3fu;
+  const uint32_t refl = ce ? (mk & 7u) : 0u;
+  if (ce) {
+    reflect_cell<DIM, N>(refl, u);
+    con_fwd_canon<DIM, N>(m, ce, u);
+  }
+  if (MASS)
+    mass_nd<DIM, N, double>(m, u, w);
+  else if (DIM == 3)
+    laplace3<N, double>(m, *reinterpret_cast<const double(*)[N * N * N]>(u), *reinterpret_cast<double(*)[N * N * N]>(w));
+  else
+    laplace2<N, double>(m, *reinterpret_cast<const double(*)[N * N]>(u), *reinterpret_cast<double(*)[N * N]>(w));
+  if (ce) {
+    con_bwd_canon<DIM, N>(m, ce, w);
+    reflect_cell<DIM, N>(refl, w);
+  }
+}
+
+constexpr int kLeafBlocks = 8192;  // grid of leaf_tiles at most (32 one-wave blocks per CU)
+constexpr int kLeafGB = 16;        // tile nodes per lane whose loads are issued together
+
+template <int DIM, int N, bool MASS, bool DOT>
+__global__ void __launch_bounds__(64) leaf_tiles(LeafView v, const double* __restrict__ x, double* __restrict__ y,
+                                                 double* __restrict__ E, double* __restrict__ part, Mats<double> m) {
+  constexpr int NP = DIM == 3 ? N * N * N : N * N;
+  HIP_DYNAMIC_SHARED(double, lds)
+  const int lane = threadIdx.x;
+  const int64_t G = gridDim.x, lb = xcd_block();
+  const int64_t t0 = v.n_tiles * lb / G, t1 = v.n_tiles * (lb + 1) / G;
+  double dot = 0.0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t nb = v.t_off[t];
+    const int nt = (int)(v.t_off[t + 1] - nb);
+    const int na = v.t_na[t], np = v.t_nb[t];
+    // gather, in rounds of kLeafGB nodes per lane: all node ids, then all
+    // values, then the LDS stores (no load waits on another inside a round)
+    for (int i0 = 0; i0 < nt; i0 += 64 * kLeafGB) {
+      int32_t d[kLeafGB];
+      double xv[kLeafGB];
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        d[k] = i < nt ? v.t_node[nb + i] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        xv[k] = i < nt ? x[d[k] < 0 ? ~d[k] : d[k]] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        if (i < nt) lds[i] = xv[k];
+      }
+    }
+    __syncthreads();
+    const int64_t c = t * 64 + lane;
+    const bool live = c < v.n_cells;
+    double w[NP];
+    {
+      double u[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const uint32_t l = live ? (uint32_t)v.lmap[(int64_t)j * v.n_cells + c] : 0u;
+        u[j] = live ? lds[l] : 0.0;
+      }
+      const uint32_t mk = live ? (uint32_t)v.mask[c] : 0u;
+      if constexpr (N <= 3)
+        leaf_cell<DIM, N, MASS>(Exact1D<N>{}, mk, u, w);
+      else
+        leaf_cell<DIM, N, MASS>(m, mk, u, w);
+      const double sc = live ? (MASS ? v.mscale[c] : v.scale[c]) : 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) w[j] *= sc;
+    }
+    // the local indices again (cached) rather than held in registers through
+    // the operator; not scheduled above this point
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t lm[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) lm[j] = live ? (uint32_t)v.lmap[(int64_t)j * v.n_cells + c] : 0u;
+    __syncthreads();
+    for (int i = lane; i < na + np; i += 64) lds[i] = 0.0;
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) atomicAdd(&lds[lm[j]], w[j]);
+    }
+    __syncthreads();
+    // write-out in rounds as the gather: complete nodes to y (Dirichlet rows
+    // zero), partial ones to the tile's slots
+    double* pslot = E + v.t_pbase[t] - na;
+    for (int i0 = 0; i0 < na + np; i0 += 64 * kLeafGB) {
+      int32_t d[kLeafGB];
+      double q[kLeafGB], xd[kLeafGB];
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        d[k] = i < na ? v.t_node[nb + i] : -1;
+        q[k] = i < na + np ? lds[i] : 0.0;
+      }
+      if (DOT) {
+#pragma unroll
+        for (int k = 0; k < kLeafGB; ++k) xd[k] = d[k] >= 0 ? x[d[k]] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        if (i < na) {
+          if (d[k] < 0) {
+            y[~d[k]] = 0.0;
+          } else {
+            y[d[k]] = q[k];
+            if (DOT) dot += xd[k] * q[k];
+          }
+        } else if (i < na + np) {
+          pslot[i] = q[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (DOT) {
+    for (int o = 32; o > 0; o >>= 1) dot += __shfl_down(dot, o, 64);
+    if (lane == 0) part[blockIdx.x] = dot;
+  }
 }
 
 // In-cell constraints of one node, gathered (3D, used by the cooperative
@@ -944,6 +1337,54 @@ __global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restric
 // consecutive block-strided nodes, unrolled so that their loads issue
 // together; one partial per block, summed in fixed order by cg_scalars)
 constexpr int kFuseNPT = 8;
+
+// tiled leaf operator, pass 2: the nodes summed from slots (partial sums of
+// the tiles touching them and constrained contributions, in ascending slot
+// order), Dirichlet rows zero; DOT: partial sums of p.q per block
+template <bool DOT>
+__global__ void __launch_bounds__(kBlock) leaf_pass2(LeafView v, const double* __restrict__ E,
+                                                     const double* __restrict__ x, double* __restrict__ y,
+                                                     double* __restrict__ part) {
+  // the first kP2S slots of every node unrolled, so that the loads of all
+  // nodes of a thread issue together; longer lists (rare) continue in a loop
+  constexpr int kP2S = 4;
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kFuseNPT + threadIdx.x;
+  int32_t d[kFuseNPT], o0[kFuseNPT], o1[kFuseNPT];
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    const bool in = i < v.n_p2;
+    d[k] = in ? v.p2_dof[i] : -1;
+    o0[k] = in ? v.p2_off[i] : 0;
+    o1[k] = in ? v.p2_off[i + 1] : 0;
+  }
+  int32_t sl[kFuseNPT][kP2S];
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k)
+#pragma unroll
+    for (int j = 0; j < kP2S; ++j) sl[k][j] = o0[k] + j < o1[k] ? v.p2_slot[o0[k] + j] : -1;
+  double q[kFuseNPT];
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    q[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kP2S; ++j) q[k] += sl[k][j] >= 0 ? E[sl[k][j]] : 0.0;
+    for (int32_t o = o0[k] + kP2S; o < o1[k]; ++o) q[k] += E[v.p2_slot[o]];
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    if (d[k] >= 0) {
+      const double qk = v.dir[d[k]] ? 0.0 : q[k];
+      y[d[k]] = qk;
+      if (DOT) s += x[d[k]] * qk;
+    }
+  }
+  if (DOT) {
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
 
 // leaf operator, pass 2, fused with the partial sums of p.q
 __global__ void __launch_bounds__(kBlock) seg_dir_dot(int64_t n, const int32_t* __restrict__ off,

@@ -181,15 +181,37 @@ size_t plan_workspace(Problem& P, char* base) {
   P.ld = pl.take<char>(size_t(off) * esz);
   P.ldinv = pl.take<char>(size_t(off) * esz);
   const int64_t N = M.n_dofs;
+  const LeafTiles& LT = M.tiles;
+  const bool tiled = LT.n_tiles > 0;
+  P.leaf = LeafView{};
   P.leaf.n_cells = M.n_leaves;
   P.leaf.n_dofs = N;
-  P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
   P.leaf.mask = pl.take<uint16_t>(M.n_leaves);
   P.leaf.scale = pl.take<double>(M.n_leaves);
   P.leaf.mscale = pl.take<double>(M.n_leaves);
-  P.leaf.slot = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
-  P.leaf.soff = pl.take<int32_t>(N + 1);
   P.leaf.dir = pl.take<uint8_t>(N);
+  int64_t e_leaf = 0;
+  if (tiled) {
+    P.leaf.n_tiles = LT.n_tiles;
+    P.leaf.n_part = LT.n_part;
+    P.leaf.n_p2 = (int64_t)LT.p2_dof.size();
+    P.leaf.max_nodes = LT.max_nodes;
+    P.leaf.t_off = pl.take<int64_t>(LT.node_off.size());
+    P.leaf.t_na = pl.take<int32_t>(LT.n_tiles);
+    P.leaf.t_nb = pl.take<int32_t>(LT.n_tiles);
+    P.leaf.t_pbase = pl.take<int32_t>(LT.n_tiles);
+    P.leaf.t_node = pl.take<int32_t>(LT.node.size());
+    P.leaf.lmap = pl.take<uint16_t>(LT.lmap.size());
+    P.leaf.p2_dof = pl.take<int32_t>(LT.p2_dof.size());
+    P.leaf.p2_off = pl.take<int32_t>(LT.p2_off.size());
+    P.leaf.p2_slot = pl.take<int32_t>(LT.p2_slot.size());
+    e_leaf = LT.n_part;
+  } else {
+    P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
+    P.leaf.slot = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
+    P.leaf.soff = pl.take<int32_t>(N + 1);
+    e_leaf = M.n_leaves * M.npc;
+  }
   P.n_dir = 0;
   for (auto d : M.dirichlet) P.n_dir += d;
   P.copy = pl.take<int32_t>(N);
@@ -200,7 +222,7 @@ size_t plan_workspace(Problem& P, char* base) {
   P.cq = pl.take<double>(N);
   P.cb = pl.take<double>(N);
   P.e_levels = e_max;
-  e_max = std::max<int64_t>(e_max, M.n_leaves * M.npc);
+  e_max = std::max<int64_t>(e_max, e_leaf);
   if (e_max >= INT32_MAX) fail(GMG_E_INVAL, "operator slots exceed 2^31");
   P.E = pl.take<double>(e_max);
   // restricted parent-cell values of the fine families of one level
@@ -210,7 +232,11 @@ size_t plan_workspace(Problem& P, char* base) {
   P.rbuf = pl.take<char>(size_t(fam_max) * M.npc * esz);
   P.scal = pl.take<double>(dev::kNumScalars + 8);
   // dot partials: the fixed dot grid, or one per block of the fused kernels
-  P.part = pl.take<double>(std::max<int64_t>(dev::kDotBlocks, (N + dev::kBlock - 1) / dev::kBlock));
+  {
+    int64_t np = std::max<int64_t>(dev::kDotBlocks, (N + dev::kBlock - 1) / dev::kBlock);
+    if (tiled) np = std::max<int64_t>(np, std::min<int64_t>(LT.n_tiles, dev::kLeafBlocks) + fuse_grid(P.leaf.n_p2));
+    P.part = pl.take<double>(np);
+  }
   int n0 = 0;
   for (auto f : M.levels[0].flags) n0 += f == kFlagS;
   if (n0 > 6000) fail(GMG_E_INVAL, "coarse level too large for the dense coarse solve (> 6000 free nodes)");
@@ -496,20 +522,36 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     P.leaf.n_con = (int64_t)ord.size();
     for (int64_t c = 0; c < M.n_leaves; ++c)
       if (split && !(M.leaf_mask[c] >> 3)) ord.push_back(c);
-    std::vector<int32_t> cm(M.leaf_cellmap_parent.size());
+    // the tiled operator keeps leaf order (its tiles are runs of it) and
+    // needs no cell map
+    std::vector<int32_t> cm(P.leaf.n_tiles ? 0 : M.leaf_cellmap_parent.size());
     std::vector<uint16_t> mk(M.n_leaves);
     for (int64_t c = 0; c < M.n_leaves; ++c) {
       mk[c] = M.leaf_mask[ord[c]];
-      for (int j = 0; j < M.npc; ++j) cm[size_t(c) * M.npc + j] = M.leaf_cellmap_parent[size_t(ord[c]) * M.npc + j];
+      if (!P.leaf.n_tiles)
+        for (int j = 0; j < M.npc; ++j)
+          cm[size_t(c) * M.npc + j] = M.leaf_cellmap_parent[size_t(ord[c]) * M.npc + j];
     }
-    h2d(P.leaf.cmap, soa(cm, M.n_leaves, M.npc), s);
     h2d(P.leaf.mask, mk, s);
-    {
+    h2d(P.leaf.dir, M.dirichlet, s);
+    if (P.leaf.n_tiles) {
+      const LeafTiles& LT = M.tiles;
+      h2d(P.leaf.t_off, LT.node_off, s);
+      h2d(P.leaf.t_na, LT.n_complete, s);
+      h2d(P.leaf.t_nb, LT.n_partial, s);
+      h2d(P.leaf.t_pbase, LT.pbase, s);
+      h2d(P.leaf.t_node, LT.node, s);
+      h2d(P.leaf.lmap, soa(LT.lmap, M.n_leaves, M.npc), s);
+      h2d(P.leaf.p2_dof, LT.p2_dof, s);
+      h2d(P.leaf.p2_off, LT.p2_off, s);
+      h2d(P.leaf.p2_slot, LT.p2_slot, s);
+      HIPCHECK(hipStreamSynchronize(s));
+    } else {
+      h2d(P.leaf.cmap, soa(cm, M.n_leaves, M.npc), s);
       std::vector<int32_t> off, sl;
       build_slots(cm, M.n_leaves, M.npc, M.n_dofs, off, sl);
       h2d(P.leaf.slot, sl, s);
       h2d(P.leaf.soff, off, s);
-      h2d(P.leaf.dir, M.dirichlet, s);
       HIPCHECK(hipStreamSynchronize(s));
     }
     std::vector<double> sc(M.n_leaves), ms(M.n_leaves);
@@ -568,15 +610,46 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
 // leaf operator q = C^T A C p with Dirichlet rows zero (or the mass matrix):
 // hanging-node constraints applied inside the cells (pass 1), per-DoF sums
 // (pass 2)
-void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s, double* E) {
+// leaf operator with the partial sums of x.y (part non-null, not with mass):
+// returns the number of partials written to part
+static int leaf_op(Problem& P, const double* x, double* y, bool mass, double* part, hipStream_t s, double* E) {
   const int64_t N = P.maps->n_dofs;
   if (!E) E = P.E;
+  if (P.leaf.n_tiles) {
+    const unsigned g1 = P.kt->leaf_t(P.leaf, x, y, E, part, mass, P.m64, s);
+    const int64_t n2 = P.leaf.n_p2;
+    if (n2 == 0 && part) {
+      fill_dev(part + g1, 1, 0.0, s);
+      return (int)g1 + 1;
+    }
+    if (n2 == 0) return (int)g1;
+    const unsigned g2 = fuse_grid(n2);
+    if (part)
+      hipLaunchKernelGGL(dev::leaf_pass2<true>, dim3(g2), dim3(dev::kBlock), 0, s, P.leaf, (const double*)E, x, y,
+                         part + g1);
+    else
+      hipLaunchKernelGGL(dev::leaf_pass2<false>, dim3(g2), dim3(dev::kBlock), 0, s, P.leaf, (const double*)E, x, y,
+                         (double*)nullptr);
+    return (int)(g1 + g2);
+  }
   P.kt->leaf_e(P.leaf, x, E, mass, P.m64, s);
+  if (part) {
+    hipLaunchKernelGGL(dev::seg_dir_dot, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff,
+                       (const double*)E, P.leaf.dir, y, x, part);
+    return (int)fuse_grid(N);
+  }
   hipLaunchKernelGGL(dev::seg_dir, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff, (const double*)E,
                      P.leaf.dir, y);
+  return 0;
 }
 
-int64_t leaf_slots(const Problem& P) { return P.maps->n_leaves * P.maps->npc; }
+void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s, double* E) {
+  leaf_op(P, x, y, mass, nullptr, s, E);
+}
+
+int64_t leaf_slots(const Problem& P) {
+  return P.leaf.n_tiles ? P.maps->tiles.n_part : P.maps->n_leaves * P.maps->npc;
+}
 
 
 struct Cheb {
@@ -908,11 +981,8 @@ static void cg_enqueue_iteration(Problem& P) {
   hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)fuse_grid(N), P.part, sc, 0);
   hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
   // q = A p, with the partial sums of p.q
-  P.kt->leaf_e(P.leaf, P.cp, P.E, false, P.m64, s);
-  hipLaunchKernelGGL(dev::seg_dir_dot, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P.leaf.soff,
-                     (const double*)P.E,
-                     P.leaf.dir, P.cq, (const double*)P.cp, P.part);
-  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)fuse_grid(N), P.part, sc, 1);
+  const int nq = leaf_op(P, P.cp, P.cq, false, P.part, s, nullptr);
+  hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, nq, P.part, sc, 1);
   hipLaunchKernelGGL(dev::update_xr, dim3(dg), dim3(dev::kBlock), 0, s, N, C.u, P.cr, P.cp, P.cq, sc, P.part);
   hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)dg, P.part, sc, 2);
   HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -182,6 +182,8 @@ inline T __shfl_xor(T v, int mask, int w = 64) {
 // data-parallel lane moves used by the kernels (gfx9 DPP controls: quad
 // permutation 0x00-0xFF, row half mirror 0x141), through block scratch:
 // every thread of the block must take part
+// scheduling barrier of the device compiler: nothing to do on the host
+inline void __builtin_amdgcn_sched_barrier(int) {}
 inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool) {
   const unsigned t = threadIdx.x;
   emu::g_shfl[t] = (double)v;

@@ -65,3 +65,29 @@ def test_request_fp64_solve_matches_oracle(r):
     ml = gi.build_request_mesh(spec, lambda d, o: gmg.Mesh(d, o), lambda m, fl: m.refine(fl),
                                lambda m: m.leaves())
     _solve_both(fo, ml, 2, "one", "one", f"request {r}")
+
+
+def test_leaf_operator_bitwise_repeatable():
+    """The leaf operator adds the cells' results of a tile in LDS; its sums
+    must come out bit for bit the same on every application and in every
+    problem instance (the serving loop's mixed-equals-alone guarantee
+    depends on it).  Fichera Q2 with 3 global refinements and 4 adaptive
+    cycles: most leaf cells carry in-cell constraints, whose results several
+    sibling cells add into the same parent nodes."""
+    from paper_1904_03317_amd import gmg
+    w = gi.workload("C2", g=3)
+    m = gmg.build_mesh(w.recipe)
+    P1 = gmg.Problem(m, gmg.options(degree=2, mg_precision=64)).bind()
+    P2 = gmg.Problem(m, gmg.options(degree=2, mg_precision=64)).bind()
+    n = P1.n_dofs
+    print(f"[gpu] leaf repeatability: N={n}", flush=True)
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(n), device="cuda")
+    ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+    P1.apply_leaf(x, ref)
+    y = torch.zeros_like(ref)
+    for k in range(20):
+        (P1 if k % 2 == 0 else P2).apply_leaf(x, y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), k
+    P1.close()
+    P2.close()

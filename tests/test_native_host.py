@@ -45,6 +45,23 @@ def test_workload_maps_bit_exact(name, g):
     compare_maps(P, discretize(f, w.degree))
 
 
+# The tiled leaf operator sums its cells' results in LDS position by
+# position and relies on this: at one local position, no two leaf cells of a
+# 2:1-balanced mesh share a node (two cells with a common node at the same
+# local position would overlap), so the adds of one step never collide and
+# their order is fixed.  Checked on the leaf maps (the non-hanging entries).
+@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C2", 3)])
+def test_leaf_nodes_distinct_per_local_position(name, g):
+    w = gi.workload(name, g=g)
+    m, P, _ = library_problem(w.recipe, w.degree)
+    npc = (w.degree + 1) ** m.dim
+    cm = P.array("LEAF_CELLMAP").reshape(-1, npc)
+    for j in range(npc):
+        col = cm[:, j]
+        col = col[col >= 0]
+        assert len(np.unique(col)) == len(col), j
+
+
 def test_closure_matches_oracle_random_flags():
     rng = np.random.default_rng(11)
     origins = gi.coarse_mesh("fichera")[1]
