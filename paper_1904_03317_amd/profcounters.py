@@ -3,7 +3,9 @@ averaged per dispatch for each (kernel, grid size), with the derived rates:
 
   VALU busy      = SQ_ACTIVE_INST_VALU / (CUs * GRBM_GUI_ACTIVE), GRBM_GUI_ACTIVE
                    the largest of its per-XCD instances
-  FP32/FP64 rate = SQ_INSTS_VALU_FLOPS_FP32/64 / kernel duration
+  FP32/FP64 rate = 64 SQ_INSTS_VALU_FLOPS_FP32/64 / kernel duration (the
+                   counters add 2 per FMA wave-instruction, 1 per add or
+                   multiply: times 64 lanes)
   occupancy      = SQ_WAVE_CYCLES / (CUs * GRBM_GUI_ACTIVE) waves per CU
                    (SQ_WAVE_CYCLES counts in quad-cycles: times 4)
   LDS bank conflict = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - conflicts)
@@ -94,7 +96,7 @@ def derive(recs, cus):
         for p in ("32", "64"):
             k = f"SQ_INSTS_VALU_FLOPS_FP{p}"
             if k in avg:
-                d[f"fp{p}_tflops"] = avg[k] / (dur * 1e-9) / 1e12
+                d[f"fp{p}_tflops"] = 64.0 * avg[k] / (dur * 1e-9) / 1e12
     wc = avg.get("SQ_WAVE_CYCLES", 0.0)
     if wc:
         for k, lab in (("SQ_WAIT_ANY", "wait_any_pct"), ("SQ_WAIT_INST_ANY", "wait_issue_pct"),
