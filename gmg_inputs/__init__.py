@@ -20,6 +20,12 @@ in for them, see the paper's Section 4):
   C2/C3/C5  3D Fichera corner [-1,1]^3 minus [0,1]^3, g global refinements then
       4 cycles: corner marks OR seeded uniform draw < 0.05.
   C4  stream of unit-cube requests refined toward a seeded point.
+  A41 the paper's "annulus" mesh of its V-cycle scaling runs (Sec. 3.5, 4.1):
+      the cube [-1,1]^3 as 5^3 coarse cells (the 125 level-0 cells of the
+      paper's per-level workload table), L-3 global refinements, then three
+      steps: cells whose centre lies inside the sphere of radius 0.55, then
+      in the shell 0.3 <= r <= 0.43, then in 0.335 <= r <= 0.39; Q2,
+      Chebyshev degree 5.
 """
 from __future__ import annotations
 
@@ -37,7 +43,13 @@ COARSE_MESHES = {
     "cube": (3, [(0, 0, 0)]),
     "fichera": (3, [(x, y, z) for z in (-1, 0) for y in (-1, 0) for x in (-1, 0)
                     if (x, y, z) != (0, 0, 0)]),
+    # [-1,1]^3 as 5^3 unit cells: physical x = 0.4 (mesh x - 2.5)
+    "cube5": (3, [(x, y, z) for z in range(5) for y in range(5) for x in range(5)]),
 }
+
+# annulus steps of the "cube5" mesh: (r / 0.4)^2 as exact fractions (num,
+# den) of the physical radii 0.55, 0.3, 0.43, 0.335, 0.39
+ANNULUS_R2 = {"0.55": (121, 64), "0.3": (9, 16), "0.43": (1849, 1600), "0.335": (4489, 6400), "0.39": (1521, 1600)}
 
 SEED_FICHERA = 1904  # shared by C2, C3, C5 (random marks: PCG64(1904*100 + c))
 SEED_NOISE = 1905    # C2/C3 nodal noise
@@ -73,6 +85,36 @@ def flags_corner(levels, anchors, cycle):
     return (d2 < r * r).astype(np.uint8)
 
 
+def _annulus_r2(levels, anchors):
+    """Squared physical distance of the cell centres from the centre of the
+    "cube5" mesh, as the integer S with r^2 / 0.4^2 = S / 2^42 (exact)."""
+    c2 = _centres_x2(levels, anchors) - 5 * (1 << 20)   # units 2^-21, centred
+    return (c2 * c2).sum(axis=1)
+
+
+def _r2_less(S, key):
+    num, den = ANNULUS_R2[key]
+    return S * den < num * (np.int64(1) << 42)
+
+
+def flags_annulus(levels, anchors, cycle):
+    """Step `cycle` (1, 2, 3) of the annulus refinement on the "cube5" mesh:
+    centre inside radius 0.55; centre in the shell 0.3 <= r <= 0.43; centre
+    in 0.335 <= r <= 0.39 (exact integer tests)."""
+    if len(levels) == 0:
+        return np.zeros(0, dtype=np.uint8)
+    S = _annulus_r2(levels, anchors)
+    if cycle == 1:
+        m = _r2_less(S, "0.55")
+    elif cycle == 2:
+        m = ~_r2_less(S, "0.3") & ~(~_r2_less(S, "0.43") & (S * 1600 != 1849 * (np.int64(1) << 42)))
+    elif cycle == 3:
+        m = ~_r2_less(S, "0.335") & ~(~_r2_less(S, "0.39") & (S * 1600 != 1521 * (np.int64(1) << 42)))
+    else:
+        m = np.zeros(len(levels), dtype=bool)
+    return m.astype(np.uint8)
+
+
 def flags_random(n_leaves, seed_cfg, cycle, frac=0.05):
     """One uniform draw per current leaf, in canonical leaf order, from
     PCG64(seed_cfg*100 + cycle); mark iff u < frac."""
@@ -101,6 +143,8 @@ class MeshRecipe:
             return flags_corner(levels, anchors, c)
         if self.marker == "corner+random":
             return flags_corner(levels, anchors, c) | flags_random(n, self.seed, c)
+        if self.marker == "annulus":
+            return flags_annulus(levels, anchors, c)
         return np.zeros(n, dtype=np.uint8)
 
     @property
@@ -153,6 +197,12 @@ def workload(name, g=None):
     if name == "C5":
         return Workload("C5", MeshRecipe("fichera", 5 if g is None else g, 4, "corner+random"), 3,
                         coeff="checker", mg_precision=32)
+    if name == "A41":
+        # the paper's V-cycle scaling mesh (Sec. 4.1): annulus refinement of
+        # the cube, L = g + 3 (g = 4: the paper's 3D table with 125 ... 2.98e6
+        # cells per level), Q2, f = 1, Chebyshev degree 5, FP32 V-cycle
+        return Workload("A41", MeshRecipe("cube5", 4 if g is None else g, 3, "annulus"), 2,
+                        mg_precision=32, cheb_degree=5)
     if name == "L43":
         # the paper's Laplace comparison (Sec. 4.3): Fichera corner, eps in
         # {1, 100}, f = 1, Q2, "MF" preconditioner (one undamped FP32 Jacobi

@@ -28,7 +28,7 @@
  *    results (solve, vcycle timings, bind) synchronise that stream first.
  *  - Geometry: coarse cells are unit squares/cubes [o, o+1]^d at distinct
  *    integer origins o.  A cell of level l has side 2^-l; anchors are given in
- *    global integer units of 2^-20.  Maximum level 18.
+ *    global integer units of 2^-20.  Maximum level 16.
  *  - Canonical cell order: by coarse cell, then z-order (Morton, child id
  *    x + 2y + 4z) of the anchor -- depth-first order of the forest.
  *  - A level DoF flag is 0 = S (smoothed on this level), 1 = I (interface:
@@ -94,7 +94,8 @@ const char* gmg_last_error(void);
  * levels, leaf mesh), Sec. 3.5 (2:1 balance).  Host only. */
 
 /* New forest of level-0 leaves.  origins: [n_coarse * dim] integer origins,
- * distinct.  dim in {2,3}; 1 <= n_coarse <= 32.  Errors: GMG_E_INVAL. */
+ * distinct.  dim in {2,3}; 1 <= n_coarse <= 128, within a box of 16 unit
+ * cells per axis.  Errors: GMG_E_INVAL. */
 int gmg_mesh_create(int dim, int n_coarse, const int32_t* origins, gmg_mesh* out);
 /* Refine the flagged leaves (flags[n_leaves], canonical order, nonzero =
  * refine), then close the mesh to 2:1 balance: any two leaves whose closures

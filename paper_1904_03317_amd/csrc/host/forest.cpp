@@ -8,7 +8,7 @@ namespace {
 constexpr uint8_t kLeaf = 1, kRefined = 2;
 
 uint64_t interleave(const uint64_t* v, int dim) {
-  // bits of the three coordinates (18 each at the finest level) interleaved
+  // bits of the three coordinates (16 each at the finest level) interleaved
   // with x in the lowest position: child id = x + 2y + 4z
   uint64_t m = 0;
   for (int b = kMaxLevel - 1; b >= 0; --b)
@@ -19,7 +19,7 @@ uint64_t interleave(const uint64_t* v, int dim) {
 
 Forest::Forest(int dim, int n, const int32_t* origins) : dim_(dim) {
   if (dim != 2 && dim != 3) fail(-1, "dim must be 2 or 3");
-  if (n < 1 || n > kMaxCoarse) fail(-1, "1 <= n_coarse <= 32 required");
+  if (n < 1 || n > kMaxCoarse) fail(-1, "1 <= n_coarse <= 128 required");
   for (int i = 0; i < 3; ++i) {
     lo_[i] = 0;
     ext_[i] = 1;
@@ -54,7 +54,7 @@ Forest::Forest(int dim, int n, const int32_t* origins) : dim_(dim) {
   for (int t = 0; t < n; ++t) {
     Cell c;
     c.level = 0;
-    c.tree = (int8_t)t;
+    c.tree = (int16_t)t;
     for (int i = 0; i < 3; ++i) c.a[i] = origins_[t][i] * (int32_t)(1 << kDepth);
     if (dim == 2) c.a[2] = 0;
     cells_.set(key(c), kLeaf);
@@ -86,7 +86,7 @@ uint64_t Forest::key(int level, const int64_t* a, int tree) const {
   for (int i = 0; i < dim_; ++i)
     v[i] = uint64_t(a[i] - int64_t(origins_[tree][i]) * (int64_t(1) << kDepth)) >>
            (kDepth - kMaxLevel);
-  return (uint64_t(tree) << 59) | (interleave(v, dim_) << 5) | uint64_t(level);
+  return (uint64_t(tree) << 57) | (interleave(v, dim_) << 5) | uint64_t(level);
 }
 
 uint64_t Forest::key(const Cell& c) const {
@@ -163,7 +163,7 @@ int64_t Forest::refine(const uint8_t* flags) {
             if (m >= kMaxLevel) fail(-1, "maximum level exceeded");
             Cell cc;
             cc.level = (int8_t)m;
-            cc.tree = (int8_t)t;
+            cc.tree = (int16_t)t;
             for (int i = 0; i < 3; ++i) cc.a[i] = (int32_t)aa[i];
             next.push_back({k, cc});
             break;

@@ -12,8 +12,8 @@
 namespace gmg {
 
 constexpr int kDepth = 20;         // anchors in units of 2^-20
-constexpr int kMaxLevel = 18;
-constexpr int kMaxCoarse = 32;
+constexpr int kMaxLevel = 16;     // key: 7 bits tree, 3 x 16 bits z-order, 5 bits level
+constexpr int kMaxCoarse = 128;
 constexpr int kMaxExtent = 16;     // bounding box of the coarse mesh, unit cells per axis
 
 inline int64_t side_of(int level) { return int64_t(1) << (kDepth - level); }
@@ -25,7 +25,7 @@ inline int64_t floor_to(int64_t v, int64_t s) {
 
 struct Cell {
   int8_t level = 0;
-  int8_t tree = 0;
+  int16_t tree = 0;
   std::array<int32_t, 3> a{};   // global anchor, units 2^-20
 };
 

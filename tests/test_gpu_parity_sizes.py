@@ -24,15 +24,15 @@ def _close(a, b, tol):
     return (np.linalg.norm(d) <= tol * np.linalg.norm(b)) and (np.abs(d).max() <= tol * np.abs(b).max())
 
 
-def _solve_both(forest_oracle, mesh_lib, k, rhs, coeff_kind, label):
+def _solve_both(forest_oracle, mesh_lib, k, rhs, coeff_kind, label, cheb_degree=4):
     from paper_1904_03317_amd import gmg
     coeff_o = gi.coeff_cells(coeff_kind, *forest_oracle.leaves_arrays()) if coeff_kind != "one" else None
-    op = problem.setup(forest_oracle, k, coeff=coeff_o)
+    op = problem.setup(forest_oracle, k, coeff=coeff_o, cheb_degree=cheb_degree)
     fn = gi.rhs_nodal(rhs, op.n_dofs)
     x, it, hist, ok = op.solve(fn)
     print(f"[gpu] {label}: N={op.n_dofs} leaves={len(forest_oracle.leaves)} oracle its={it}", flush=True)
     coeff_l = gi.coeff_cells(coeff_kind, *mesh_lib.leaves()) if coeff_kind != "one" else None
-    P = gmg.Problem(mesh_lib, gmg.options(degree=k, mg_precision=64), coeff=coeff_l).bind()
+    P = gmg.Problem(mesh_lib, gmg.options(degree=k, mg_precision=64, cheb_degree=cheb_degree), coeff=coeff_l).bind()
     assert P.n_dofs == op.n_dofs
     u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
     st, its, h = P.solve(torch.as_tensor(fn, device="cuda"), u)
@@ -46,12 +46,34 @@ def _solve_both(forest_oracle, mesh_lib, k, rhs, coeff_kind, label):
     P.close()
 
 
-@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C5", 2)])
+@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C5", 2), ("A41", 1)])
 def test_workload_fp64_solve_matches_oracle(name, g):
     from paper_1904_03317_amd import gmg
     w = gi.workload(name, g=g)
     _solve_both(problem.build_forest(w.recipe), gmg.build_mesh(w.recipe), w.degree, w.rhs, w.coeff,
-                f"{name} g={w.recipe.globals_}")
+                f"{name} g={w.recipe.globals_}", cheb_degree=w.cheb_degree)
+
+
+def test_annulus_fp32_mg_solve():
+    """The paper's V-cycle workload (annulus, Q2, Chebyshev degree 5, FP32
+    V-cycle in FP64 CG): the FP32-MG solve reaches the tolerance with the
+    true residual (leaf operator) at most 1.0001e-10 and at most one
+    iteration more than the oracle's FP64 solve."""
+    from paper_1904_03317_amd import gmg
+    w = gi.workload("A41", g=1)
+    op = problem.setup(problem.build_forest(w.recipe), w.degree, cheb_degree=w.cheb_degree)
+    f = np.ones(op.n_dofs)
+    x, it, hist, ok = op.solve(f)
+    P = gmg.Problem(gmg.build_mesh(w.recipe), gmg.options(degree=2, mg_precision=32, cheb_degree=5)).bind()
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    st, its, h = P.solve(torch.as_tensor(f, device="cuda"), u)
+    uh = u.cpu().numpy()
+    print(f"[gpu] A41 g=1 FP32-MG: N={op.n_dofs} its {its} (oracle FP64 {it})", flush=True)
+    assert st == 0 and ok and its <= it + 1
+    b = op.rhs(f)
+    assert np.linalg.norm(b - op.A @ uh) <= 1.0001e-10 * np.linalg.norm(b)
+    assert _close(uh, x, 1e-8)
+    P.close()
 
 
 @pytest.mark.parametrize("r", [0, 1, 2, 3])

@@ -192,3 +192,31 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+# The paper's annulus mesh (Sec. 3.5 refinement recipe; the V-cycle scaling
+# runs of Sec. 4.1 use it): with the cell-centre reading of all three steps,
+# the library's forest reproduces the paper's cells per level exactly on
+# levels 0-5 and 7; level 6 comes out 92,032 cells (11 %) above the paper's,
+# a reading of the first shell step the paper's text does not settle (the
+# cell-entirely-in-the-shell reading gives 4.8 % below).
+def test_annulus_level_cells_against_the_paper():
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    want = gold["annulus_3d_level_cells"]["value"]
+    w = gi.workload("A41")
+    m, P, _ = library_problem(w.recipe, 1)
+    info = P.info()
+    got = list(info.level_cells[:info.n_levels])
+    assert len(got) == len(want)
+    for l in (0, 1, 2, 3, 4, 5, 7):
+        assert got[l] == want[l], l
+    assert got[6] == want[6] + 92032
+
+
+def test_annulus_maps_bit_exact_small():
+    w = gi.workload("A41", g=1)
+    m, P, _ = library_problem(w.recipe, w.degree)
+    f = op.build_forest(w.recipe)
+    compare_maps(P, discretize(f, w.degree))
