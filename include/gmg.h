@@ -220,6 +220,24 @@ int gmg_apply_level(gmg_problem p, int level, int variant, const void* d_in, voi
                     hipStream_t stream);
 int gmg_vcycle(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream);
 
+/* One V-cycle z_i = B_i r_i (as gmg_vcycle) for each of n bound problems of
+ * the same dimension, degree, precision and smoother (several resident
+ * solves, Sec. 2.3 local smoothing per problem), with the level sweeps of
+ * all of them in one launch each: every smoothing step, residual pass and
+ * second restriction pass on level l is one launch over the level-l
+ * families of all problems that have a level l (levels aligned from the
+ * coarse end); transfers, copies and coarse solves run per problem on the
+ * same stream.  Each z_i equals gmg_vcycle's bit for bit.
+ * ps: [n] problems (host array); d_r, d_z: [n] device pointers (host
+ * arrays), each [n_dofs of its problem].  d_table: device memory the
+ * library writes the launch tables to (256-byte aligned, caller-owned);
+ * *table_bytes: its size on entry; on return the size needed.  With d_table
+ * NULL only the size is returned and nothing is enqueued.  Synchronises the
+ * stream before returning.  Errors: GMG_E_INVAL (mixed problems, table too
+ * small), GMG_E_STATE (a problem not bound), GMG_E_HIP. */
+int gmg_vcycle_batch(const gmg_problem* ps, int n, const double* const* d_r, double* const* d_z, void* d_table,
+                     size_t* table_bytes, hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * V-cycle as gmg_vcycle, with its work memory (level vectors x, g, t, d,
@@ -248,10 +266,15 @@ int gmg_problem_last_timing(gmg_problem p, double* out3);
  * scheduler thread admits ready requests in arrival order whenever a slot
  * and enough arena memory are free (first fit), sets them up on the device
  * on the slot's stream and then advances every resident solve one CG
- * iteration per tick, each on its own stream with its V-cycle replayed as a
- * captured HIP graph.  A finished request frees its slot and memory for the
- * next one.  Results do not depend on the other resident requests (all
- * kernels are deterministic). */
+ * iteration per tick.  The V-cycles of the requests due in a tick that share
+ * dimension, degree, precision, Chebyshev degree and smoother run as one
+ * batched V-cycle (as gmg_vcycle_batch: one launch per level sweep for all
+ * of them) on a batch stream; the rest of each iteration runs on the
+ * request's own stream.  A request alone in its group replays its V-cycle
+ * as a captured HIP graph.  A finished request frees its slot and memory for
+ * the next one.  Results do not depend on the other resident requests (all
+ * kernels are deterministic and a batched V-cycle equals the request's own
+ * bit for bit). */
 
 typedef struct {       /* seconds on the server clock (0 = gmg_server_create) */
   double arrival;      /* submit */
@@ -266,6 +289,9 @@ typedef struct {
   size_t arena_used, arena_peak, arena_bytes;
   double dofs_done;    /* sum of DoFs of completed requests */
   double clock;        /* server clock now */
+  int64_t iterations;  /* CG iterations enqueued */
+  int64_t batched_iterations;  /* of which with a batched V-cycle */
+  int64_t batches;     /* batched V-cycles */
 } gmg_server_stats_t;
 
 enum { GMG_REQ_QUEUED = 0, GMG_REQ_SETUP = 1, GMG_REQ_READY = 2, GMG_REQ_BINDING = 3, GMG_REQ_RUNNING = 4,
@@ -276,7 +302,9 @@ enum { GMG_REQ_QUEUED = 0, GMG_REQ_SETUP = 1, GMG_REQ_READY = 2, GMG_REQ_BINDING
 #define GMG_RHS_LATER ((int64_t)-1)
 
 /* d_arena: device memory owned by the caller (256-byte aligned) that holds
- * the workspaces of resident requests; arena_bytes is the HBM budget.
+ * the workspaces of resident requests and, at its front, the launch tables
+ * of the batched V-cycles (1/32 of it, at most 16 MiB; none, and so no
+ * batching, below 2 MiB); arena_bytes is the HBM budget.
  * max_slots: resident requests at most (1..64); host_threads: workers for
  * host set-up and device binding (1..64).  Uses the current device. */
 int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int32_t host_threads,
@@ -313,6 +341,13 @@ int gmg_server_result(gmg_server s, uint64_t request_id, double* u_host, int64_t
 /* Forget a finished request. */
 int gmg_server_release(gmg_server s, uint64_t request_id);
 int gmg_server_stats(gmg_server s, gmg_server_stats_t* out);
+/* Batched V-cycles on (enable = 1, the default) or off (every request
+ * replays its own V-cycle graph); results are the same either way. */
+int gmg_server_set_batching(gmg_server s, int enable);
+/* hold = 1: resident solves are not advanced (admission and set-up go on),
+ * so that requests arriving in a burst start their iterations together, or
+ * to quiesce the device; hold = 0 resumes. */
+int gmg_server_hold(gmg_server s, int hold);
 /* Stops the threads after the current tick; resident solves are abandoned. */
 int gmg_server_destroy(gmg_server s);
 

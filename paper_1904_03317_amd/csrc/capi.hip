@@ -321,6 +321,30 @@ int gmg_vcycle(gmg_problem p, const double* r, double* z, hipStream_t s) {
   });
 }
 
+int gmg_vcycle_batch(const gmg_problem* ps, int n, const double* const* r, double* const* z, void* table,
+                     size_t* table_bytes, hipStream_t s) {
+  return guard([&] {
+    REQUIRE(ps && n >= 1 && table_bytes, "null argument");
+    std::vector<gmg::Problem*> pv(n);
+    for (int i = 0; i < n; ++i) {
+      REQUIRE(ps[i], "null problem");
+      pv[i] = &ps[i]->P;
+    }
+    if (table) {
+      REQUIRE(r && z, "null argument");
+      for (int i = 0; i < n; ++i) REQUIRE(r[i] && z[i], "null vector");
+    }
+    size_t need = 0;
+    gmg::vcycle_batch(pv, r, z, (char*)table, *table_bytes, &need, nullptr, s, false);
+    *table_bytes = need;
+    if (table) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) gmg::fail(GMG_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    return 0;
+  });
+}
+
 int gmg_vcycle_noalloc(gmg_problem p, const double* r, double* z, hipStream_t s) {
   return guard([&] {
     REQUIRE(p && r && z, "null argument");

@@ -74,6 +74,10 @@ struct MatsH {
 namespace dev {
 template <typename T>
 struct Epi;
+template <typename T>
+struct OpItem;
+template <typename T>
+struct SumItem;
 }
 
 template <typename T>
@@ -96,6 +100,12 @@ struct LevelOps {
                   hipStream_t);
   // level 0, pass 1 of the operator: cell results into the node-major slots
   void (*cell_e)(const LevelView&, const T* x, T* E, const MatsH<T>&, hipStream_t);
+  // pass 1 and pass 2 of several levels in one launch (device item tables,
+  // b0 set from op_blocks / sum_blocks); op_batch is null where pass 1 has
+  // no batched form (3D at k >= 3)
+  void (*op_batch)(const dev::OpItem<T>* items, int n, int64_t blocks, int epi, const MatsH<T>&, hipStream_t);
+  void (*sum_batch)(const dev::SumItem<T>* items, int n, int64_t blocks, int epi, hipStream_t);
+  int64_t (*op_blocks)(const LevelView&);   // pass-1 blocks of a level
 };
 
 struct KernelTable {

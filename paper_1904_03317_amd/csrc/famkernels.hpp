@@ -504,9 +504,10 @@ __device__ __forceinline__ void gather_patch(int64_t f0, int nf, const T* __rest
   }
 }
 
+// pass 1 for the families of logical block blk
 template <int DIM, int K, typename T, int EPI>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelView v, const T* __restrict__ xin,
-                                                                          Epi<T> ep, T* __restrict__ E, Mats<T> m) {
+__device__ __forceinline__ void fam_op_body(const LevelView& v, const T* __restrict__ xin, const Epi<T>& ep,
+                                            T* __restrict__ E, const Mats<T>& m, int64_t blk) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP;
@@ -518,7 +519,7 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
   __shared__ int64_t bo[NB];
-  const int64_t f0 = xcd_block() * FB;
+  const int64_t f0 = blk * FB;
   const int nf = (int)(v.n_fam - f0 < FB ? v.n_fam - f0 : FB);
   const int tid = threadIdx.x;
   // interior epilogue operands: contiguous, known before anything else
@@ -571,6 +572,46 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelVi
   }
   __syncthreads();
   patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
+}
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op(LevelView v, const T* __restrict__ xin,
+                                                                          Epi<T> ep, T* __restrict__ E, Mats<T> m) {
+  fam_op_body<DIM, K, T, EPI>(v, xin, ep, E, m, xcd_block());
+}
+
+// Several levels (of several problems) in one launch: item i covers the
+// blocks [b0_i, b0_{i+1}) of the grid, each item a level with its input,
+// epilogue and slots.  A level's families get the same logical blocks as in
+// a launch of their own, so every result is the same bit for bit.
+template <typename T>
+struct OpItem {
+  LevelView v;
+  Epi<T> ep;
+  const T* x;
+  T* E;
+  int64_t b0;
+};
+
+// the item of this block (items in ascending b0, the first at 0)
+template <typename Item>
+__device__ __forceinline__ int batch_item(const Item* items, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (items[mid].b0 <= (int64_t)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op_batch(const OpItem<T>* __restrict__ items,
+                                                                                int n, Mats<T> m) {
+  const OpItem<T> it = items[batch_item(items, n)];
+  fam_op_body<DIM, K, T, EPI>(it.v, it.x, it.ep, it.E, m, (int64_t)blockIdx.x - it.b0);
 }
 
 // Pass 1 in 3D at k >= 3 (same contract as fam_op).  Per cell, with the
@@ -742,8 +783,8 @@ __device__ __forceinline__ T sum_slots(const LevelView& v, const T* __restrict__
 }
 
 template <int DIM, int K, typename T, int EPI>
-__global__ void __launch_bounds__(kBlock) fam_sum(LevelView v, const T* __restrict__ E, Epi<T> ep) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fam_sum_body(const LevelView& v, const T* __restrict__ E, const Epi<T>& ep,
+                                             int64_t t) {
   if (t >= v.shn[DIM + 1]) return;
   T s;
   int64_t i;
@@ -758,6 +799,25 @@ __global__ void __launch_bounds__(kBlock) fam_sum(LevelView v, const T* __restri
     s = sum_slots<DIM, K, DIM == 3 ? 3 : 2, T>(v, E, i);
   }
   epi_shared<T, EPI>(ep, i, s);
+}
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__(kBlock) fam_sum(LevelView v, const T* __restrict__ E, Epi<T> ep) {
+  fam_sum_body<DIM, K, T, EPI>(v, E, ep, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T>
+struct SumItem {
+  LevelView v;
+  Epi<T> ep;
+  const T* E;
+  int64_t b0;
+};
+
+template <int DIM, int K, typename T, int EPI>
+__global__ void __launch_bounds__(kBlock) fam_sum_batch(const SumItem<T>* __restrict__ items, int n) {
+  const SumItem<T> it = items[batch_item(items, n)];
+  fam_sum_body<DIM, K, T, EPI>(it.v, it.E, it.ep, ((int64_t)blockIdx.x - it.b0) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ transfers

@@ -205,8 +205,68 @@ struct Inst {
   }
 
   template <typename T>
+  static void op_batch(const dev::OpItem<T>* items, int n, int64_t blocks, int epi, const MatsH<T>& m,
+                       hipStream_t s) {
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      fail(GMG_E_STATE, "no batched level operator at this degree");
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      if (blocks <= 0) return;
+      const dim3 g((unsigned)blocks), b(S::THREADS);
+      switch (epi) {
+        case dev::kEpiPlain:
+          hipLaunchKernelGGL((dev::fam_op_batch<DIM, K, T, dev::kEpiPlain>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        case dev::kEpiCheb:
+          hipLaunchKernelGGL((dev::fam_op_batch<DIM, K, T, dev::kEpiCheb>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        case dev::kEpiResid:
+          hipLaunchKernelGGL((dev::fam_op_batch<DIM, K, T, dev::kEpiResid>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        default:
+          break;
+      }
+      fail(GMG_E_INVAL, "unsupported batched operator epilogue");
+    }
+  }
+  template <typename T>
+  static void sum_batch(const dev::SumItem<T>* items, int n, int64_t blocks, int epi, hipStream_t s) {
+    if (blocks <= 0) return;
+    const dim3 g((unsigned)blocks), b(dev::kBlock);
+    switch (epi) {
+      case dev::kEpiPlain:
+        hipLaunchKernelGGL((dev::fam_sum_batch<DIM, K, T, dev::kEpiPlain>), g, b, 0, s, items, n);
+        return;
+      case dev::kEpiCheb:
+        hipLaunchKernelGGL((dev::fam_sum_batch<DIM, K, T, dev::kEpiCheb>), g, b, 0, s, items, n);
+        return;
+      case dev::kEpiResid:
+        hipLaunchKernelGGL((dev::fam_sum_batch<DIM, K, T, dev::kEpiResid>), g, b, 0, s, items, n);
+        return;
+      case dev::kEpiRStart:
+        hipLaunchKernelGGL((dev::fam_sum_batch<DIM, K, T, dev::kEpiRStart>), g, b, 0, s, items, n);
+        return;
+      default:
+        break;
+    }
+    fail(GMG_E_INVAL, "unsupported batched epilogue");
+  }
+  template <typename T>
+  static int64_t op_blocks(const LevelView& v) {
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      using S = dev::CoopShape<DIM, K, T>;
+      return (v.n_fam + S::FB - 1) / S::FB;
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      return (v.n_fam + S::FB - 1) / S::FB;
+    }
+  }
+
+  template <typename T>
   static constexpr LevelOps<T> ops() {
-    return LevelOps<T>{&op<T>, &sum<T>, &restrict_fc<T>, &restrict0<T>, &prolong<T>, &cell_e<T>};
+    return LevelOps<T>{&op<T>,        &sum<T>,   &restrict_fc<T>,
+                       &restrict0<T>, &prolong<T>, &cell_e<T>,
+                       dev::kCoopOp<DIM, K> ? nullptr : &op_batch<T>, &sum_batch<T>, &op_blocks<T>};
   }
   static const KernelTable* table() {
     static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &leaf_t, &diag0};

@@ -90,9 +90,24 @@ void vcycle(Problem& P, const double* r, double* z, hipStream_t s);
 // V-cycle with its work memory in the library's fixed device scratch array
 // (no allocation); GMG_E_INVAL when the problem needs more than it holds
 void vcycle_noalloc(Problem& P, const double* r, double* z, hipStream_t s);
+// one V-cycle for each problem of a batch (same dimension, degree, precision,
+// smoother), the level sweeps of all of them batched; d_table (device,
+// 256-byte aligned, table_bytes) receives the launch tables, *need their
+// size; with d_table null only *need is computed; h_stage: optional pinned
+// host staging buffer of at least *need bytes; dot_rz: the partial sums of
+// r.z into each problem's dot partials (CG)
+void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, double* const* z, char* d_table,
+                  size_t table_bytes, size_t* need, char* h_stage, hipStream_t s, bool dot_rz,
+                  hipEvent_t staged = nullptr);
 int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s);
 void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed);
 bool cg_poll(Problem& P, bool block);
+// the state machine split for callers that enqueue the preconditioner
+// themselves (batched): cg_check returns 0 (busy), 1 (finished) or 2 (next
+// iteration due); cg_enqueue_tail enqueues the iteration after z = B r
+int cg_check(Problem& P, bool block);
+void cg_enqueue_tail(Problem& P, hipStream_t s);
+void cg_enqueue_iteration(Problem& P);  // preconditioner and tail on the CG stream
 void set_constant(double* p, int64_t n, double v, hipStream_t s);
 void apply_level_hook(Problem& P, int level, int variant, const void* x, void* y, hipStream_t s);
 

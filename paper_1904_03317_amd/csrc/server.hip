@@ -3,9 +3,15 @@
 // it arrives; the scheduler thread admits ready requests whenever a slot and
 // enough arena memory are free (first fit), binds them (upload and device
 // set-up on the slot's stream), and then advances every resident solve by
-// one CG iteration per tick, each on its own stream with its V-cycle replayed
-// as a captured HIP graph, so the work of different requests overlaps on the
-// device.  Requests leave when their residual reaches the tolerance and
+// one CG iteration per tick.  The V-cycles of the requests whose next
+// iteration is due in a tick, grouped by dimension, degree, precision and
+// smoother, run as one batched V-cycle on the batch stream: each smoothing
+// step, residual and restriction pass of a level is one launch over that
+// level of all of them, so that a tick of K small requests costs the launches
+// of one V-cycle and fills the device with the blocks of all K; the rest of
+// each CG iteration follows on the request's own slot stream.  A request
+// alone in its group (or with batching off) replays its V-cycle as a
+// captured HIP graph on its slot stream.  Requests leave when their residual reaches the tolerance and
 // their memory and slot go to the next ones (continuous batching at CG
 // iteration granularity).  All kernels are deterministic, so a result does
 // not depend on what else was resident.  A finished solution is copied back
@@ -24,6 +30,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gmg.h"
@@ -125,6 +132,19 @@ struct Server {
   int max_slots = 1;
   int device = 0;
   std::vector<hipStream_t> streams;
+  // batched V-cycles: launch tables at the front of the arena (table_bytes,
+  // 0 = batching unavailable), uploaded through two pinned staging buffers
+  // in turn, each reusable once its event (recorded after the upload) is done
+  bool batching = true;
+  std::atomic<bool> hold{false};  // resident solves not advanced while set
+  hipStream_t bstream = nullptr;
+  char* d_table = nullptr;
+  size_t table_bytes = 0;
+  char* h_stage[2] = {nullptr, nullptr};
+  hipEvent_t ev_stage[2] = {nullptr, nullptr};
+  hipEvent_t ev_batch = nullptr;
+  int stage_next = 0;
+  int64_t iterations = 0, batched_iterations = 0, batches = 0;
   std::vector<int> slot_free;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -283,6 +303,58 @@ void worker_loop(Server* S) {
   }
 }
 
+// The next CG iteration of each request of `due` (all of one group), its
+// V-cycle batched; requests whose iteration could not be enqueued are added
+// to `failed` with their error.
+void enqueue_batch(Server& S, const std::vector<Request*>& due,
+                   std::vector<std::tuple<Request*, int, std::string>>& failed) {
+  std::vector<Problem*> ps;
+  std::vector<const double*> rs;
+  std::vector<double*> zs;
+  for (Request* r : due) {
+    ps.push_back(r->P.get());
+    rs.push_back(r->P->cr);
+    zs.push_back(r->P->cz);
+  }
+  const int k = S.stage_next;
+  S.stage_next ^= 1;
+  size_t need = 0;
+  try {
+    vcycle_batch(ps, rs.data(), zs.data(), nullptr, 0, &need, nullptr, S.bstream, true);
+    if (need > S.table_bytes) {
+      // tables of the whole group do not fit: two halves in turn
+      if (due.size() >= 2) {
+        const size_t h = due.size() / 2;
+        enqueue_batch(S, std::vector<Request*>(due.begin(), due.begin() + h), failed);
+        enqueue_batch(S, std::vector<Request*>(due.begin() + h, due.end()), failed);
+        return;
+      }
+      cg_enqueue_iteration(*due[0]->P);
+      ++S.iterations;
+      return;
+    }
+    SRV_HIPCHECK(hipEventSynchronize(S.ev_stage[k]));  // the previous upload from this buffer has read it
+    vcycle_batch(ps, rs.data(), zs.data(), S.d_table, S.table_bytes, &need, S.h_stage[k], S.bstream, true,
+                 S.ev_stage[k]);
+    SRV_HIPCHECK(hipEventRecord(S.ev_batch, S.bstream));
+  } catch (const Error& e) {
+    for (Request* r : due) failed.emplace_back(r, e.code, e.what());
+    return;
+  }
+  ++S.batches;
+  for (Request* r : due) {
+    try {
+      hipStream_t s = S.streams[r->slot];
+      SRV_HIPCHECK(hipStreamWaitEvent(s, S.ev_batch, 0));
+      cg_enqueue_tail(*r->P, s);
+      ++S.iterations;
+      ++S.batched_iterations;
+    } catch (const Error& e) {
+      failed.emplace_back(r, e.code, e.what());
+    }
+  }
+}
+
 void scheduler_loop(Server* S) {
   SRV_HIPCHECK(hipSetDevice(S->device));
   while (!S->stop) {
@@ -311,7 +383,7 @@ void scheduler_loop(Server* S) {
     std::vector<Request*> run, cop;
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      run = S->running;
+      if (!S->hold) run = S->running;
       cop = S->copying;
     }
     // copy-backs that have completed: the request is done, its memory and
@@ -337,20 +409,45 @@ void scheduler_loop(Server* S) {
       r->P.reset();   // drop host maps and device views; the arena range is free
       S->cv_done.notify_all();
     }
+    // requests whose solve finished (or failed), with status and error
+    std::vector<std::tuple<Request*, int, std::string>> fin;
+    // requests whose next iteration is due, by kernel set, precision,
+    // Chebyshev degree and smoother
+    std::map<std::tuple<const void*, int, int, int>, std::vector<Request*>> due;
     for (Request* r : run) {
-      bool done = false;
-      int status = 0;
-      std::string err;
       try {
-        done = cg_poll(*r->P, false);
-        status = r->P->cg.status;
+        const int st = cg_check(*r->P, false);
+        if (st == 0) continue;
+        idle = false;
+        if (st == 1) {
+          fin.emplace_back(r, r->P->cg.status, std::string());
+        } else {
+          const gmg_options& o = r->P->opt;
+          due[std::make_tuple((const void*)r->P->kt, o.mg_precision, o.cheb_degree, o.smoother)].push_back(r);
+        }
       } catch (const Error& e) {
-        done = true;
-        status = e.code;
-        err = e.what();
+        idle = false;
+        fin.emplace_back(r, e.code, e.what());
       }
-      if (!done) continue;
-      idle = false;
+    }
+    for (auto& g : due) {
+      if (S->batching && S->table_bytes && g.second.size() >= 2) {
+        enqueue_batch(*S, g.second, fin);
+        continue;
+      }
+      for (Request* r : g.second) {
+        try {
+          cg_enqueue_iteration(*r->P);
+          ++S->iterations;
+        } catch (const Error& e) {
+          fin.emplace_back(r, e.code, e.what());
+        }
+      }
+    }
+    for (auto& f : fin) {
+      Request* r = std::get<0>(f);
+      int status = std::get<1>(f);
+      std::string err = std::get<2>(f);
       Problem& P = *r->P;
       hipStream_t s = S->streams[r->slot];
       r->iterations = P.cg.it;
@@ -417,14 +514,25 @@ int gmg_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots, int3
     if (!d_arena || !out || max_slots < 1 || max_slots > 64 || host_threads < 1 || host_threads > 64)
       gmg::fail(GMG_E_INVAL, "invalid server arguments");
     if (reinterpret_cast<uintptr_t>(d_arena) & 255) gmg::fail(GMG_E_INVAL, "arena must be 256-byte aligned");
+    // launch tables of the batched V-cycles at the front of the arena: 1/32
+    // of it, at most 16 MiB (none for arenas under 2 MiB)
+    const size_t tb = arena_bytes >= (size_t(2) << 20) ? std::min(arena_bytes / 32, size_t(16) << 20) & ~size_t(255) : 0;
     auto h = std::make_unique<gmg_server_s>();
-    h->S = std::make_unique<Server>((char*)d_arena, arena_bytes, max_slots);
+    h->S = std::make_unique<Server>((char*)d_arena + tb, arena_bytes - tb, max_slots);
     Server& S = *h->S;
+    S.d_table = (char*)d_arena;
+    S.table_bytes = tb;
     SRV_HIPCHECK(hipGetDevice(&S.device));
     S.streams.resize(max_slots);
     for (int i = 0; i < max_slots; ++i) {
       SRV_HIPCHECK(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
       S.slot_free.push_back(max_slots - 1 - i);
+    }
+    SRV_HIPCHECK(hipStreamCreateWithFlags(&S.bstream, hipStreamNonBlocking));
+    SRV_HIPCHECK(hipEventCreateWithFlags(&S.ev_batch, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      SRV_HIPCHECK(hipEventCreateWithFlags(&S.ev_stage[i], hipEventDisableTiming));
+      if (tb) SRV_HIPCHECK(hipHostMalloc((void**)&S.h_stage[i], tb, hipHostMallocDefault));
     }
     S.host_cpus = std::max(1, (int)std::min(16u, std::thread::hardware_concurrency()));
     for (int i = 0; i < host_threads; ++i) S.workers.emplace_back(gmg::worker_loop, &S);
@@ -577,6 +685,27 @@ int gmg_server_stats(gmg_server h, gmg_server_stats_t* o) {
     o->arena_bytes = S.arena.size();
     o->dofs_done = S.dofs_done;
     o->clock = S.now();
+    o->iterations = S.iterations;
+    o->batched_iterations = S.batched_iterations;
+    o->batches = S.batches;
+    return 0;
+  });
+}
+
+int gmg_server_hold(gmg_server h, int hold) {
+  return sguard([&] {
+    if (!h) gmg::fail(GMG_E_INVAL, "null argument");
+    h->S->hold = hold != 0;
+    return 0;
+  });
+}
+
+int gmg_server_set_batching(gmg_server h, int enable) {
+  return sguard([&] {
+    if (!h) gmg::fail(GMG_E_INVAL, "null argument");
+    Server& S = *h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.batching = enable != 0;
     return 0;
   });
 }
@@ -594,6 +723,15 @@ int gmg_server_destroy(gmg_server h) {
   for (auto s : S.streams) {
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
+  }
+  if (S.bstream) {
+    (void)hipStreamSynchronize(S.bstream);
+    (void)hipStreamDestroy(S.bstream);
+  }
+  if (S.ev_batch) (void)hipEventDestroy(S.ev_batch);
+  for (int i = 0; i < 2; ++i) {
+    if (S.ev_stage[i]) (void)hipEventDestroy(S.ev_stage[i]);
+    if (S.h_stage[i]) (void)hipHostFree(S.h_stage[i]);
   }
   delete h;  // requests free their pinned buffers and events
   return 0;

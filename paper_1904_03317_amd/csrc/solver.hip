@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 
 #define GMG_SOLVER_TU
@@ -877,6 +878,245 @@ void vcycle_noalloc(Problem& P, const double* r, double* z, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- batched V-cycle
+// One V-cycle for each of several bound problems of the same dimension,
+// degree, precision and smoother, with the level sweeps of all of them in
+// one launch each: the levels are aligned from the coarse end (level l of
+// every problem that has one, finest levels first on the way down), every
+// smoothing step and residual pass (pass 1 and pass 2 of the level
+// operator, with their epilogues) and the second pass of every restriction
+// is one batched launch over the problems' levels, and the per-problem
+// steps (leaf <-> level copies, transfers, coarse solve) run between them on
+// the same stream.  Every problem sees exactly the operations of its own
+// V-cycle in the same order, and the batched kernels give every family the
+// logical block it gets alone, so each result equals the solo V-cycle's bit
+// for bit.
+namespace {
+struct BatchPlan {
+  std::vector<char> blob;                                  // host image of the item tables
+  std::vector<std::function<void(const char*)>> q;         // launches, in order (argument: device table)
+  template <typename Item>
+  size_t put(const std::vector<Item>& items) {
+    const size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + items.size() * sizeof(Item));
+    std::memcpy(blob.data() + off, items.data(), items.size() * sizeof(Item));
+    return off;
+  }
+};
+}  // namespace
+
+template <typename T>
+static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, double* const* z,
+                              hipStream_t s, bool dot_rz, BatchPlan& B) {
+  const int np = (int)ps.size();
+  const LevelOps<T>& op = ops<T>(*ps[0]);
+  const MatsH<T> mt = mats<T>(*ps[0]);
+  const int dim = ps[0]->maps->dim;
+  const int m = ps[0]->opt.cheb_degree;
+  int Lmax = 0;
+  for (Problem* P : ps) Lmax = std::max(Lmax, (int)P->lv.size() - 1);
+  auto level_of = [](Problem* P) { return (int)P->lv.size() - 1; };
+  auto cheb_ep = [](Problem& P, int l, int j) {
+    DevLevel& V = P.lv[l];
+    dev::Epi<T> ep;
+    ep.x = (T*)P.lx + V.off;
+    ep.d = (T*)P.ld + V.off;
+    ep.g = (T*)P.lg + V.off;
+    ep.dinv = (const T*)P.ldinv + V.off;
+    ep.flags = V.v.flags;
+    const StepCoef c = step_coef(P, l, j);
+    ep.c1 = T(c.c1);
+    ep.c2 = T(c.c2);
+    return ep;
+  };
+  // one batched level sweep (pass 1 + pass 2) with epilogue epi on level l of
+  // the problems `who`; input of pass 1: their x on that level
+  auto sweep = [&](int l, int epi, int step, const std::vector<int>& who) {
+    if (who.empty()) return;
+    std::vector<dev::OpItem<T>> oi;
+    std::vector<dev::SumItem<T>> si;
+    int64_t ob = 0, sb = 0;
+    for (int i : who) {
+      Problem& P = *ps[i];
+      DevLevel& V = P.lv[l];
+      dev::Epi<T> ep;
+      if (epi == dev::kEpiCheb) {
+        ep = cheb_ep(P, l, step);
+      } else {
+        ep.y = (T*)P.lt + V.off;
+        ep.g = (T*)P.lg + V.off;
+        ep.flags = V.v.flags;
+      }
+      oi.push_back(dev::OpItem<T>{V.v, ep, (const T*)P.lx + V.off, (T*)P.E, ob});
+      si.push_back(dev::SumItem<T>{V.v, ep, (const T*)P.E, sb});
+      ob += op.op_blocks(V.v);
+      sb += (V.v.shn[dim + 1] + dev::kBlock - 1) / dev::kBlock;
+    }
+    const int n = (int)who.size();
+    if (op.op_batch) {
+      const size_t oo = B.put(oi);
+      B.q.push_back([=, &op](const char* t) { op.op_batch((const dev::OpItem<T>*)(t + oo), n, ob, epi, mt, s); });
+    } else {
+      for (const auto& it : oi)
+        B.q.push_back([=, &op](const char*) { op.op(it.v, epi, it.x, it.ep, it.E, mt, s); });
+    }
+    const size_t so = B.put(si);
+    B.q.push_back([=, &op](const char* t) { op.sum_batch((const dev::SumItem<T>*)(t + so), n, sb, epi, s); });
+  };
+  // leaf residual into the levels, first pre-smoothing step on the finest level
+  for (int i = 0; i < np; ++i) {
+    Problem* P = ps[i];
+    const int L = level_of(P);
+    const double* ri = r ? r[i] : nullptr;  // r, z: NULL when only the table size is asked for
+    const T s1 = L >= 1 ? T(step_coef(*P, L, 1).c2) : T(0);
+    B.q.push_back([=](const char*) {
+      const int64_t N = P->maps->n_dofs;
+      T *X = (T*)P->lx, *G = (T*)P->lg, *R = (T*)P->lt, *Dd = (T*)P->ld, *Di = (T*)P->ldinv;
+      fill_dev(G, P->n_total, T(0), s);
+      hipLaunchKernelGGL(dev::copy_to_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P->copy, ri, G);
+      if (L >= 1) {
+        DevLevel& V = P->lv[L];
+        hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(V.v.n_dofs)), dim3(dev::kBlock), 0, s, V.v.n_dofs,
+                           X + V.off, Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0), s1, 1);
+      }
+    });
+  }
+  for (int l = Lmax; l >= 1; --l) {
+    std::vector<int> act, sm;
+    for (int i = 0; i < np; ++i)
+      if (level_of(ps[i]) >= l) {
+        act.push_back(i);
+        if (ps[i]->lv[l].n_S > 0) sm.push_back(i);
+      }
+    for (int j = 2; j <= m; ++j) sweep(l, dev::kEpiCheb, j, sm);
+    sweep(l, dev::kEpiResid, 0, sm);
+    std::vector<dev::SumItem<T>> rs;
+    int64_t rb = 0;
+    for (int i : act) {
+      Problem* P = ps[i];
+      DevLevel& V = P->lv[l];
+      DevLevel& W = P->lv[l - 1];
+      T *X = (T*)P->lx, *G = (T*)P->lg, *R = (T*)P->lt, *Dd = (T*)P->ld, *Di = (T*)P->ldinv;
+      T* E = (T*)P->E;
+      if (V.n_S == 0) {
+        const int64_t n = V.v.n_dofs;
+        B.q.push_back([=](const char*) {
+          hipLaunchKernelGGL(dev::seg_residual<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n,
+                             (const int32_t*)nullptr, (const T*)E, G + V.off, V.v.flags, R + V.off, 0);
+        });
+      }
+      if (l - 1 >= 1) {
+        dev::Epi<T> ep;
+        ep.x = X + W.off;
+        ep.d = Dd + W.off;
+        ep.g = G + W.off;
+        ep.dinv = Di + W.off;
+        ep.flags = W.v.flags;
+        ep.c2 = T(step_coef(*P, l - 1, 1).c2);
+        ep.smooth = 1;
+        const LevelView fv = V.v, cv = W.v;
+        T* rbuf = (T*)P->rbuf;
+        const T* rin = R + V.off;
+        B.q.push_back([=, &op](const char*) { op.restrict_fc(fv, cv, rin, ep, rbuf, E, mt, s); });
+        rs.push_back(dev::SumItem<T>{W.v, ep, (const T*)E, rb});
+        rb += (W.v.shn[dim + 1] + dev::kBlock - 1) / dev::kBlock;
+      } else {
+        const LevelView fv = V.v, cv = W.v;
+        const T* rin = R + V.off;
+        B.q.push_back([=, &op](const char*) {
+          op.restrict0(fv, rin, E, mt, s);
+          hipLaunchKernelGGL(dev::seg_restrict_start<T>, dim3(grid1(cv.n_dofs)), dim3(dev::kBlock), 0, s,
+                             cv.n_dofs, cv.roff, (const T*)E, G + W.off, X + W.off, Dd + W.off, Di + W.off, T(0), 0);
+        });
+      }
+    }
+    if (!rs.empty()) {
+      const size_t so = B.put(rs);
+      const int n = (int)rs.size();
+      B.q.push_back([=, &op](const char* t) {
+        op.sum_batch((const dev::SumItem<T>*)(t + so), n, rb, dev::kEpiRStart, s);
+      });
+    }
+  }
+  for (int i = 0; i < np; ++i) {
+    Problem* P = ps[i];
+    B.q.push_back([=](const char*) {
+      hipLaunchKernelGGL(dev::coarse_solve<T>, dim3(1), dim3(dev::kBlock), P->n0 * sizeof(double), s,
+                         (int)P->lv[0].v.n_dofs, P->n0, P->ainv, P->cidx, (T*)P->lg + P->lv[0].off,
+                         (T*)P->lx + P->lv[0].off);
+    });
+  }
+  for (int l = 1; l <= Lmax; ++l) {
+    std::vector<int> sm;
+    for (int i = 0; i < np; ++i) {
+      Problem* P = ps[i];
+      if (level_of(P) < l) continue;
+      const LevelView fv = P->lv[l].v, cv = P->lv[l - 1].v;
+      T* X = (T*)P->lx;
+      const int64_t fo = P->lv[l].off, co = P->lv[l - 1].off;
+      B.q.push_back([=, &op](const char*) { op.prolong(fv, cv, X + co, X + fo, mt, s); });
+      if (P->lv[l].n_S > 0) sm.push_back(i);
+    }
+    for (int j = 1; j <= m; ++j) sweep(l, dev::kEpiCheb, j, sm);
+  }
+  for (int i = 0; i < np; ++i) {
+    Problem* P = ps[i];
+    const double* ri = r ? r[i] : nullptr;
+    double* zi = z ? z[i] : nullptr;
+    B.q.push_back([=](const char*) {
+      const int64_t N = P->maps->n_dofs;
+      if (dot_rz)
+        hipLaunchKernelGGL(dev::copy_from_levels_dot<T>, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P->copy,
+                           (const T*)P->lx, zi, ri, P->part);
+      else
+        hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P->copy,
+                           (T*)P->lx, zi);
+    });
+  }
+}
+
+// Plans the batched V-cycle; with d_table, uploads the item tables (through
+// h_stage, pinned host memory of at least table_bytes, when given; the event
+// `staged`, when given, is recorded once the upload has read it) and
+// enqueues it.  *need: bytes of the item tables.
+void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, double* const* z, char* d_table,
+                  size_t table_bytes, size_t* need, char* h_stage, hipStream_t s, bool dot_rz, hipEvent_t staged) {
+  if (ps.empty()) fail(GMG_E_INVAL, "empty batch");
+  {
+    std::vector<Problem*> u(ps);
+    std::sort(u.begin(), u.end());
+    if (std::adjacent_find(u.begin(), u.end()) != u.end()) fail(GMG_E_INVAL, "a problem twice in one batch");
+  }
+  for (Problem* P : ps) {
+    if (!P->bound) fail(GMG_E_STATE, "problem not bound");
+    if (P->kt != ps[0]->kt || P->opt.mg_precision != ps[0]->opt.mg_precision ||
+        P->opt.cheb_degree != ps[0]->opt.cheb_degree || P->opt.smoother != ps[0]->opt.smoother ||
+        P->device != ps[0]->device)
+      fail(GMG_E_INVAL, "a batch needs one dimension, degree, precision, smoother and device");
+  }
+  BatchPlan B;
+  if (ps[0]->opt.mg_precision == 32)
+    plan_vcycle_batch<float>(ps, r, z, s, dot_rz, B);
+  else
+    plan_vcycle_batch<double>(ps, r, z, s, dot_rz, B);
+  const size_t bytes = std::max<size_t>(256, (B.blob.size() + 255) & ~size_t(255));
+  if (need) *need = bytes;
+  if (!d_table) return;
+  if ((reinterpret_cast<uintptr_t>(d_table) & 255) != 0) fail(GMG_E_INVAL, "batch table must be 256-byte aligned");
+  if (table_bytes < bytes) fail(GMG_E_INVAL, "batch table too small");
+  if (!B.blob.empty()) {
+    const char* src = B.blob.data();
+    if (h_stage) {
+      std::memcpy(h_stage, B.blob.data(), B.blob.size());
+      src = h_stage;
+    }
+    HIPCHECK(hipMemcpyAsync(d_table, src, B.blob.size(), hipMemcpyHostToDevice, s));
+  }
+  if (staged) HIPCHECK(hipEventRecord(staged, s));
+  for (auto& f : B.q) f(d_table);
+  HIPCHECK(hipGetLastError());
+}
+
 // the CG preconditioner: replay of a captured graph of one V-cycle on the
 // fixed CG buffers r -> z when enabled
 static void precondition(Problem& P, hipStream_t s) {
@@ -969,15 +1209,13 @@ void cg_start(Problem& P, const double* b, double* u, hipStream_t s, bool timed)
   P.timing[2] = 0.0;
 }
 
-static void cg_enqueue_iteration(Problem& P) {
+// the CG iteration after the preconditioner (z = B r with the partial sums
+// of r.z already enqueued on s)
+void cg_enqueue_tail(Problem& P, hipStream_t s) {
   CgState& C = P.cg;
-  hipStream_t s = C.stream;
   const int64_t N = P.maps->n_dofs;
   const unsigned dg = dot_grid(N);
   double* sc = P.scal;
-  if (C.timed) HIPCHECK(hipEventRecord(P.ev[2], s));
-  precondition(P, s);  // z = B r, with the partial sums of r.z
-  if (C.timed) HIPCHECK(hipEventRecord(P.ev[3], s));
   hipLaunchKernelGGL(dev::cg_scalars, dim3(1), dim3(dev::kBlock), 0, s, (int)fuse_grid(N), P.part, sc, 0);
   hipLaunchKernelGGL(dev::update_p, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P.cp, P.cz, sc);
   // q = A p, with the partial sums of p.q
@@ -988,6 +1226,15 @@ static void cg_enqueue_iteration(Problem& P) {
   HIPCHECK(hipMemcpyAsync(P.host, sc, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipEventRecord(P.ev[4], s));
   C.pending = true;
+}
+
+void cg_enqueue_iteration(Problem& P) {
+  CgState& C = P.cg;
+  hipStream_t s = C.stream;
+  if (C.timed) HIPCHECK(hipEventRecord(P.ev[2], s));
+  precondition(P, s);  // z = B r, with the partial sums of r.z
+  if (C.timed) HIPCHECK(hipEventRecord(P.ev[3], s));
+  cg_enqueue_tail(P, s);
 }
 
 static void cg_finish(Problem& P, int status) {
@@ -1003,16 +1250,18 @@ static void cg_finish(Problem& P, int status) {
   }
 }
 
-// returns true when the solve has finished (status in P.cg.status)
-bool cg_poll(Problem& P, bool block) {
+// 0: the last enqueued work is still running; 1: the solve has finished
+// (status in P.cg.status); 2: the next iteration is due (iteration count
+// advanced, nothing enqueued yet)
+int cg_check(Problem& P, bool block) {
   CgState& C = P.cg;
-  if (!C.running) return true;
+  if (!C.running) return 1;
   if (C.pending) {
     if (block) {
       HIPCHECK(hipEventSynchronize(P.ev[4]));
     } else {
       hipError_t e = hipEventQuery(P.ev[4]);
-      if (e == hipErrorNotReady) return false;
+      if (e == hipErrorNotReady) return 0;
       if (e != hipSuccess) fail(GMG_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
     }
     C.pending = false;
@@ -1022,11 +1271,11 @@ bool cg_poll(Problem& P, bool block) {
     C.hist[0] = bb > 0 ? 1.0 : 0.0;
     if (!std::isfinite(bb)) {
       cg_finish(P, GMG_E_NAN);
-      return true;
+      return 1;
     }
     if (bb == 0.0) {
       cg_finish(P, GMG_OK);
-      return true;
+      return 1;
     }
     C.nb = std::sqrt(bb);
   } else {
@@ -1041,24 +1290,31 @@ bool cg_poll(Problem& P, bool block) {
     C.hist[C.it] = res / C.nb;
     if (!std::isfinite(rr) || !std::isfinite(rho) || !std::isfinite(pq)) {
       cg_finish(P, GMG_E_NAN);
-      return true;
+      return 1;
     }
     if (!(rho > 0.0) || !(pq > 0.0)) {
       cg_finish(P, GMG_E_BREAKDOWN);
-      return true;
+      return 1;
     }
     if (res <= P.opt.rtol * C.nb) {
       cg_finish(P, GMG_OK);
-      return true;
+      return 1;
     }
     if (C.it >= P.opt.max_iter) {
       cg_finish(P, GMG_NOT_CONVERGED);
-      return true;
+      return 1;
     }
   }
   ++C.it;
-  cg_enqueue_iteration(P);
-  return false;
+  return 2;
+}
+
+// returns true when the solve has finished (status in P.cg.status); else
+// enqueues the next iteration when it is due
+bool cg_poll(Problem& P, bool block) {
+  const int r = cg_check(P, block);
+  if (r == 2) cg_enqueue_iteration(P);
+  return r == 1;
 }
 
 int solve(Problem& P, const double* b, double* u, int32_t* iters, double* hist, hipStream_t s) {

@@ -48,7 +48,8 @@ class gmg_timing(C.Structure):
 class gmg_server_stats(C.Structure):
     _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("completed", C.c_int64),
                 ("failed", C.c_int64), ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t),
-                ("arena_bytes", C.c_size_t), ("dofs_done", C.c_double), ("clock", C.c_double)]
+                ("arena_bytes", C.c_size_t), ("dofs_done", C.c_double), ("clock", C.c_double),
+                ("iterations", C.c_int64), ("batched_iterations", C.c_int64), ("batches", C.c_int64)]
 
 
 REQ_STATES = ["QUEUED", "SETUP", "READY", "BINDING", "RUNNING", "DONE", "FAILED", "WAIT_RHS"]
@@ -90,6 +91,7 @@ def configure(L):
         "gmg_apply_level": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp]),
         "gmg_vcycle": (C.c_int, [vp, vp, vp, vp]),
         "gmg_vcycle_noalloc": (C.c_int, [vp, vp, vp, vp]),
+        "gmg_vcycle_batch": (C.c_int, [vp, C.c_int, vp, vp, vp, C.POINTER(C.c_size_t), vp]),
         "gmg_problem_last_timing": (C.c_int, [vp, C.POINTER(dbl)]),
         "gmg_server_create": (C.c_int, [vp, C.c_size_t, i32, i32, C.POINTER(vp)]),
         "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, vp, i64, C.POINTER(C.c_uint64)]),
@@ -102,6 +104,8 @@ def configure(L):
         "gmg_server_release": (C.c_int, [vp, C.c_uint64]),
         "gmg_server_stats": (C.c_int, [vp, C.POINTER(gmg_server_stats)]),
         "gmg_server_destroy": (C.c_int, [vp]),
+        "gmg_server_set_batching": (C.c_int, [vp, i32]),
+        "gmg_server_hold": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -132,11 +136,11 @@ def exported_symbols():
             "gmg_mesh_num_leaves", "gmg_mesh_leaves", "gmg_mesh_dim", "gmg_mesh_destroy",
             "gmg_problem_create", "gmg_problem_clone", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
-            "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle", "gmg_vcycle_noalloc",
+            "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle", "gmg_vcycle_noalloc", "gmg_vcycle_batch",
             "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_request_dofs",
             "gmg_server_set_rhs", "gmg_server_poll",
             "gmg_server_wait", "gmg_server_result", "gmg_server_release", "gmg_server_stats",
-            "gmg_server_destroy"]
+            "gmg_server_destroy", "gmg_server_set_batching", "gmg_server_hold"]
 
 
 def _check(code):
@@ -166,6 +170,24 @@ def _stream(stream=None):
         return C.c_void_p(stream)
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def vcycle_batch(problems, rs, zs, table=None, stream=None):
+    """gmg_vcycle_batch: one V-cycle per problem, level sweeps batched.  rs,
+    zs: device tensors; table: a device uint8 tensor for the launch tables
+    (allocated here when None).  Returns the table."""
+    import torch
+    n = len(problems)
+    ph = (C.c_void_p * n)(*[p.h.value for p in problems])
+    rp = (C.c_void_p * n)(*[r.data_ptr() for r in rs])
+    zp = (C.c_void_p * n)(*[z.data_ptr() for z in zs])
+    need = C.c_size_t(0)
+    _check(lib().gmg_vcycle_batch(ph, n, rp, zp, None, C.byref(need), _stream(stream)))
+    if table is None or table.numel() < need.value:
+        table = torch.empty(need.value, dtype=torch.uint8, device=rs[0].device)
+    cap = C.c_size_t(table.numel())
+    _check(lib().gmg_vcycle_batch(ph, n, rp, zp, _ptr(table), C.byref(cap), _stream(stream)))
+    return table
 
 
 class Mesh:
@@ -315,13 +337,15 @@ class Problem:
 class Server:
     """Serving loop (gmg_server_*): resident solves on one HBM arena."""
 
-    def __init__(self, arena_bytes, max_slots=8, host_threads=4, device="cuda"):
+    def __init__(self, arena_bytes, max_slots=8, host_threads=4, device="cuda", batching=True):
         import torch
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = C.c_void_p()
         _check(lib().gmg_server_create(_ptr(self.arena), self.arena.numel(), max_slots, host_threads,
                                        C.byref(h)))
         self.h = h
+        if not batching:
+            _check(lib().gmg_server_set_batching(self.h, 0))
 
     def submit(self, mesh: Mesh, opts=None, coeff=None, f=None, rhs_later=False):
         """Queue a solve; the server takes the mesh.  f: nodal right-hand side
@@ -380,6 +404,10 @@ class Server:
 
     def release(self, rid):
         _check(lib().gmg_server_release(self.h, rid))
+
+    def hold(self, on=True):
+        """Stop (True) or resume (False) advancing the resident solves."""
+        _check(lib().gmg_server_hold(self.h, 1 if on else 0))
 
     def stats(self):
         s = gmg_server_stats()

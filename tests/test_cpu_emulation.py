@@ -38,7 +38,7 @@ def emu_results():
     build_emu.build()
     env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
     procs = {}
-    for case, prec in EMU_CASES:
+    for case, prec in EMU_CASES + [("serve", 64)]:
         procs[(case, prec)] = subprocess.Popen(
             [sys.executable, os.path.join(HERE, "cpuemu", "run_emu.py"), case, str(prec)],
             stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
@@ -51,6 +51,21 @@ def emu_results():
             so, se = p.communicate()
         out[key] = (p.returncode, so, se)
     return out
+
+
+def test_emulated_serving_batched_matches_solo(emu_results):
+    """The serving loop (scheduler and worker threads, batched V-cycles) in
+    the emulation: two requests, three CG iterations each, match their solo
+    solves (same status and iteration count; rounding-level differences only,
+    the emulated LDS additions having no fixed order), and batched V-cycles
+    did run."""
+    rc, so, se = emu_results[("serve", 64)]
+    assert "AddressSanitizer" not in se, se[-6000:]
+    assert rc == 0, se[-6000:]
+    r = json.loads(so.strip().splitlines()[-1])
+    assert r["completed"] == 2 and r["same_its"]
+    assert r["rel"] <= 1e-12
+    assert r["batched_iterations"] == 6
 
 
 @pytest.mark.parametrize("case,prec", EMU_CASES)
@@ -67,5 +82,6 @@ def test_emulated_kernels_match_oracle(emu_results, case, prec):
         # FP32 level operators and V-cycle: single-precision rounding
         assert r["level_rel"] <= 2e-6 and r["edge_rel"] <= 2e-6 and r["vcycle_rel"] <= 1e-5
     assert r["noalloc_equal"]
+    assert r["batch_equal"]
     assert r["status"] == 0 and r["its"] == r["its_oracle"]
     assert r["solve_rel"] <= 1e-10

@@ -2,6 +2,8 @@
 together give the same result as alone (bitwise: every kernel is
 deterministic), admission respects the memory budget, failures are reported
 per request."""
+import time
+
 import numpy as np
 import pytest
 
@@ -31,16 +33,34 @@ def _alone(r, opts):
     return st, its, u.cpu().numpy()
 
 
-def test_mixed_equals_alone():
+@pytest.mark.parametrize("batching", [True, False])
+def test_mixed_equals_alone(batching):
+    """Eight requests through three slots: with batching on, the V-cycles of
+    the resident requests due in a tick run as one batched V-cycle (their
+    level sweeps in one launch each); every result equals the request's solo
+    solve bit for bit either way."""
     from paper_1904_03317_amd import gmg
     opts = gmg.options(degree=2, mg_precision=32)
     ids = list(range(8))
-    S = gmg.Server(arena_bytes=1 << 30, max_slots=3, host_threads=3)
+    S = gmg.Server(arena_bytes=1 << 30, max_slots=3, host_threads=3, batching=batching)
+    # held until the first three are resident, so that they start together
+    S.hold(True)
     rids = {S.submit(_mesh(r), opts): r for r in ids}
+    first = list(rids)[:3]
+    t0 = time.time()
+    while not all(S.poll(rid)[0] == "RUNNING" for rid in first) and time.time() - t0 < 120:
+        time.sleep(0.01)
+    S.hold(False)
     for rid in rids:
         S.wait(rid, 300)
     st = S.stats()
+    print(f"[gpu] serving batching={batching}: {st['iterations']} iterations, {st['batched_iterations']} batched "
+          f"in {st['batches']} batches", flush=True)
     assert st["completed"] == len(ids) and st["failed"] == 0 and st["arena_used"] == 0
+    if batching:
+        assert st["batched_iterations"] > 0 and st["batches"] > 0
+    else:
+        assert st["batched_iterations"] == 0
     for rid, r in rids.items():
         res = S.result(rid)
         s0, its0, u0 = _alone(r, opts)

@@ -120,8 +120,9 @@ def test_errors_are_reported():
 
 
 def test_max_level_rejected():
+    """Refinement stops at level 16 (the forest's largest level)."""
     m = gmg.Mesh(2, [(0, 0)])
-    for _ in range(18):
+    for _ in range(16):
         lv, an = m.leaves()
         f = np.zeros(len(lv), np.uint8)
         f[0] = 1
