@@ -216,7 +216,7 @@ def build_request_meshes(ids, threads=8):
         return list(ex.map(one, ids))
 
 
-def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_g=None):
+def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_g=None, closed_n=64, resident=32):
     """Open-loop serving stream of unit-cube Q2 requests (FP32 V-cycle, FP64
     CG) with Poisson arrivals at `load` times the throughput measured in a
     closed-loop warm-up.  Latency = completion - arrival on the server clock."""
@@ -237,6 +237,53 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
         bm = gmg.build_mesh(wb.recipe)
         big = (bm, gmg.options(degree=wb.degree, mg_precision=32), gi.coeff_cells(wb.coeff, *bm.leaves()))
         log(f"serve: C5 job with g={big_g}: {bm.n_leaves} leaves (its host set-up runs on a server thread)")
+    closed = {}
+    if big is None:
+        # closed loop, all requests at once, with the V-cycles of the requests
+        # due in a tick batched and with each request replaying its own
+        # V-cycle graph
+        for batching in (False, True):
+            Sc = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=slots, host_threads=threads,
+                            batching=batching)
+            ms = build_request_meshes(range(20000, 20000 + closed_n), threads)  # submit takes them
+            c0 = Sc.stats()["clock"]
+            ids = [Sc.submit(m, opts) for m in ms]
+            for i in ids:
+                Sc.wait(i, 600)
+            c1 = Sc.stats()["clock"]
+            st = Sc.stats()
+            Sc.close()
+            key = "batched" if batching else "per_request_graphs"
+            closed[key] = {"throughput_rps": closed_n / (c1 - c0), "iterations": st["iterations"],
+                           "batched_iterations": st["batched_iterations"], "batches": st["batches"]}
+            log(f"serve: closed loop of {closed_n} requests, {key}: {closed_n / (c1 - c0):.1f} req/s "
+                f"({st['batched_iterations']} of {st['iterations']} iterations in {st['batches']} batches)")
+        # the solve phase alone: `resident` requests set up and bound while
+        # the server holds, then released together; time until the last one
+        # finished (CG iterations and copy-back, no host set-up)
+        for batching in (False, True):
+            Sc = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=resident, host_threads=threads,
+                            batching=batching)
+            Sc.hold(True)
+            ids = [Sc.submit(m, opts) for m in build_request_meshes(range(30000, 30000 + resident), threads)]
+            while not all(Sc.poll(i)[0] == "RUNNING" for i in ids):
+                time.sleep(0.002)
+            c0 = Sc.stats()["clock"]
+            Sc.hold(False)
+            fin, nd = 0.0, 0
+            for i in ids:
+                Sc.wait(i, 600)
+                r = Sc.result(i)
+                fin = max(fin, r["timing"]["finished"])
+                nd += len(r["u"])
+            st = Sc.stats()
+            Sc.close()
+            key = "resident_batched" if batching else "resident_per_request_graphs"
+            closed[key] = {"requests": resident, "solve_phase_s": fin - c0, "dofs": nd,
+                           "dofs_per_s": nd / (fin - c0), "iterations": st["iterations"],
+                           "batched_iterations": st["batched_iterations"], "batches": st["batches"]}
+            log(f"serve: {resident} resident requests ({nd} DoFs), {key}: solve phase {(fin - c0) * 1e3:.1f} ms "
+                f"({st['batched_iterations']} of {st['iterations']} iterations in {st['batches']} batches)")
     S = gmg.Server(arena_bytes=int(arena_gb * (1 << 30)), max_slots=slots, host_threads=threads)
     # closed loop: all warm-up requests at once
     c0 = S.stats()["clock"]
@@ -297,7 +344,9 @@ def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_
             "dofs_per_s": dofs / span, "total_dofs": dofs, "cg_iterations_max": int(max(its)),
             "cg_iterations_min": int(min(its)), "failed": int(sum(1 for s in status if s != 0)),
             "slots": slots, "host_threads": threads, "arena_peak_gb": st["arena_peak"] / 2 ** 30,
-            "large_job": big_info, "latency_stages": breakdown,
+            "large_job": big_info, "latency_stages": breakdown, "closed_loop": closed or None,
+            "iterations": st["iterations"], "batched_iterations": st["batched_iterations"],
+            "batches": st["batches"],
             "latency_includes": "queueing + host set-up + device set-up + solve + copy-back"}
 
 

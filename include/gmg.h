@@ -266,12 +266,12 @@ int gmg_problem_last_timing(gmg_problem p, double* out3);
  * scheduler thread admits ready requests in arrival order whenever a slot
  * and enough arena memory are free (first fit), sets them up on the device
  * on the slot's stream and then advances every resident solve one CG
- * iteration per tick.  The V-cycles of the requests due in a tick that share
- * dimension, degree, precision, Chebyshev degree and smoother run as one
- * batched V-cycle (as gmg_vcycle_batch: one launch per level sweep for all
- * of them) on a batch stream; the rest of each iteration runs on the
- * request's own stream.  A request alone in its group replays its V-cycle
- * as a captured HIP graph.  A finished request frees its slot and memory for
+ * iteration per tick.  The requests due in a tick that share dimension,
+ * degree, precision, Chebyshev degree and smoother run that iteration as
+ * one batched iteration on a batch stream (V-cycle as gmg_vcycle_batch, and
+ * the rest of the CG iteration likewise: one launch per step for all of
+ * them).  A request alone in its group replays its V-cycle as a captured
+ * HIP graph on its own stream.  A finished request frees its slot and memory for
  * the next one.  Results do not depend on the other resident requests (all
  * kernels are deterministic and a batched V-cycle equals the request's own
  * bit for bit). */

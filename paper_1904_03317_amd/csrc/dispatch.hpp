@@ -78,7 +78,13 @@ template <typename T>
 struct OpItem;
 template <typename T>
 struct SumItem;
+template <typename T>
+struct XferItem;
+struct LeafItem;
 }
+
+// kinds of batched transfers (LevelOps::xfer_batch)
+enum XferKind { kXRFine = 0, kXRestrict = 1, kXRestrict0 = 2, kXProlong = 3 };
 
 template <typename T>
 struct LevelOps {
@@ -106,6 +112,11 @@ struct LevelOps {
   void (*op_batch)(const dev::OpItem<T>* items, int n, int64_t blocks, int epi, const MatsH<T>&, hipStream_t);
   void (*sum_batch)(const dev::SumItem<T>* items, int n, int64_t blocks, int epi, hipStream_t);
   int64_t (*op_blocks)(const LevelView&);   // pass-1 blocks of a level
+  // transfers of several problems in one launch (XferKind; the blocks of an
+  // item from xfer_blocks of its fine level, coarse level for kXRestrict);
+  // null where they have no batched form (3D at k >= 3)
+  void (*xfer_batch)(int kind, const dev::XferItem<T>* items, int n, int64_t blocks, const MatsH<T>&, hipStream_t);
+  int64_t (*xfer_blocks)(int kind, const LevelView&);
 };
 
 struct KernelTable {
@@ -120,6 +131,11 @@ struct KernelTable {
                      const MatsH<double>&, hipStream_t);
   // level 0: diagonal of the operator accumulated per node
   void (*diag0)(const LevelView&, double* diag, const MatsH<double>&, hipStream_t);
+  // the tiled leaf operator (with partial sums of x.y) of several problems
+  // in one launch, lds: the largest dynamic LDS of the items; null for 3D at
+  // degree >= 3
+  void (*leaf_t_batch)(const dev::LeafItem* items, int n, int64_t blocks, size_t lds, const MatsH<double>&,
+                       hipStream_t);
 };
 
 const KernelTable* kernel_table(int dim, int k);

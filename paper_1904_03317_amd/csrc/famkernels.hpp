@@ -593,20 +593,6 @@ struct OpItem {
   int64_t b0;
 };
 
-// the item of this block (items in ascending b0, the first at 0)
-template <typename Item>
-__device__ __forceinline__ int batch_item(const Item* items, int n) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (items[mid].b0 <= (int64_t)blockIdx.x)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 template <int DIM, int K, typename T, int EPI>
 __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_op_batch(const OpItem<T>* __restrict__ items,
                                                                                 int n, Mats<T> m) {
@@ -898,8 +884,8 @@ __device__ __forceinline__ void restrict_family(const LevelView& fine, int64_t f
 // 2^d lanes sum their (k+1)^d parent-cell values; rb[f (k+1)^d + j] receives
 // the restricted residual of family f's parent cell.
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(LevelView fine, const T* __restrict__ r,
-                                                                             T* __restrict__ rb, Mats<T> m) {
+__device__ __forceinline__ void fam_rfine_at(const LevelView& fine, const T* __restrict__ r, T* __restrict__ rb,
+                                             const Mats<T>& m, int64_t b, int64_t nb) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
@@ -909,7 +895,7 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(Leve
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
   __shared__ int64_t bo[NB];
-  const int64_t f0 = xcd_block() * FB;
+  const int64_t f0 = xcd_block_of(b, nb) * FB;
   const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
   const int tid = threadIdx.x;
   stage_bases<DIM, K, T>(fine, f0, sgb, sex, bq, bc, bo);
@@ -981,6 +967,11 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(Leve
       if (j % CPF == cid) rb[(f0 + fl) * NP + j] = v[j];
   }
 }
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(LevelView fine, const T* __restrict__ r,
+                                                                             T* __restrict__ rb, Mats<T> m) {
+  fam_rfine_at<DIM, K, T>(fine, r, rb, m, blockIdx.x, gridDim.x);
+}
 
 // Restriction, coarse side: one workgroup per FB coarse families, one lane
 // per coarse cell reading the restricted values of its fine family (if the
@@ -989,9 +980,8 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_rfine(Leve
 // the level passes through it, restricted contribution or not; pass 2 of
 // the coarse level finishes the shared nodes).
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(LevelView coarse,
-                                                                                const T* __restrict__ rb, Epi<T> ep,
-                                                                                T* __restrict__ E, Mats<T> m) {
+__device__ __forceinline__ void fam_restrict_at(const LevelView& coarse, const T* __restrict__ rb, const Epi<T>& ep,
+                                                T* __restrict__ E, const Mats<T>& m, int64_t b, int64_t nb) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
@@ -1001,7 +991,7 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(L
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
   __shared__ int64_t bo[NB];
-  const int64_t f0 = xcd_block() * FB;
+  const int64_t f0 = xcd_block_of(b, nb) * FB;
   const int nf = (int)(coarse.n_fam - f0 < FB ? coarse.n_fam - f0 : FB);
   const int tid = threadIdx.x;
   int32_t inode[S::ITI];
@@ -1024,20 +1014,31 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(L
   __syncthreads();
   patch_out<DIM, K, T, kEpiRStart>(coarse, f0, nf, sout, sout, sgb, sex, bq, bc, bo, ep, E, inode, iops);
 }
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_restrict(LevelView coarse,
+                                                                                const T* __restrict__ rb, Epi<T> ep,
+                                                                                T* __restrict__ E, Mats<T> m) {
+  fam_restrict_at<DIM, K, T>(coarse, rb, ep, E, m, blockIdx.x, gridDim.x);
+}
 
 // Restriction from level 1 into level 0 (no families there): one lane per
 // level-1 family, parent-node values to the level-0 node-major slots
 // (summed by seg_restrict_start).
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__(kBlock) fam_restrict0(LevelView fine, const T* __restrict__ r,
-                                                        T* __restrict__ E, Mats<T> m) {
+__device__ __forceinline__ void fam_restrict0_at(const LevelView& fine, const T* __restrict__ r, T* __restrict__ E,
+                                                 const Mats<T>& m, int64_t b, int64_t nb) {
   using G = Geo<DIM, K>;
-  const int64_t f = xcd_tid();
+  const int64_t f = xcd_block_of(b, nb) * blockDim.x + threadIdx.x;
   if (f >= fine.n_fam) return;
   T out[G::NP];
   restrict_family<DIM, K, T>(fine, f, r, m, out);
 #pragma unroll
   for (int j = 0; j < G::NP; ++j) E[fine.rslot[(int64_t)j * fine.n_fam + f]] = out[j];
+}
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) fam_restrict0(LevelView fine, const T* __restrict__ r,
+                                                        T* __restrict__ E, Mats<T> m) {
+  fam_restrict0_at<DIM, K, T>(fine, r, E, m, blockIdx.x, gridDim.x);
 }
 
 // Prolongation x_f += P x_c, fine families in workgroups like the operator:
@@ -1149,9 +1150,9 @@ __device__ __forceinline__ void prolong_add(int64_t f0, int nf, const T* sout, c
 }
 
 template <int DIM, int K, typename T>
-__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(LevelView fine, LevelView coarse,
-                                                                               const T* __restrict__ xc,
-                                                                               T* __restrict__ xf, Mats<T> m) {
+__device__ __forceinline__ void fam_prolong_at(const LevelView& fine, const LevelView& coarse,
+                                               const T* __restrict__ xc, T* __restrict__ xf, const Mats<T>& m,
+                                               int64_t b, int64_t nb) {
   using S = FamShape<DIM, K, T>;
   using G = Geo<DIM, K>;
   constexpr int N = G::N, MFP = S::MFP, FB = S::FB, CPF = G::CPF, NJ = G::NJ, NP = G::NP, NB = G::NB;
@@ -1161,7 +1162,7 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(Le
   __shared__ uint32_t sown[FB];
   __shared__ uint16_t bq[NB];
   __shared__ uint32_t bc[NB];
-  const int64_t f0 = xcd_block() * FB;
+  const int64_t f0 = xcd_block_of(b, nb) * FB;
   const int nf = (int)(fine.n_fam - f0 < FB ? fine.n_fam - f0 : FB);
   const int tid = threadIdx.x;
   prolong_stage<DIM, K, T, S>(fine, coarse, xc, f0, nf, sgb, sown, bq, bc, su);
@@ -1222,6 +1223,50 @@ __global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(Le
   }
   __syncthreads();
   prolong_add<DIM, K, T, S>(f0, nf, sout, sgb, sown, bq, bc, xf);
+}
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS)) fam_prolong(LevelView fine, LevelView coarse,
+                                                                               const T* __restrict__ xc,
+                                                                               T* __restrict__ xf, Mats<T> m) {
+  fam_prolong_at<DIM, K, T>(fine, coarse, xc, xf, m, blockIdx.x, gridDim.x);
+}
+
+// The transfer kernels of several problems in one launch (item contract as
+// OpItem; fields a kernel does not take are unused): restriction fine side
+// (f, in = r, out = rb), coarse side (c, in = rb, ep, E), into level 0 (f,
+// in = r, E), prolongation (f, c, in = x_c, out = x_f).
+template <typename T>
+struct XferItem {
+  LevelView f, c;
+  const T* in;
+  T* out;
+  Epi<T> ep;
+  T* E;
+  int64_t b0, nb;
+};
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS))
+    fam_rfine_batch(const XferItem<T>* __restrict__ items, int n, Mats<T> m) {
+  const XferItem<T>& it = items[batch_item(items, n)];
+  fam_rfine_at<DIM, K, T>(it.f, it.in, it.out, m, (int64_t)blockIdx.x - it.b0, it.nb);
+}
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS))
+    fam_restrict_batch(const XferItem<T>* __restrict__ items, int n, Mats<T> m) {
+  const XferItem<T>& it = items[batch_item(items, n)];
+  fam_restrict_at<DIM, K, T>(it.c, it.in, it.ep, it.E, m, (int64_t)blockIdx.x - it.b0, it.nb);
+}
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__(kBlock) fam_restrict0_batch(const XferItem<T>* __restrict__ items, int n,
+                                                              Mats<T> m) {
+  const XferItem<T>& it = items[batch_item(items, n)];
+  fam_restrict0_at<DIM, K, T>(it.f, it.in, it.E, m, (int64_t)blockIdx.x - it.b0, it.nb);
+}
+template <int DIM, int K, typename T>
+__global__ void __launch_bounds__((FamShape<DIM, K, T>::THREADS))
+    fam_prolong_batch(const XferItem<T>* __restrict__ items, int n, Mats<T> m) {
+  const XferItem<T>& it = items[batch_item(items, n)];
+  fam_prolong_at<DIM, K, T>(it.f, it.c, it.in, it.out, m, (int64_t)blockIdx.x - it.b0, it.nb);
 }
 
 // ------------------------------------------------------------------ transfers, 3D at k >= 3

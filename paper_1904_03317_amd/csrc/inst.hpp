@@ -263,13 +263,66 @@ struct Inst {
   }
 
   template <typename T>
+  static void xfer_batch(int kind, const dev::XferItem<T>* items, int n, int64_t blocks, const MatsH<T>& m,
+                         hipStream_t s) {
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      fail(GMG_E_STATE, "no batched transfers at this degree");
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      if (blocks <= 0) return;
+      const dim3 g((unsigned)blocks), b(S::THREADS);
+      switch (kind) {
+        case kXRFine:
+          hipLaunchKernelGGL((dev::fam_rfine_batch<DIM, K, T>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        case kXRestrict:
+          hipLaunchKernelGGL((dev::fam_restrict_batch<DIM, K, T>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        case kXRestrict0:
+          hipLaunchKernelGGL((dev::fam_restrict0_batch<DIM, K, T>), g, dim3(dev::kBlock), 0, s, items, n, to_dev(m));
+          return;
+        case kXProlong:
+          hipLaunchKernelGGL((dev::fam_prolong_batch<DIM, K, T>), g, b, 0, s, items, n, to_dev(m));
+          return;
+        default:
+          break;
+      }
+      fail(GMG_E_INVAL, "unknown transfer kind");
+    }
+  }
+  // blocks of one transfer launch (as restrict_fc, restrict0, prolong)
+  template <typename T>
+  static int64_t xfer_blocks(int kind, const LevelView& v) {
+    if (kind == kXRestrict0) return grid_for(v.n_fam);
+    if constexpr (dev::kCoopOp<DIM, K>) {
+      using S = dev::CoopShape<DIM, K, T>;
+      return (v.n_fam + S::FB - 1) / S::FB;
+    } else {
+      using S = dev::FamShape<DIM, K, T>;
+      return (v.n_fam + S::FB - 1) / S::FB;
+    }
+  }
+  static void leaf_t_batch(const dev::LeafItem* items, int n, int64_t blocks, size_t lds, const MatsH<double>& m,
+                           hipStream_t s) {
+    if constexpr (DIM == 3 && K >= 3) {
+      fail(GMG_E_STATE, "tiled leaf operator not built for 3D degree >= 3");
+    } else {
+      if (blocks <= 0) return;
+      hipLaunchKernelGGL((dev::leaf_tiles_batch<DIM, N>), dim3((unsigned)blocks), dim3(64), lds, s, items, n,
+                         to_dev(m));
+    }
+  }
+
+  template <typename T>
   static constexpr LevelOps<T> ops() {
     return LevelOps<T>{&op<T>,        &sum<T>,   &restrict_fc<T>,
                        &restrict0<T>, &prolong<T>, &cell_e<T>,
-                       dev::kCoopOp<DIM, K> ? nullptr : &op_batch<T>, &sum_batch<T>, &op_blocks<T>};
+                       dev::kCoopOp<DIM, K> ? nullptr : &op_batch<T>, &sum_batch<T>, &op_blocks<T>,
+                       dev::kCoopOp<DIM, K> ? nullptr : &xfer_batch<T>, &xfer_blocks<T>};
   }
   static const KernelTable* table() {
-    static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &leaf_t, &diag0};
+    static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &leaf_t, &diag0,
+                            (DIM == 3 && K >= 3) ? nullptr : &leaf_t_batch};
     return &t;
   }
 };

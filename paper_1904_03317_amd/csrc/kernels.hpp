@@ -49,12 +49,48 @@ struct Exact1D<3> {
 // Consecutive hardware dispatch goes round-robin over the 8 XCDs, each with
 // its own L2.  Give each XCD one contiguous range of the logical block space
 // so that neighbouring cells (which share nodes) hit the same L2.
-__device__ __forceinline__ int64_t xcd_block() {
-  const int64_t nb = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int64_t xcd_block_of(int64_t b, int64_t nb) {
   const int64_t q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
   return x * q + (x < r ? x : r) + i;
 }
+__device__ __forceinline__ int64_t xcd_block() { return xcd_block_of(blockIdx.x, gridDim.x); }
 __device__ __forceinline__ int64_t xcd_tid() { return xcd_block() * blockDim.x + threadIdx.x; }
+
+// ------------------------------------------------------------------ batched launches
+// Kernel bodies below take their block index b and grid size nb as
+// arguments, so that one launch can run the same body for several problems:
+// item i of a batched launch covers the blocks [b0_i, b0_i + nb_i) of the
+// grid and runs its body with b = blockIdx.x - b0_i.  Each item's blocks do
+// exactly what the blocks of its own launch would do (same results bit for
+// bit).
+
+// the item of this block (items in ascending b0, the first at 0)
+template <typename Item>
+__device__ __forceinline__ int batch_item(const Item* items, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (items[mid].b0 <= (int64_t)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// a body (a device function object called with (b, nb)) and its blocks
+template <class F>
+struct LaunchItem {
+  F f;
+  int64_t b0, nb;
+};
+
+template <class F, int TH>
+__global__ void __launch_bounds__(TH) run_items(const LaunchItem<F>* __restrict__ items, int n) {
+  const int i = batch_item(items, n);
+  const F f = items[i].f;
+  f((int64_t)blockIdx.x - items[i].b0, items[i].nb);
+}
 
 template <typename T>
 __device__ __forceinline__ void atomic_add(T* p, T v) {
@@ -687,12 +723,14 @@ constexpr int kLeafBlocks = 8192;  // grid of leaf_tiles at most (32 one-wave bl
 constexpr int kLeafGB = 16;        // tile nodes per lane whose loads are issued together
 
 template <int DIM, int N, bool MASS, bool DOT>
-__global__ void __launch_bounds__(64) leaf_tiles(LeafView v, const double* __restrict__ x, double* __restrict__ y,
-                                                 double* __restrict__ E, double* __restrict__ part, Mats<double> m) {
+__device__ __forceinline__ void leaf_tiles_at(const LeafView& v, const double* __restrict__ x,
+                                              double* __restrict__ y, double* __restrict__ E,
+                                              double* __restrict__ part, const Mats<double>& m, int64_t b,
+                                              int64_t G) {
   constexpr int NP = DIM == 3 ? N * N * N : N * N;
   HIP_DYNAMIC_SHARED(double, lds)
   const int lane = threadIdx.x;
-  const int64_t G = gridDim.x, lb = xcd_block();
+  const int64_t lb = xcd_block_of(b, G);
   const int64_t t0 = v.n_tiles * lb / G, t1 = v.n_tiles * (lb + 1) / G;
   double dot = 0.0;
   for (int64_t t = t0; t < t1; ++t) {
@@ -789,8 +827,29 @@ __global__ void __launch_bounds__(64) leaf_tiles(LeafView v, const double* __res
   }
   if (DOT) {
     for (int o = 32; o > 0; o >>= 1) dot += __shfl_down(dot, o, 64);
-    if (lane == 0) part[blockIdx.x] = dot;
+    if (lane == 0) part[b] = dot;
   }
+}
+template <int DIM, int N, bool MASS, bool DOT>
+__global__ void __launch_bounds__(64) leaf_tiles(LeafView v, const double* __restrict__ x, double* __restrict__ y,
+                                                 double* __restrict__ E, double* __restrict__ part, Mats<double> m) {
+  leaf_tiles_at<DIM, N, MASS, DOT>(v, x, y, E, part, m, blockIdx.x, gridDim.x);
+}
+
+// the tiled leaf operator of several problems in one launch (q = A p with
+// the partial sums of p.q, as leaf_tiles<DIM, N, false, true>)
+struct LeafItem {
+  LeafView v;
+  const double* x;
+  double* y;
+  double* E;
+  double* part;
+  int64_t b0, nb;
+};
+template <int DIM, int N>
+__global__ void __launch_bounds__(64) leaf_tiles_batch(const LeafItem* __restrict__ items, int n, Mats<double> m) {
+  const LeafItem& it = items[batch_item(items, n)];
+  leaf_tiles_at<DIM, N, false, true>(it.v, it.x, it.y, it.E, it.part, m, (int64_t)blockIdx.x - it.b0, it.nb);
 }
 
 // In-cell constraints of one node, gathered (3D, used by the cooperative
@@ -1129,9 +1188,12 @@ __global__ void make_dinv(int64_t n, const double* __restrict__ diag, const uint
 
 // ------------------------------------------------------------------ vectors
 template <typename T>
+__device__ __forceinline__ void fill_at(int64_t n, T* __restrict__ p, T v, int64_t b, int64_t nb) {
+  for (int64_t i = b * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) p[i] = v;
+}
+template <typename T>
 __global__ void fill(int64_t n, T* __restrict__ p, T v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
+  fill_at(n, p, v, blockIdx.x, gridDim.x);
 }
 
 // t = x on the rows whose flag is want, 0 elsewhere (t may alias x)
@@ -1145,9 +1207,10 @@ __global__ void mask_rows(int64_t n, const uint8_t* __restrict__ flags, int want
 // t = 0.  zero_start: d = c2 D^{-1} g; x = d (first step from x = 0).
 // Rows that are not smoothed have D^{-1} = 0 and keep d = 0.
 template <typename T>
-__global__ void cheb_step(int64_t n, T* __restrict__ x, T* __restrict__ d, const T* __restrict__ g,
-                          T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2, int zero_start) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cheb_step_at(int64_t n, T* __restrict__ x, T* __restrict__ d,
+                                             const T* __restrict__ g, T* __restrict__ t,
+                                             const T* __restrict__ dinv, T c1, T c2, int zero_start, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T di = dinv[i];
   if (zero_start) {
@@ -1161,19 +1224,34 @@ __global__ void cheb_step(int64_t n, T* __restrict__ x, T* __restrict__ d, const
     t[i] = T(0);
   }
 }
-
 template <typename T>
-__global__ void copy_to_levels(int64_t n, const int32_t* __restrict__ copy, const double* __restrict__ r,
-                               T* __restrict__ lg) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) lg[copy[i]] = T(r[i]);
+__global__ void cheb_step(int64_t n, T* __restrict__ x, T* __restrict__ d, const T* __restrict__ g,
+                          T* __restrict__ t, const T* __restrict__ dinv, T c1, T c2, int zero_start) {
+  cheb_step_at(n, x, d, g, t, dinv, c1, c2, zero_start, blockIdx.x);
 }
 
 template <typename T>
+__device__ __forceinline__ void copy_to_levels_at(int64_t n, const int32_t* __restrict__ copy,
+                                                  const double* __restrict__ r, T* __restrict__ lg, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
+  if (i < n) lg[copy[i]] = T(r[i]);
+}
+template <typename T>
+__global__ void copy_to_levels(int64_t n, const int32_t* __restrict__ copy, const double* __restrict__ r,
+                               T* __restrict__ lg) {
+  copy_to_levels_at(n, copy, r, lg, blockIdx.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void copy_from_levels_at(int64_t n, const int32_t* __restrict__ copy,
+                                                    const T* __restrict__ lx, double* __restrict__ z, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = double(lx[copy[i]]);
+}
+template <typename T>
 __global__ void copy_from_levels(int64_t n, const int32_t* __restrict__ copy, const T* __restrict__ lx,
                                  double* __restrict__ z) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] = double(lx[copy[i]]);
+  copy_from_levels_at(n, copy, lx, z, blockIdx.x);
 }
 
 // z = level solution read back through the copy map, fused with the partial
@@ -1186,9 +1264,9 @@ __global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const 
 
 // exact coarse solve: x0[S] = A0^{-1} d0[S] (FP64), other rows of x0 zero
 template <typename T>
-__global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, const double* __restrict__ ainv,
-                                                       const int32_t* __restrict__ idx, const T* __restrict__ d0,
-                                                       T* __restrict__ x0) {
+__device__ __forceinline__ void coarse_solve_at(int n_nodes, int n0, const double* __restrict__ ainv,
+                                                const int32_t* __restrict__ idx, const T* __restrict__ d0,
+                                                T* __restrict__ x0) {
   HIP_DYNAMIC_SHARED(double, sd)
   for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) x0[i] = T(0);
   for (int i = threadIdx.x; i < n0; i += blockDim.x) sd[i] = double(d0[idx[i]]);
@@ -1198,6 +1276,12 @@ __global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, cons
     for (int j = 0; j < n0; ++j) s += ainv[(int64_t)i * n0 + j] * sd[j];
     x0[idx[i]] = T(s);
   }
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) coarse_solve(int n_nodes, int n0, const double* __restrict__ ainv,
+                                                       const int32_t* __restrict__ idx, const T* __restrict__ d0,
+                                                       T* __restrict__ x0) {
+  coarse_solve_at(n_nodes, n0, ainv, idx, d0, x0);
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -1217,13 +1301,19 @@ __device__ __forceinline__ T seg_sum(const int32_t* __restrict__ off, const T* _
 
 // residual r = g - A x on free rows, 0 on Dirichlet rows (use_e = 0: A x = 0)
 template <typename T>
-__global__ void seg_residual(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
-                             const T* __restrict__ g, const uint8_t* __restrict__ flags, T* __restrict__ r,
-                             int use_e) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void seg_residual_at(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
+                                                const T* __restrict__ g, const uint8_t* __restrict__ flags,
+                                                T* __restrict__ r, int use_e, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T y = use_e ? seg_sum(off, E, i) : T(0);
   r[i] = flags[i] == 2 ? T(0) : g[i] - y;
+}
+template <typename T>
+__global__ void seg_residual(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
+                             const T* __restrict__ g, const uint8_t* __restrict__ flags, T* __restrict__ r,
+                             int use_e) {
+  seg_residual_at(n, off, E, g, flags, r, use_e, blockIdx.x);
 }
 
 template <typename T>
@@ -1235,10 +1325,11 @@ __global__ void seg_plain(int64_t n, const int32_t* __restrict__ off, const T* _
 // g += restricted contributions; then the first Chebyshev step from x = 0:
 // d = c2 D^{-1} g, x = d
 template <typename T>
-__global__ void seg_restrict_start(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
-                                   T* __restrict__ g, T* __restrict__ x, T* __restrict__ d,
-                                   const T* __restrict__ dinv, T c2, int smooth) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void seg_restrict_start_at(int64_t n, const int32_t* __restrict__ off,
+                                                      const T* __restrict__ E, T* __restrict__ g, T* __restrict__ x,
+                                                      T* __restrict__ d, const T* __restrict__ dinv, T c2,
+                                                      int smooth, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T gi = g[i] + seg_sum(off, E, i);
   g[i] = gi;
@@ -1247,6 +1338,12 @@ __global__ void seg_restrict_start(int64_t n, const int32_t* __restrict__ off, c
     d[i] = v;
     x[i] = v;
   }
+}
+template <typename T>
+__global__ void seg_restrict_start(int64_t n, const int32_t* __restrict__ off, const T* __restrict__ E,
+                                   T* __restrict__ g, T* __restrict__ x, T* __restrict__ d,
+                                   const T* __restrict__ dinv, T c2, int smooth) {
+  seg_restrict_start_at(n, off, E, g, x, d, dinv, c2, smooth, blockIdx.x);
 }
 
 #ifdef GMG_SOLVER_TU
@@ -1289,8 +1386,8 @@ __global__ void __launch_bounds__(kBlock) dot_partial(int64_t n, const double* _
 enum ScalarSlot { kRho = 0, kRhoOld, kAlpha, kBeta, kPq, kRr, kBb, kFirst, kNumScalars };
 
 // sums the partials (fixed order) and updates the CG scalars
-__global__ void __launch_bounds__(kBlock) cg_scalars(int nparts, const double* __restrict__ part,
-                                                     double* __restrict__ sc, int op) {
+__device__ __forceinline__ void cg_scalars_at(int nparts, const double* __restrict__ part,
+                                              double* __restrict__ sc, int op) {
   double v = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[i];
   v = block_sum(v);
@@ -1309,28 +1406,42 @@ __global__ void __launch_bounds__(kBlock) cg_scalars(int nparts, const double* _
     sc[kBb] = v;
   }
 }
+__global__ void __launch_bounds__(kBlock) cg_scalars(int nparts, const double* __restrict__ part,
+                                                     double* __restrict__ sc, int op) {
+  cg_scalars_at(nparts, part, sc, op);
+}
 
-__global__ void update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z,
-                         const double* __restrict__ sc) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void update_p_at(int64_t n, double* __restrict__ p, const double* __restrict__ z,
+                                            const double* __restrict__ sc, int64_t b) {
+  const int64_t i = b * blockDim.x + threadIdx.x;
   const double beta = sc[kBeta];
   if (i < n) p[i] = z[i] + beta * p[i];
 }
+__global__ void update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z,
+                         const double* __restrict__ sc) {
+  update_p_at(n, p, z, sc, blockIdx.x);
+}
 
 // x += alpha p ; r -= alpha q ; partial sums of r.r with the dot's grid
-__global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
-                                                    const double* __restrict__ sc, double* __restrict__ part) {
+__device__ __forceinline__ void update_xr_at(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                             const double* __restrict__ p, const double* __restrict__ q,
+                                             const double* __restrict__ sc, double* __restrict__ part, int64_t b,
+                                             int64_t nb) {
   const double alpha = sc[kAlpha];
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = b * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     s += ri * ri;
   }
   s = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[b] = s;
+}
+__global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ sc, double* __restrict__ part) {
+  update_xr_at(n, x, r, p, q, sc, part, blockIdx.x, gridDim.x);
 }
 
 // nodes per thread of the kernels fused with a dot product (kFuseNPT
@@ -1342,13 +1453,13 @@ constexpr int kFuseNPT = 8;
 // the tiles touching them and constrained contributions, in ascending slot
 // order), Dirichlet rows zero; DOT: partial sums of p.q per block
 template <bool DOT>
-__global__ void __launch_bounds__(kBlock) leaf_pass2(LeafView v, const double* __restrict__ E,
-                                                     const double* __restrict__ x, double* __restrict__ y,
-                                                     double* __restrict__ part) {
+__device__ __forceinline__ void leaf_pass2_at(const LeafView& v, const double* __restrict__ E,
+                                              const double* __restrict__ x, double* __restrict__ y,
+                                              double* __restrict__ part, int64_t b) {
   // the first kP2S slots of every node unrolled, so that the loads of all
   // nodes of a thread issue together; longer lists (rare) continue in a loop
   constexpr int kP2S = 4;
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kFuseNPT + threadIdx.x;
+  const int64_t base = b * blockDim.x * kFuseNPT + threadIdx.x;
   int32_t d[kFuseNPT], o0[kFuseNPT], o1[kFuseNPT];
 #pragma unroll
   for (int k = 0; k < kFuseNPT; ++k) {
@@ -1382,8 +1493,14 @@ __global__ void __launch_bounds__(kBlock) leaf_pass2(LeafView v, const double* _
   }
   if (DOT) {
     s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[b] = s;
   }
+}
+template <bool DOT>
+__global__ void __launch_bounds__(kBlock) leaf_pass2(LeafView v, const double* __restrict__ E,
+                                                     const double* __restrict__ x, double* __restrict__ y,
+                                                     double* __restrict__ part) {
+  leaf_pass2_at<DOT>(v, E, x, y, part, blockIdx.x);
 }
 
 // leaf operator, pass 2, fused with the partial sums of p.q
@@ -1407,11 +1524,11 @@ __global__ void __launch_bounds__(kBlock) seg_dir_dot(int64_t n, const int32_t* 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const int32_t* __restrict__ copy,
-                                                               const T* __restrict__ lx, double* __restrict__ z,
-                                                               const double* __restrict__ r,
-                                                               double* __restrict__ part) {
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kFuseNPT + threadIdx.x;
+__device__ __forceinline__ void copy_from_levels_dot_at(int64_t n, const int32_t* __restrict__ copy,
+                                                        const T* __restrict__ lx, double* __restrict__ z,
+                                                        const double* __restrict__ r, double* __restrict__ part,
+                                                        int64_t b) {
+  const int64_t base = b * blockDim.x * kFuseNPT + threadIdx.x;
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < kFuseNPT; ++k) {
@@ -1423,7 +1540,14 @@ __global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const 
     }
   }
   s = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[b] = s;
+}
+template <typename T>
+__global__ void __launch_bounds__(kBlock) copy_from_levels_dot(int64_t n, const int32_t* __restrict__ copy,
+                                                               const T* __restrict__ lx, double* __restrict__ z,
+                                                               const double* __restrict__ r,
+                                                               double* __restrict__ part) {
+  copy_from_levels_dot_at(n, copy, lx, z, r, part, blockIdx.x);
 }
 
 __global__ void copy_vec(int64_t n, const double* __restrict__ a, double* __restrict__ b) {

@@ -108,6 +108,12 @@ bool cg_poll(Problem& P, bool block);
 int cg_check(Problem& P, bool block);
 void cg_enqueue_tail(Problem& P, hipStream_t s);
 void cg_enqueue_iteration(Problem& P);  // preconditioner and tail on the CG stream
+// The next CG iteration of every problem of ps (each with its iteration due,
+// cg_check having returned 2), each step one launch over all of them on s:
+// the batched V-cycle z = B r, then the rest of the iteration; each
+// problem's iteration event is recorded on s.  Tables as vcycle_batch.
+void cg_iteration_batch(const std::vector<Problem*>& ps, char* d_table, size_t table_bytes, size_t* need,
+                        char* h_stage, hipStream_t s, hipEvent_t staged = nullptr);
 void set_constant(double* p, int64_t n, double v, hipStream_t s);
 void apply_level_hook(Problem& P, int level, int variant, const void* x, void* y, hipStream_t s);
 

@@ -3,20 +3,23 @@
 // it arrives; the scheduler thread admits ready requests whenever a slot and
 // enough arena memory are free (first fit), binds them (upload and device
 // set-up on the slot's stream), and then advances every resident solve by
-// one CG iteration per tick.  The V-cycles of the requests whose next
-// iteration is due in a tick, grouped by dimension, degree, precision and
-// smoother, run as one batched V-cycle on the batch stream: each smoothing
-// step, residual and restriction pass of a level is one launch over that
-// level of all of them, so that a tick of K small requests costs the launches
-// of one V-cycle and fills the device with the blocks of all K; the rest of
-// each CG iteration follows on the request's own slot stream.  A request
-// alone in its group (or with batching off) replays its V-cycle as a
-// captured HIP graph on its slot stream.  Requests leave when their residual reaches the tolerance and
-// their memory and slot go to the next ones (continuous batching at CG
-// iteration granularity).  All kernels are deterministic, so a result does
-// not depend on what else was resident.  A finished solution is copied back
-// into a pinned host buffer of the request on its slot stream; the scheduler
-// keeps ticking the other requests and completes the copy on a later tick.
+// one CG iteration per tick.  The requests whose next iteration is due in a
+// tick, grouped by dimension, degree, precision and smoother, run it as one
+// batched iteration on the batch stream: every step of the V-cycle (each
+// smoothing step, residual, restriction and prolongation of a level, the
+// coarse solves) and of the rest of the CG iteration is one launch over all
+// of them, so that a tick of K requests costs the launches of one iteration
+// and fills the device with the blocks of all K.  The members of a batch are
+// next checked together, once all of them finished, so that a group stays
+// in step.  A request alone in its group (or with batching off) replays its
+// V-cycle as a captured HIP graph on its own slot stream.  Requests leave
+// when their residual reaches the tolerance and their memory and slot go to
+// the next ones (continuous batching at CG iteration granularity).  All
+// kernels are deterministic and a batched launch computes what the
+// request's own launches would, so a result does not depend on what else
+// was resident.  A finished solution is copied back into a pinned host
+// buffer of the request on its slot stream; the scheduler keeps ticking the
+// other requests and completes the copy on a later tick.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,6 +148,10 @@ struct Server {
   hipEvent_t ev_batch = nullptr;
   int stage_next = 0;
   int64_t iterations = 0, batched_iterations = 0, batches = 0;
+  // members of batched iterations still in flight: none of them is checked
+  // before all of them have finished, so that a group stays in step and
+  // its next V-cycles are batched again
+  std::vector<std::vector<Request*>> inflight;
   std::vector<int> slot_free;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -303,24 +310,16 @@ void worker_loop(Server* S) {
   }
 }
 
-// The next CG iteration of each request of `due` (all of one group), its
-// V-cycle batched; requests whose iteration could not be enqueued are added
-// to `failed` with their error.
+// The next CG iteration of each request of `due` (all of one group) as one
+// batched iteration on the batch stream; requests whose iteration could not
+// be enqueued are added to `failed` with their error.
 void enqueue_batch(Server& S, const std::vector<Request*>& due,
                    std::vector<std::tuple<Request*, int, std::string>>& failed) {
   std::vector<Problem*> ps;
-  std::vector<const double*> rs;
-  std::vector<double*> zs;
-  for (Request* r : due) {
-    ps.push_back(r->P.get());
-    rs.push_back(r->P->cr);
-    zs.push_back(r->P->cz);
-  }
-  const int k = S.stage_next;
-  S.stage_next ^= 1;
+  for (Request* r : due) ps.push_back(r->P.get());
   size_t need = 0;
   try {
-    vcycle_batch(ps, rs.data(), zs.data(), nullptr, 0, &need, nullptr, S.bstream, true);
+    cg_iteration_batch(ps, nullptr, 0, &need, nullptr, S.bstream);
     if (need > S.table_bytes) {
       // tables of the whole group do not fit: two halves in turn
       if (due.size() >= 2) {
@@ -333,26 +332,43 @@ void enqueue_batch(Server& S, const std::vector<Request*>& due,
       ++S.iterations;
       return;
     }
+    const int k = S.stage_next;
+    S.stage_next ^= 1;
     SRV_HIPCHECK(hipEventSynchronize(S.ev_stage[k]));  // the previous upload from this buffer has read it
-    vcycle_batch(ps, rs.data(), zs.data(), S.d_table, S.table_bytes, &need, S.h_stage[k], S.bstream, true,
-                 S.ev_stage[k]);
-    SRV_HIPCHECK(hipEventRecord(S.ev_batch, S.bstream));
+    cg_iteration_batch(ps, S.d_table, S.table_bytes, &need, S.h_stage[k], S.bstream, S.ev_stage[k]);
   } catch (const Error& e) {
+    // nothing of the failed requests may still run when their memory is
+    // handed on
+    (void)hipStreamSynchronize(S.bstream);
+    (void)hipGetLastError();
     for (Request* r : due) failed.emplace_back(r, e.code, e.what());
     return;
   }
   ++S.batches;
-  for (Request* r : due) {
-    try {
-      hipStream_t s = S.streams[r->slot];
-      SRV_HIPCHECK(hipStreamWaitEvent(s, S.ev_batch, 0));
-      cg_enqueue_tail(*r->P, s);
-      ++S.iterations;
-      ++S.batched_iterations;
-    } catch (const Error& e) {
-      failed.emplace_back(r, e.code, e.what());
+  S.iterations += (int64_t)due.size();
+  S.batched_iterations += (int64_t)due.size();
+  S.inflight.push_back(due);
+}
+
+// requests of batched iterations whose batch has not finished yet (the
+// others' batches are dropped from the in-flight list)
+std::vector<Request*> gated(Server& S) {
+  std::vector<Request*> out;
+  for (size_t b = 0; b < S.inflight.size();) {
+    bool all = true;
+    for (Request* r : S.inflight[b])
+      if (hipEventQuery(r->P->ev[4]) == hipErrorNotReady) {
+        all = false;
+        break;
+      }
+    if (all) {
+      S.inflight.erase(S.inflight.begin() + b);
+    } else {
+      out.insert(out.end(), S.inflight[b].begin(), S.inflight[b].end());
+      ++b;
     }
   }
+  return out;
 }
 
 void scheduler_loop(Server* S) {
@@ -414,7 +430,9 @@ void scheduler_loop(Server* S) {
     // requests whose next iteration is due, by kernel set, precision,
     // Chebyshev degree and smoother
     std::map<std::tuple<const void*, int, int, int>, std::vector<Request*>> due;
+    const std::vector<Request*> wait = gated(*S);
     for (Request* r : run) {
+      if (std::find(wait.begin(), wait.end(), r) != wait.end()) continue;
       try {
         const int st = cg_check(*r->P, false);
         if (st == 0) continue;

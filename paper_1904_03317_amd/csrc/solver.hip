@@ -892,9 +892,12 @@ void vcycle_noalloc(Problem& P, const double* r, double* z, hipStream_t s) {
 // logical block it gets alone, so each result equals the solo V-cycle's bit
 // for bit.
 namespace {
+// A batched V-cycle (or CG iteration) as a host image of its launch tables
+// and the launches that read them, in order (argument: the device address
+// of the tables).
 struct BatchPlan {
-  std::vector<char> blob;                                  // host image of the item tables
-  std::vector<std::function<void(const char*)>> q;         // launches, in order (argument: device table)
+  std::vector<char> blob;
+  std::vector<std::function<void(const char*)>> q;
   template <typename Item>
   size_t put(const std::vector<Item>& items) {
     const size_t off = (blob.size() + 255) & ~size_t(255);
@@ -903,6 +906,103 @@ struct BatchPlan {
     return off;
   }
 };
+
+// the items of one batched launch of a kernel body (a device function
+// object called with its block index and grid size)
+template <class F>
+struct Launch {
+  std::vector<dev::LaunchItem<F>> items;
+  int64_t blocks = 0;
+  size_t shmem = 0;
+  void add(const F& f, int64_t nb) {
+    if (nb <= 0) return;
+    items.push_back(dev::LaunchItem<F>{f, blocks, nb});
+    blocks += nb;
+  }
+  template <int TH = dev::kBlock>
+  void emit(BatchPlan& B, hipStream_t s) const {
+    if (items.empty()) return;
+    const size_t off = B.put(items);
+    const int n = (int)items.size();
+    const int64_t nb = blocks;
+    const size_t sh = shmem;
+    B.q.push_back([=](const char* t) {
+      hipLaunchKernelGGL((dev::run_items<F, TH>), dim3((unsigned)nb), dim3(TH), sh, s,
+                         (const dev::LaunchItem<F>*)(t + off), n);
+    });
+  }
+};
+
+// batched transfers of one kind
+template <typename T>
+struct Xfer {
+  std::vector<dev::XferItem<T>> items;
+  int64_t blocks = 0;
+  void add(dev::XferItem<T> it, int64_t nb) {
+    if (nb <= 0) return;
+    it.b0 = blocks;
+    it.nb = nb;
+    items.push_back(it);
+    blocks += nb;
+  }
+  void emit(BatchPlan& B, const LevelOps<T>& op, int kind, const MatsH<T>& mt, hipStream_t s) const {
+    if (items.empty()) return;
+    const size_t off = B.put(items);
+    const int n = (int)items.size();
+    const int64_t nb = blocks;
+    const LevelOps<T>* o = &op;
+    B.q.push_back([=](const char* t) { o->xfer_batch(kind, (const dev::XferItem<T>*)(t + off), n, nb, mt, s); });
+  }
+};
+
+// kernel bodies of the batched launches (device function objects)
+template <typename T>
+auto fill_body(int64_t n, T* p, T v) {
+  return [=] __device__(int64_t b, int64_t nb) { dev::fill_at(n, p, v, b, nb); };
+}
+template <typename T>
+auto copy_to_body(int64_t n, const int32_t* copy, const double* r, T* g) {
+  return [=] __device__(int64_t b, int64_t) { dev::copy_to_levels_at(n, copy, r, g, b); };
+}
+template <typename T>
+auto cheb_body(int64_t n, T* x, T* d, const T* g, T* t, const T* dinv, T c1, T c2, int zero_start) {
+  return [=] __device__(int64_t b, int64_t) { dev::cheb_step_at(n, x, d, g, t, dinv, c1, c2, zero_start, b); };
+}
+template <typename T>
+auto residual_body(int64_t n, const T* E, const T* g, const uint8_t* flags, T* r) {
+  return [=] __device__(int64_t b, int64_t) {
+    dev::seg_residual_at(n, (const int32_t*)nullptr, E, g, flags, r, 0, b);
+  };
+}
+template <typename T>
+auto rstart0_body(int64_t n, const int32_t* off, const T* E, T* g, T* x, T* d, const T* dinv) {
+  return [=] __device__(int64_t b, int64_t) { dev::seg_restrict_start_at(n, off, E, g, x, d, dinv, T(0), 0, b); };
+}
+template <typename T>
+auto coarse_body(int n_nodes, int n0, const double* ainv, const int32_t* idx, const T* d0, T* x0) {
+  return [=] __device__(int64_t, int64_t) { dev::coarse_solve_at(n_nodes, n0, ainv, idx, d0, x0); };
+}
+template <typename T>
+auto copy_from_body(int64_t n, const int32_t* copy, const T* lx, double* z) {
+  return [=] __device__(int64_t b, int64_t) { dev::copy_from_levels_at(n, copy, lx, z, b); };
+}
+template <typename T>
+auto copy_from_dot_body(int64_t n, const int32_t* copy, const T* lx, double* z, const double* r, double* part) {
+  return [=] __device__(int64_t b, int64_t) { dev::copy_from_levels_dot_at(n, copy, lx, z, r, part, b); };
+}
+auto scalars_body(int nparts, const double* part, double* sc, int op) {
+  return [=] __device__(int64_t, int64_t) { dev::cg_scalars_at(nparts, part, sc, op); };
+}
+auto update_p_body(int64_t n, double* p, const double* z, const double* sc) {
+  return [=] __device__(int64_t b, int64_t) { dev::update_p_at(n, p, z, sc, b); };
+}
+auto update_xr_body(int64_t n, double* x, double* r, const double* p, const double* q, const double* sc,
+                    double* part) {
+  return [=] __device__(int64_t b, int64_t nb) { dev::update_xr_at(n, x, r, p, q, sc, part, b, nb); };
+}
+auto pass2_body(LeafView v, const double* E, const double* x, double* y, double* part) {
+  return [=] __device__(int64_t b, int64_t) { dev::leaf_pass2_at<true>(v, E, x, y, part, b); };
+}
 }  // namespace
 
 template <typename T>
@@ -913,6 +1013,7 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
   const MatsH<T> mt = mats<T>(*ps[0]);
   const int dim = ps[0]->maps->dim;
   const int m = ps[0]->opt.cheb_degree;
+  const bool xb = op.xfer_batch != nullptr;
   int Lmax = 0;
   for (Problem* P : ps) Lmax = std::max(Lmax, (int)P->lv.size() - 1);
   auto level_of = [](Problem* P) { return (int)P->lv.size() - 1; };
@@ -963,23 +1064,28 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
     const size_t so = B.put(si);
     B.q.push_back([=, &op](const char* t) { op.sum_batch((const dev::SumItem<T>*)(t + so), n, sb, epi, s); });
   };
-  // leaf residual into the levels, first pre-smoothing step on the finest level
-  for (int i = 0; i < np; ++i) {
-    Problem* P = ps[i];
-    const int L = level_of(P);
-    const double* ri = r ? r[i] : nullptr;  // r, z: NULL when only the table size is asked for
-    const T s1 = L >= 1 ? T(step_coef(*P, L, 1).c2) : T(0);
-    B.q.push_back([=](const char*) {
+  // residual into the levels, first pre-smoothing step on each finest level
+  {
+    Launch<decltype(fill_body<T>(0, nullptr, T(0)))> lf;
+    Launch<decltype(copy_to_body<T>(0, nullptr, nullptr, nullptr))> lc;
+    Launch<decltype(cheb_body<T>(0, nullptr, nullptr, nullptr, nullptr, nullptr, T(0), T(0), 0))> lh;
+    for (int i = 0; i < np; ++i) {
+      Problem* P = ps[i];
+      const int L = level_of(P);
       const int64_t N = P->maps->n_dofs;
       T *X = (T*)P->lx, *G = (T*)P->lg, *R = (T*)P->lt, *Dd = (T*)P->ld, *Di = (T*)P->ldinv;
-      fill_dev(G, P->n_total, T(0), s);
-      hipLaunchKernelGGL(dev::copy_to_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P->copy, ri, G);
+      lf.add(fill_body<T>(P->n_total, G, T(0)), std::min<int64_t>(4096, grid1(P->n_total)));
+      lc.add(copy_to_body<T>(N, P->copy, r ? r[i] : nullptr, G), grid1(N));
       if (L >= 1) {
         DevLevel& V = P->lv[L];
-        hipLaunchKernelGGL(dev::cheb_step<T>, dim3(grid1(V.v.n_dofs)), dim3(dev::kBlock), 0, s, V.v.n_dofs,
-                           X + V.off, Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0), s1, 1);
+        lh.add(cheb_body<T>(V.v.n_dofs, X + V.off, Dd + V.off, G + V.off, R + V.off, Di + V.off, T(0),
+                            T(step_coef(*P, L, 1).c2), 1),
+               grid1(V.v.n_dofs));
       }
-    });
+    }
+    lf.emit(B, s);
+    lc.emit(B, s);
+    lh.emit(B, s);
   }
   for (int l = Lmax; l >= 1; --l) {
     std::vector<int> act, sm;
@@ -990,6 +1096,9 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
       }
     for (int j = 2; j <= m; ++j) sweep(l, dev::kEpiCheb, j, sm);
     sweep(l, dev::kEpiResid, 0, sm);
+    Launch<decltype(residual_body<T>(0, nullptr, nullptr, nullptr, nullptr))> lres;
+    Launch<decltype(rstart0_body<T>(0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr))> lrs0;
+    Xfer<T> xf, xc, x0;
     std::vector<dev::SumItem<T>> rs;
     int64_t rb = 0;
     for (int i : act) {
@@ -998,13 +1107,7 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
       DevLevel& W = P->lv[l - 1];
       T *X = (T*)P->lx, *G = (T*)P->lg, *R = (T*)P->lt, *Dd = (T*)P->ld, *Di = (T*)P->ldinv;
       T* E = (T*)P->E;
-      if (V.n_S == 0) {
-        const int64_t n = V.v.n_dofs;
-        B.q.push_back([=](const char*) {
-          hipLaunchKernelGGL(dev::seg_residual<T>, dim3(grid1(n)), dim3(dev::kBlock), 0, s, n,
-                             (const int32_t*)nullptr, (const T*)E, G + V.off, V.v.flags, R + V.off, 0);
-        });
-      }
+      if (V.n_S == 0) lres.add(residual_body<T>(V.v.n_dofs, E, G + V.off, V.v.flags, R + V.off), grid1(V.v.n_dofs));
       if (l - 1 >= 1) {
         dev::Epi<T> ep;
         ep.x = X + W.off;
@@ -1017,19 +1120,46 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
         const LevelView fv = V.v, cv = W.v;
         T* rbuf = (T*)P->rbuf;
         const T* rin = R + V.off;
-        B.q.push_back([=, &op](const char*) { op.restrict_fc(fv, cv, rin, ep, rbuf, E, mt, s); });
+        if (xb) {
+          dev::XferItem<T> a{};
+          a.f = fv;
+          a.in = rin;
+          a.out = rbuf;
+          xf.add(a, fv.n_fam ? op.xfer_blocks(kXRFine, fv) : 0);
+          dev::XferItem<T> c{};
+          c.c = cv;
+          c.in = rbuf;
+          c.ep = ep;
+          c.E = E;
+          xc.add(c, cv.n_fam ? op.xfer_blocks(kXRestrict, cv) : 0);
+        } else {
+          B.q.push_back([=, &op](const char*) { op.restrict_fc(fv, cv, rin, ep, rbuf, E, mt, s); });
+        }
         rs.push_back(dev::SumItem<T>{W.v, ep, (const T*)E, rb});
         rb += (W.v.shn[dim + 1] + dev::kBlock - 1) / dev::kBlock;
       } else {
         const LevelView fv = V.v, cv = W.v;
         const T* rin = R + V.off;
-        B.q.push_back([=, &op](const char*) {
-          op.restrict0(fv, rin, E, mt, s);
-          hipLaunchKernelGGL(dev::seg_restrict_start<T>, dim3(grid1(cv.n_dofs)), dim3(dev::kBlock), 0, s,
-                             cv.n_dofs, cv.roff, (const T*)E, G + W.off, X + W.off, Dd + W.off, Di + W.off, T(0), 0);
-        });
+        if (xb) {
+          dev::XferItem<T> a{};
+          a.f = fv;
+          a.in = rin;
+          a.E = E;
+          x0.add(a, fv.n_fam ? op.xfer_blocks(kXRestrict0, fv) : 0);
+        } else {
+          B.q.push_back([=, &op](const char*) { op.restrict0(fv, rin, E, mt, s); });
+        }
+        lrs0.add(rstart0_body<T>(cv.n_dofs, cv.roff, E, G + W.off, X + W.off, Dd + W.off, Di + W.off),
+                 grid1(cv.n_dofs));
       }
     }
+    lres.emit(B, s);
+    // the restriction launches after every residual of the level (the
+    // non-batched ones were queued per problem above, in order)
+    xf.emit(B, op, kXRFine, mt, s);
+    xc.emit(B, op, kXRestrict, mt, s);
+    x0.emit(B, op, kXRestrict0, mt, s);
+    lrs0.emit(B, s);
     if (!rs.empty()) {
       const size_t so = B.put(rs);
       const int n = (int)rs.size();
@@ -1038,49 +1168,139 @@ static void plan_vcycle_batch(const std::vector<Problem*>& ps, const double* con
       });
     }
   }
-  for (int i = 0; i < np; ++i) {
-    Problem* P = ps[i];
-    B.q.push_back([=](const char*) {
-      hipLaunchKernelGGL(dev::coarse_solve<T>, dim3(1), dim3(dev::kBlock), P->n0 * sizeof(double), s,
-                         (int)P->lv[0].v.n_dofs, P->n0, P->ainv, P->cidx, (T*)P->lg + P->lv[0].off,
-                         (T*)P->lx + P->lv[0].off);
-    });
+  {
+    Launch<decltype(coarse_body<T>(0, 0, nullptr, nullptr, nullptr, nullptr))> lco;
+    for (int i = 0; i < np; ++i) {
+      Problem* P = ps[i];
+      lco.add(coarse_body<T>((int)P->lv[0].v.n_dofs, P->n0, P->ainv, P->cidx, (T*)P->lg + P->lv[0].off,
+                             (T*)P->lx + P->lv[0].off),
+              1);
+      lco.shmem = std::max(lco.shmem, size_t(P->n0) * sizeof(double));
+    }
+    lco.emit(B, s);
   }
   for (int l = 1; l <= Lmax; ++l) {
     std::vector<int> sm;
+    Xfer<T> xp;
     for (int i = 0; i < np; ++i) {
       Problem* P = ps[i];
       if (level_of(P) < l) continue;
       const LevelView fv = P->lv[l].v, cv = P->lv[l - 1].v;
       T* X = (T*)P->lx;
       const int64_t fo = P->lv[l].off, co = P->lv[l - 1].off;
-      B.q.push_back([=, &op](const char*) { op.prolong(fv, cv, X + co, X + fo, mt, s); });
+      if (xb) {
+        dev::XferItem<T> a{};
+        a.f = fv;
+        a.c = cv;
+        a.in = X + co;
+        a.out = X + fo;
+        xp.add(a, fv.n_fam ? op.xfer_blocks(kXProlong, fv) : 0);
+      } else {
+        B.q.push_back([=, &op](const char*) { op.prolong(fv, cv, X + co, X + fo, mt, s); });
+      }
       if (P->lv[l].n_S > 0) sm.push_back(i);
     }
+    xp.emit(B, op, kXProlong, mt, s);
     for (int j = 1; j <= m; ++j) sweep(l, dev::kEpiCheb, j, sm);
   }
+  if (dot_rz) {
+    Launch<decltype(copy_from_dot_body<T>(0, nullptr, nullptr, nullptr, nullptr, nullptr))> lz;
+    for (int i = 0; i < np; ++i) {
+      Problem* P = ps[i];
+      const int64_t N = P->maps->n_dofs;
+      lz.add(copy_from_dot_body<T>(N, P->copy, (const T*)P->lx, z ? z[i] : nullptr, r ? r[i] : nullptr, P->part),
+             fuse_grid(N));
+    }
+    lz.emit(B, s);
+  } else {
+    Launch<decltype(copy_from_body<T>(0, nullptr, nullptr, nullptr))> lz;
+    for (int i = 0; i < np; ++i) {
+      Problem* P = ps[i];
+      const int64_t N = P->maps->n_dofs;
+      lz.add(copy_from_body<T>(N, P->copy, (const T*)P->lx, z ? z[i] : nullptr), grid1(N));
+    }
+    lz.emit(B, s);
+  }
+}
+
+// The CG iteration after the preconditioner (as cg_enqueue_tail) for every
+// problem, each step one launch over all of them: beta and p = z + beta p;
+// q = A p (tiled leaf operator, pass 2) with the partials of p.q; alpha;
+// x += alpha p, r -= alpha q with the partials of r.r; the scalars to the
+// host, the iteration's event recorded per problem.
+static void plan_cg_tail_batch(const std::vector<Problem*>& ps, hipStream_t s, BatchPlan& B) {
+  const int np = (int)ps.size();
+  const KernelTable* kt = ps[0]->kt;
+  Launch<decltype(scalars_body(0, nullptr, nullptr, 0))> s0, s1, s2;
+  Launch<decltype(update_p_body(0, nullptr, nullptr, nullptr))> lp;
+  Launch<decltype(fill_body<double>(0, nullptr, 0.0))> lz;
+  Launch<decltype(pass2_body(LeafView{}, nullptr, nullptr, nullptr, nullptr))> l2;
+  Launch<decltype(update_xr_body(0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr))> lx;
+  std::vector<dev::LeafItem> li;
+  int64_t lb = 0;
+  size_t lds = 0;
+  std::vector<int> per;  // problems whose leaf operator runs on its own (not tiled)
   for (int i = 0; i < np; ++i) {
     Problem* P = ps[i];
-    const double* ri = r ? r[i] : nullptr;
-    double* zi = z ? z[i] : nullptr;
+    const int64_t N = P->maps->n_dofs;
+    s0.add(scalars_body((int)fuse_grid(N), P->part, P->scal, 0), 1);
+    lp.add(update_p_body(N, P->cp, P->cz, P->scal), grid1(N));
+    int nq;
+    if (P->leaf.n_tiles && kt->leaf_t_batch) {
+      const int64_t g1 = std::min<int64_t>(P->leaf.n_tiles, dev::kLeafBlocks);
+      li.push_back(dev::LeafItem{P->leaf, P->cp, P->cq, P->E, P->part, lb, g1});
+      lb += g1;
+      lds = std::max(lds, size_t(P->leaf.max_nodes) * sizeof(double));
+      if (P->leaf.n_p2 == 0) {
+        lz.add(fill_body<double>(1, P->part + g1, 0.0), 1);
+        nq = (int)g1 + 1;
+      } else {
+        const unsigned g2 = fuse_grid(P->leaf.n_p2);
+        l2.add(pass2_body(P->leaf, P->E, P->cp, P->cq, P->part + g1), g2);
+        nq = (int)(g1 + g2);
+      }
+    } else {
+      per.push_back(i);
+      nq = P->leaf.n_tiles ? -1 : (int)fuse_grid(N);
+      if (nq < 0) fail(GMG_E_STATE, "batched leaf operator unavailable");
+    }
+    s1.add(scalars_body(nq, P->part, P->scal, 1), 1);
+    lx.add(update_xr_body(N, P->cg.u, P->cr, P->cp, P->cq, P->scal, P->part), dot_grid(N));
+    s2.add(scalars_body((int)dot_grid(N), P->part, P->scal, 2), 1);
+  }
+  s0.emit(B, s);
+  lp.emit(B, s);
+  if (!li.empty()) {
+    const size_t off = B.put(li);
+    const int n = (int)li.size();
+    const MatsH<double> m64 = ps[0]->m64;
+    B.q.push_back([=](const char* t) { kt->leaf_t_batch((const dev::LeafItem*)(t + off), n, lb, lds, m64, s); });
+  }
+  for (int i : per) {
+    Problem* P = ps[i];
     B.q.push_back([=](const char*) {
       const int64_t N = P->maps->n_dofs;
-      if (dot_rz)
-        hipLaunchKernelGGL(dev::copy_from_levels_dot<T>, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P->copy,
-                           (const T*)P->lx, zi, ri, P->part);
-      else
-        hipLaunchKernelGGL(dev::copy_from_levels<T>, dim3(grid1(N)), dim3(dev::kBlock), 0, s, N, P->copy,
-                           (T*)P->lx, zi);
+      P->kt->leaf_e(P->leaf, P->cp, P->E, false, P->m64, s);
+      hipLaunchKernelGGL(dev::seg_dir_dot, dim3(fuse_grid(N)), dim3(dev::kBlock), 0, s, N, P->leaf.soff,
+                         (const double*)P->E, P->leaf.dir, P->cq, P->cp, P->part);
+    });
+  }
+  lz.emit(B, s);
+  l2.emit(B, s);
+  s1.emit(B, s);
+  lx.emit(B, s);
+  s2.emit(B, s);
+  for (int i = 0; i < np; ++i) {
+    Problem* P = ps[i];
+    B.q.push_back([=](const char*) {
+      HIPCHECK(hipMemcpyAsync(P->host, P->scal, dev::kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipEventRecord(P->ev[4], s));
+      P->cg.pending = true;
     });
   }
 }
 
-// Plans the batched V-cycle; with d_table, uploads the item tables (through
-// h_stage, pinned host memory of at least table_bytes, when given; the event
-// `staged`, when given, is recorded once the upload has read it) and
-// enqueues it.  *need: bytes of the item tables.
-void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, double* const* z, char* d_table,
-                  size_t table_bytes, size_t* need, char* h_stage, hipStream_t s, bool dot_rz, hipEvent_t staged) {
+static void check_batch(const std::vector<Problem*>& ps) {
   if (ps.empty()) fail(GMG_E_INVAL, "empty batch");
   {
     std::vector<Problem*> u(ps);
@@ -1094,11 +1314,12 @@ void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, doubl
         P->device != ps[0]->device)
       fail(GMG_E_INVAL, "a batch needs one dimension, degree, precision, smoother and device");
   }
-  BatchPlan B;
-  if (ps[0]->opt.mg_precision == 32)
-    plan_vcycle_batch<float>(ps, r, z, s, dot_rz, B);
-  else
-    plan_vcycle_batch<double>(ps, r, z, s, dot_rz, B);
+}
+
+// uploads the plan's tables (through h_stage when given) and enqueues its
+// launches; *need: bytes of the tables
+static void run_plan(BatchPlan& B, char* d_table, size_t table_bytes, size_t* need, char* h_stage, hipStream_t s,
+                     hipEvent_t staged) {
   const size_t bytes = std::max<size_t>(256, (B.blob.size() + 255) & ~size_t(255));
   if (need) *need = bytes;
   if (!d_table) return;
@@ -1115,6 +1336,40 @@ void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, doubl
   if (staged) HIPCHECK(hipEventRecord(staged, s));
   for (auto& f : B.q) f(d_table);
   HIPCHECK(hipGetLastError());
+}
+
+void cg_iteration_batch(const std::vector<Problem*>& ps, char* d_table, size_t table_bytes, size_t* need,
+                        char* h_stage, hipStream_t s, hipEvent_t staged) {
+  check_batch(ps);
+  std::vector<const double*> rs;
+  std::vector<double*> zs;
+  for (Problem* P : ps) {
+    if (!P->cg.running) fail(GMG_E_STATE, "no solve in progress");
+    rs.push_back(P->cr);
+    zs.push_back(P->cz);
+  }
+  BatchPlan B;
+  if (ps[0]->opt.mg_precision == 32)
+    plan_vcycle_batch<float>(ps, rs.data(), zs.data(), s, true, B);
+  else
+    plan_vcycle_batch<double>(ps, rs.data(), zs.data(), s, true, B);
+  plan_cg_tail_batch(ps, s, B);
+  run_plan(B, d_table, table_bytes, need, h_stage, s, staged);
+}
+
+// Plans the batched V-cycle; with d_table, uploads the item tables (through
+// h_stage, pinned host memory of at least table_bytes, when given; the event
+// `staged`, when given, is recorded once the upload has read it) and
+// enqueues it.  *need: bytes of the item tables.
+void vcycle_batch(const std::vector<Problem*>& ps, const double* const* r, double* const* z, char* d_table,
+                  size_t table_bytes, size_t* need, char* h_stage, hipStream_t s, bool dot_rz, hipEvent_t staged) {
+  check_batch(ps);
+  BatchPlan B;
+  if (ps[0]->opt.mg_precision == 32)
+    plan_vcycle_batch<float>(ps, r, z, s, dot_rz, B);
+  else
+    plan_vcycle_batch<double>(ps, r, z, s, dot_rz, B);
+  run_plan(B, d_table, table_bytes, need, h_stage, s, staged);
 }
 
 // the CG preconditioner: replay of a captured graph of one V-cycle on the
