@@ -485,12 +485,10 @@ __device__ __forceinline__ void gather_patch(int64_t f0, int nf, const T* __rest
 #pragma unroll
   for (int it = 0; it < S::ITB; ++it) {
     const int e = tid + it * S::THREADS;
-    vb[it] = T(0);
-    if (e < nf * NB) {
-      const int fl = e / NB;
-      const uint32_t c = bc[e % NB];
-      vb[it] = xin[sgb[fl * NJ + G::cj(c)] + G::cloc(c)];
-    }
+    const int ee = e < nf * NB ? e : 0;  // a valid position when out of range
+    const int fl = ee / NB;
+    const uint32_t c = bc[ee % NB];
+    vb[it] = xin[sgb[fl * NJ + G::cj(c)] + G::cloc(c)];
   }
 #pragma unroll
   for (int it = 0; it < S::ITI; ++it) {
@@ -566,9 +564,10 @@ __device__ __forceinline__ void fam_op_body(const LevelView& v, const T* __restr
     // sibling sum by lane moves (floating-point atomic adds in LDS measured
     // several times slower)
     family_sum<DIM, N, T>(cid, w);
+    // every lane holds the family totals of its nodes (bit for bit the same
+    // in all lanes sharing a node), so all of them may write
 #pragma unroll
-    for (int j = 0; j < NP; ++j)
-      if (family_owner<DIM, N>(cid, j)) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = w[j];
+    for (int j = 0; j < NP; ++j) sout[fl * MFP + cell_patch_pos<DIM, K>(cid, j)] = w[j];
   }
   __syncthreads();
   patch_out<DIM, K, T, EPI>(v, f0, nf, sout, sin, sgb, sex, bq, bc, bo, ep, E, inode, iops);
