@@ -33,16 +33,17 @@ def log(*a):
 
 KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_03317_amd", "csrc",
                              "famkernels.hpp")
+LEAF_SOURCE = os.path.join(os.path.dirname(KERNEL_SOURCE), "kernels.hpp")
 # committed counter summaries per workload (mesh recipe and global refinements)
 TRAFFIC_FILES = {("C2", 5): "level_kernels_traffic.json",
                  ("C3-Q2", 6): "level_kernels_traffic_fichera_q2_g6.json"}
 
 
 def measured_traffic(name, g):
-    """HBM bytes per launch of the level kernels from the committed counter
-    summary of this workload (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
-    copy of known size); empty when there is none or the kernel source has
-    changed since it was taken."""
+    """HBM bytes per launch of the level kernels and of the leaf operator from
+    the committed counter summary of this workload (rocprofv3 FETCH_SIZE /
+    WRITE_SIZE, scaled by a copy of known size); each left out when there is
+    none or its kernel source has changed since it was taken."""
     import hashlib
     fn = TRAFFIC_FILES.get((name, g))
     if fn is None:
@@ -52,10 +53,18 @@ def measured_traffic(name, g):
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return {}
-    return rec if rec.get("kernel_source_sha256") == sha else {}
+    out = dict(rec) if rec.get("kernel_source_sha256") == sha else {}
+    out.pop("leaf", None)
+    try:
+        lsha = hashlib.sha256(open(LEAF_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        lsha = None
+    if rec.get("leaf") and rec.get("leaf_kernel_source_sha256") == lsha:
+        out["leaf"] = rec["leaf"]
+    return out
 
 
-def roofline(r, traffic):
+def roofline(r, traffic, leaf_traffic=None):
     """Dominant unit of the solve: one Chebyshev step on the largest level
     (pass 1 + pass 2), algorithmic bytes = read x, d, g, D^-1 and write x, d;
     beside it the operator apply y = A x (read x, write y)."""
@@ -73,9 +82,11 @@ def roofline(r, traffic):
                       "traffic": traffic.get("apply_bytes_per_launch") if traffic else None}}
     if "t_leaf" in r:
         a_leaf = 16 * r["N"] / r["t_leaf"] / 1e9
+        lt = leaf_traffic.get("bytes_per_launch") if leaf_traffic else None
         out["leaf"] = {"achieved": a_leaf, "frac": a_leaf / HBM_PEAK_GBS, "t_launch_us": r["t_leaf"] * 1e6,
-                       "bytes_per_dof": 16, "kernel": "FP64 leaf operator q = C^T A C p with hanging nodes "
-                                                      "(read p, write q), 512 MB cache flush before each launch"}
+                       "bytes_per_dof": 16, "traffic": lt,
+                       "kernel": "FP64 leaf operator q = C^T A C p with hanging nodes (tiles of 64 cells, pass 1 "
+                                 "+ pass 2; read p, write q), 512 MB cache flush before each launch"}
     return out
 
 
@@ -498,7 +509,7 @@ def main():
                    "setup_maps_s": r["maps_s"], "setup_device_s": r["bind_s"]},
     }
     traffic = measured_traffic(w.name, g_used)
-    out["roofline"] = roofline(r, traffic.get(f"fp{prim}"))
+    out["roofline"] = roofline(r, traffic.get(f"fp{prim}"), traffic.get("leaf"))
     out["roofline"]["measured_copy_gbs"] = copy_gbs
     other = 32 if prim == 64 else 64
     if other in results:
@@ -509,7 +520,7 @@ def main():
                                 "vcycle_ms": o["vcycle_ms"], "vcycle_dofs_per_s": o["N"] / (o["vcycle_ms"] * 1e-3),
                                 "rel_diff_vs_fp64_mg": d, "fp32_speedup_over_fp64": (
                                     results[64]["ms"] / results[32]["ms"] if 32 in results else None),
-                                "roofline": roofline(o, traffic.get(f"fp{other}"))}
+                                "roofline": roofline(o, traffic.get(f"fp{other}"), traffic.get("leaf"))}
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
         out["serve"] = serve_leg(args.serve)

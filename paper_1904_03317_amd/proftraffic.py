@@ -8,7 +8,8 @@ python -m paper_1904_03317_amd.proftraffic <fetch results.db> <write results.db>
 With --json, also writes the bytes per launch of the two level-operator
 units on the largest level of each precision (the operator apply y = A x and
 one Chebyshev step, each pass 1 fam_op + pass 2 fam_sum), keyed by the
-SHA-256 of the kernel source they were measured on.
+SHA-256 of the kernel source they were measured on, and those of the FP64
+tiled leaf operator (pass 1 + pass 2, keyed by the SHA-256 of its source).
 """
 import argparse
 import collections
@@ -81,6 +82,18 @@ def units(table):
                     "apply_bytes_per_launch": None if None in ap else sum(ap),
                     "cheb_bytes_per_launch": None if None in ch else sum(ch),
                     "apply_parts": ap, "cheb_parts": ch}
+    # the FP64 tiled leaf operator (apply without the dot: the bench's timing
+    # loop): pass 1 and pass 2, the grids with the most dispatches
+    def most(prefix):
+        c = [(v[0], n, g) for (n, g), v in table.items() if n.startswith(prefix)]
+        if not c:
+            return None
+        _, n, g = max(c)
+        v = table[(n, g)]
+        return v[1] + v[3]
+    l1, l2 = most("leaf_tiles<"), most("leaf_pass2<")
+    if l1 is not None:
+        out["leaf"] = {"bytes_per_launch": l1 + (l2 or 0.0), "parts": [l1, l2]}
     return out
 
 
@@ -98,12 +111,18 @@ def main():
         print(f"{n[:44]:44s} {g:9d} {nf:5d} {fb / 1e6:14.2f} {wb / 1e6:14.2f}")
     u = units(table)
     for k, v in u.items():
+        if k == "leaf":
+            print(f"leaf operator: {v['bytes_per_launch'] / 1e6:.1f} MB/launch (pass 1, pass 2: "
+                  f"{', '.join('-' if x is None else f'{x / 1e6:.1f}' for x in v['parts'])} MB)")
+            continue
         print(f"{k}: apply {v['apply_bytes_per_launch'] / 1e6:.1f} MB/launch, "
               f"Chebyshev step {v['cheb_bytes_per_launch'] / 1e6:.1f} MB/launch "
               f"(fam_op grid {v['fam_op_grid']}, fam_sum grid {v['fam_sum_grid']})")
     if a.json:
         src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "famkernels.hpp")
         u["kernel_source_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        lsrc = os.path.join(os.path.dirname(src), "kernels.hpp")
+        u["leaf_kernel_source_sha256"] = hashlib.sha256(open(lsrc, "rb").read()).hexdigest()
         u["calibration_scale"] = {"fetch": sf, "write": sw}
         json.dump(u, open(a.json, "w"), indent=1)
 
