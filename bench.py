@@ -227,6 +227,74 @@ def build_request_meshes(ids, threads=8):
         return list(ex.map(one, ids))
 
 
+def adaptive_leg(g0=3, cycles=9, fraction=0.142):
+    """The adaptive loop of the paper's Laplace comparison (Sec. 4.3) on the
+    GPU: Fichera corner, Q2, eps = 1 if min(x,y,z) > -1/2 else 100, f = 1,
+    the "MF" preconditioner (one undamped FP32 Jacobi step per level), from
+    g0 global refinements; per cycle the host set-up (maps), device set-up,
+    solve to 1e-10, the residual error estimator and the marking of the 14.2 %
+    largest estimates (HIP events on the launch stream) and the refinement
+    (host).  One JSON object with the cycles."""
+    import numpy as np
+    import torch
+
+    import gmg_inputs as gi
+    from paper_1904_03317_amd import gmg
+
+    mesh = gmg.build_mesh(gi.MeshRecipe("fichera", g0, 0, "none"))
+    opts = gmg.options(degree=2, mg_precision=32, cheb_degree=1, smoother=gmg.SMOOTHER_JACOBI)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for c in range(cycles):
+        lv, an = mesh.leaves()
+        eps = gi.coeff_cells("eps", lv, an)
+        t0 = time.perf_counter()
+        P = gmg.Problem(mesh, opts, coeff=eps)
+        t1 = time.perf_counter()
+        P.bind()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        N = P.n_dofs
+        f = torch.ones(N, dtype=torch.float64, device="cuda")
+        u = torch.zeros_like(f)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        st, its, h = P.solve(f, u)
+        ev[1].record(stream)
+        ws = P.estimator_workspace()
+        eta = torch.zeros(len(lv), dtype=torch.float64, device="cuda")
+        P.estimate(u, f, eta, ws)   # uploads the face tables into the workspace
+        torch.cuda.synchronize()
+        ev[2].record(stream)
+        P.estimate(u, f, eta, ws)
+        flags = torch.zeros(len(lv), dtype=torch.uint8, device="cuda")
+        ev[3].record(stream)
+        P.mark(eta, flags, ws, fraction)
+        e4 = torch.cuda.Event(enable_timing=True)
+        e4.record(stream)
+        torch.cuda.synchronize()
+        if st != 0 or h[-1] > 1e-10:
+            raise RuntimeError(f"adaptive cycle {c}: solve status {st}, residual {h[-1]:.2e}")
+        fl = flags.cpu().numpy()
+        t3 = time.perf_counter()
+        mesh.refine(fl)
+        t4 = time.perf_counter()
+        row = {"cycle": c, "leaves": len(lv), "dofs": N, "cg_iterations": its, "final_rel_residual": float(h[-1]),
+               "setup_maps_s": t1 - t0, "setup_device_s": t2 - t1, "solve_ms": ev[0].elapsed_time(ev[1]),
+               "estimate_ms": ev[2].elapsed_time(ev[3]), "mark_ms": ev[3].elapsed_time(e4),
+               "refine_host_s": t4 - t3, "marked": int(fl.sum())}
+        row["solve_dofs_per_s"] = N / (row["solve_ms"] * 1e-3)
+        row["estimate_cells_per_s"] = len(lv) / (row["estimate_ms"] * 1e-3)
+        rows.append(row)
+        log(f"adaptive cycle {c}: {len(lv)} leaves, N={N}, its {its}, maps {t1 - t0:.2f} s, bind {t2 - t1:.2f} s, "
+            f"solve {row['solve_ms']:.1f} ms, estimate {row['estimate_ms']:.2f} ms, mark {row['mark_ms']:.2f} ms")
+        P.close()
+        del ws, eta, flags, u, f
+    return {"workload": "Fichera corner Q2, eps in {1, 100} (Sec. 4.3), f = 1, one undamped FP32 Jacobi step per "
+                        f"level, {g0} global refinements then cycles of estimate / mark 14.2 % / refine",
+            "cycles": rows}
+
+
 def serve_leg(n_req, slots=16, threads=8, arena_gb=64.0, warm=16, load=0.7, big_g=None, closed_n=64, resident=32):
     """Open-loop serving stream of unit-cube Q2 requests (FP32 V-cycle, FP64
     CG) with Poisson arrivals at `load` times the throughput measured in a
@@ -376,6 +444,8 @@ def main():
                     help="only the unit timings of the largest level and the leaf operator (for counter runs)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--adaptive", type=int, default=9, metavar="CYCLES",
+                    help="cycles of the Sec. 4.3 adaptive loop (estimate, mark, refine) on the GPU (0: skip)")
     ap.add_argument("--serve-big", type=int, default=5, metavar="G",
                     help="a second stream with the C5 job (Q3 checkerboard, G global refinements) as request 128 "
                          "(negative: skip)")
@@ -521,6 +591,9 @@ def main():
                                 "rel_diff_vs_fp64_mg": d, "fp32_speedup_over_fp64": (
                                     results[64]["ms"] / results[32]["ms"] if 32 in results else None),
                                 "roofline": roofline(o, traffic.get(f"fp{other}"), traffic.get("leaf"))}
+    if args.adaptive > 0:
+        log(f"adaptive loop: {args.adaptive} cycles ...")
+        out["adaptive"] = adaptive_leg(cycles=args.adaptive)
     if args.serve > 0:
         log(f"serving stream: {args.serve} requests ...")
         out["serve"] = serve_leg(args.serve)

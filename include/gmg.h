@@ -238,6 +238,32 @@ int gmg_vcycle(gmg_problem p, const double* d_r, double* d_z, hipStream_t stream
 int gmg_vcycle_batch(const gmg_problem* ps, int n, const double* const* d_r, double* const* d_z, void* d_table,
                      size_t* table_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------ adaptive loop
+ * Residual error estimator of the adaptive loop (Sec. 4.3), per leaf K in
+ * canonical leaf order:
+ *   eta_K = h_K^2 || f_h + a_K Laplace u_h ||_K^2
+ *         + sum over the faces F of K of h_K || [a grad u_h . n] ||_F^2,
+ * u_h, f_h the cell polynomials of the constrained nodal values of d_u and
+ * d_f_nodal (leaf DoF vectors [n_dofs], device), a the problem's cell
+ * coefficient; (k+1)-point Gauss quadrature per direction; no term on the
+ * domain boundary; a face shared with finer leaves is integrated over each
+ * of their faces; h_K the side of K.  d_eta: [n_leaves] device.  The work
+ * memory is a caller-owned device workspace (256-byte aligned) of
+ * gmg_estimator_workspace_bytes bytes; it receives the problem's face and
+ * constraint tables on the first call with that workspace (again after
+ * another problem used it).  Errors: GMG_E_INVAL (null argument, workspace
+ * too small or misaligned), GMG_E_HIP. */
+int gmg_estimator_workspace_bytes(gmg_problem p, size_t* bytes);
+int gmg_estimate(gmg_problem p, const double* d_u, const double* d_f_nodal, void* d_ws, size_t ws_bytes,
+                 double* d_eta, hipStream_t stream);
+/* Marking (Sec. 4.3: the 14.2 % of the leaves with the largest estimates):
+ * d_flags[K] = 1 for the round(fraction n_leaves) leaves with the largest
+ * d_eta, equal values taken in leaf order, else 0 ([n_leaves] uint8, device;
+ * the flags of gmg_mesh_refine once copied to the host).  Same workspace as
+ * gmg_estimate.  Errors: GMG_E_INVAL (fraction outside [0, 1]). */
+int gmg_mark(gmg_problem p, const double* d_eta, double fraction, uint8_t* d_flags, void* d_ws, size_t ws_bytes,
+             hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * V-cycle as gmg_vcycle, with its work memory (level vectors x, g, t, d,

@@ -345,6 +345,32 @@ int gmg_vcycle_batch(const gmg_problem* ps, int n, const double* const* r, doubl
   });
 }
 
+int gmg_estimator_workspace_bytes(gmg_problem p, size_t* bytes) {
+  return guard([&] {
+    REQUIRE(p && bytes, "null argument");
+    *bytes = gmg::est_workspace_bytes(p->P);
+    return 0;
+  });
+}
+
+int gmg_estimate(gmg_problem p, const double* u, const double* f, void* ws, size_t bytes, double* eta,
+                 hipStream_t s) {
+  return guard([&] {
+    REQUIRE(p && u && f && eta, "null argument");
+    gmg::estimate(p->P, u, f, (char*)ws, bytes, eta, s);
+    return 0;
+  });
+}
+
+int gmg_mark(gmg_problem p, const double* eta, double fraction, uint8_t* flags, void* ws, size_t bytes,
+             hipStream_t s) {
+  return guard([&] {
+    REQUIRE(p && eta && flags, "null argument");
+    gmg::mark(p->P, eta, fraction, flags, (char*)ws, bytes, s);
+    return 0;
+  });
+}
+
 int gmg_vcycle_noalloc(gmg_problem p, const double* r, double* z, hipStream_t s) {
   return guard([&] {
     REQUIRE(p && r && z, "null argument");

@@ -81,6 +81,8 @@ struct SumItem;
 template <typename T>
 struct XferItem;
 struct LeafItem;
+struct EstView;
+struct EstMatsD;
 }
 
 // kinds of batched transfers (LevelOps::xfer_batch)
@@ -136,6 +138,9 @@ struct KernelTable {
   // degree >= 3
   void (*leaf_t_batch)(const dev::LeafItem* items, int n, int64_t blocks, size_t lds, const MatsH<double>&,
                        hipStream_t);
+  // residual error estimator (Sec. 4.3): eta[c] for every leaf from the
+  // solution u and the nodal right-hand side f (leaf DoF vectors)
+  void (*est)(const dev::EstView&, const double* u, const double* f, double* eta, const dev::EstMatsD&, hipStream_t);
 };
 
 const KernelTable* kernel_table(int dim, int k);

@@ -71,7 +71,7 @@ void lagrange_values(const FE1D& fe, double xi, double* out) {
   }
 }
 
-static void lagrange_derivs(const FE1D& fe, double xi, double* out) {
+void lagrange_derivs(const FE1D& fe, double xi, double* out) {
   for (int j = 0; j < fe.n; ++j) {
     double s = 0.0;
     for (int i = 0; i < fe.n; ++i) {
@@ -82,6 +82,31 @@ static void lagrange_derivs(const FE1D& fe, double xi, double* out) {
       s += t;
     }
     out[j] = s;
+  }
+}
+
+void lagrange_second_derivs(const FE1D& fe, double xi, double* out) {
+  for (int j = 0; j < fe.n; ++j) {
+    double s = 0.0;
+    for (int a = 0; a < fe.n; ++a) {
+      if (a == j) continue;
+      for (int b = 0; b < fe.n; ++b) {
+        if (b == j || b == a) continue;
+        double t = 1.0 / ((fe.x[j] - fe.x[a]) * (fe.x[j] - fe.x[b]));
+        for (int m = 0; m < fe.n; ++m)
+          if (m != j && m != a && m != b) t *= (xi - fe.x[m]) / (fe.x[j] - fe.x[m]);
+        s += t;
+      }
+    }
+    out[j] = s;
+  }
+}
+
+void gauss_01(int n, double* x, double* w) {
+  gauss_legendre(n, x, w);
+  for (int q = 0; q < n; ++q) {
+    x[q] = 0.5 * (x[q] + 1.0);
+    w[q] *= 0.5;
   }
 }
 

@@ -19,5 +19,10 @@ struct FE1D {
 FE1D make_fe1d(int k);
 // values of the Lagrange basis on the nodes of `fe` at xi: out[j], j <= k
 void lagrange_values(const FE1D& fe, double xi, double* out);
+// their first and second derivatives at xi
+void lagrange_derivs(const FE1D& fe, double xi, double* out);
+void lagrange_second_derivs(const FE1D& fe, double xi, double* out);
+// n-point Gauss-Legendre points and weights on [0,1], ascending
+void gauss_01(int n, double* x, double* w);
 
 }  // namespace gmg

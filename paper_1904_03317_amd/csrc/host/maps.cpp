@@ -289,9 +289,11 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
   const int64_t nl = (int64_t)leaves.size();
   M.n_leaves = nl;
   M.leaf_level.resize(nl);
+  M.leaf_anchor.resize(size_t(nl) * 3);
   M.leaf_coeff.resize(nl);
   for (int64_t i = 0; i < nl; ++i) {
     M.leaf_level[i] = leaves[i].c.level;
+    for (int a = 0; a < 3; ++a) M.leaf_anchor[size_t(i) * 3 + a] = leaves[i].c.a[a];
     M.leaf_coeff[i] = coeff ? coeff[i] : 1.0;
     if (!(M.leaf_coeff[i] > 0.0) || !std::isfinite(M.leaf_coeff[i]))
       fail(-1, "cell coefficients must be positive and finite");

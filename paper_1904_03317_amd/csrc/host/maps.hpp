@@ -46,6 +46,7 @@ struct Maps {
   // edge along x / y / z (at the child's corner edge of the parent)
   std::vector<uint16_t> leaf_mask;
   std::vector<int8_t> leaf_level;
+  std::vector<int32_t> leaf_anchor;   // [n_leaves * 3] global anchors (units 2^-20)
   std::vector<double> leaf_coeff;
   std::vector<uint8_t> dirichlet;     // [n_dofs]
   std::vector<int64_t> con_off;       // [n_hanging+1]

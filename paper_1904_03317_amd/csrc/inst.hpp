@@ -3,6 +3,7 @@
 #include "dispatch.hpp"
 #include "gmg.h"
 #include "host/common.hpp"
+#include "estkernels.hpp"
 #include "famkernels.hpp"
 #include "kernels.hpp"
 
@@ -313,6 +314,13 @@ struct Inst {
     }
   }
 
+  static void est(const dev::EstView& v, const double* u, const double* f, double* eta, const dev::EstMatsD& m,
+                  hipStream_t s) {
+    if (!v.n_cells) return;
+    hipLaunchKernelGGL((dev::est_cells<DIM, N>), dim3((unsigned)((v.n_cells + 63) / 64)), dim3(64), 0, s, v, u, f,
+                       eta, m);
+  }
+
   template <typename T>
   static constexpr LevelOps<T> ops() {
     return LevelOps<T>{&op<T>,        &sum<T>,   &restrict_fc<T>,
@@ -322,7 +330,7 @@ struct Inst {
   }
   static const KernelTable* table() {
     static KernelTable t = {ops<float>(), ops<double>(), &leaf_e, &leaf_t, &diag0,
-                            (DIM == 3 && K >= 3) ? nullptr : &leaf_t_batch};
+                            (DIM == 3 && K >= 3) ? nullptr : &leaf_t_batch, &est};
     return &t;
   }
 };

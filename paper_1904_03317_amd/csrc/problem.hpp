@@ -8,6 +8,7 @@
 
 #include "../../include/gmg.h"
 #include "dispatch.hpp"
+#include "host/esttables.hpp"
 #include "host/maps.hpp"
 
 namespace gmg {
@@ -76,6 +77,10 @@ struct Problem {
   double timing[3] = {0, 0, 0};
   CgState cg;
   std::vector<hipEvent_t> ev;
+  // error estimator: face tables (built on first use) and the workspace
+  // they were last uploaded to
+  std::shared_ptr<const EstTables> est;
+  mutable const char* est_uploaded = nullptr;
 
   ~Problem();
 };
@@ -108,6 +113,16 @@ bool cg_poll(Problem& P, bool block);
 int cg_check(Problem& P, bool block);
 void cg_enqueue_tail(Problem& P, hipStream_t s);
 void cg_enqueue_iteration(Problem& P);  // preconditioner and tail on the CG stream
+// residual error estimator and marking (Sec. 4.3), device work memory in a
+// caller-owned workspace of est_workspace_bytes(P) bytes
+size_t est_workspace_bytes(Problem& P);
+void estimate(Problem& P, const double* u, const double* f, char* ws, size_t bytes, double* eta, hipStream_t s);
+void mark(Problem& P, const double* eta, double fraction, uint8_t* flags, char* ws, size_t bytes, hipStream_t s);
+// marking kernels (mark.hip): flags of the m largest of eta[0..n) (ties in
+// index order) through a stable descending key sort
+size_t mark_temp_bytes(int64_t n);
+void mark_top(const double* eta, int64_t n, int64_t m, double* keys_out, int32_t* idx_in, int32_t* idx_out,
+              void* temp, size_t temp_bytes, uint8_t* flags, hipStream_t s);
 // The next CG iteration of every problem of ps (each with its iteration due,
 // cg_check having returned 2), each step one launch over all of them on s:
 // the batched V-cycle z = B r, then the rest of the iteration; each

@@ -92,6 +92,9 @@ def configure(L):
         "gmg_vcycle": (C.c_int, [vp, vp, vp, vp]),
         "gmg_vcycle_noalloc": (C.c_int, [vp, vp, vp, vp]),
         "gmg_vcycle_batch": (C.c_int, [vp, C.c_int, vp, vp, vp, C.POINTER(C.c_size_t), vp]),
+        "gmg_estimator_workspace_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "gmg_estimate": (C.c_int, [vp, vp, vp, vp, C.c_size_t, vp, vp]),
+        "gmg_mark": (C.c_int, [vp, vp, C.c_double, vp, vp, C.c_size_t, vp]),
         "gmg_problem_last_timing": (C.c_int, [vp, C.POINTER(dbl)]),
         "gmg_server_create": (C.c_int, [vp, C.c_size_t, i32, i32, C.POINTER(vp)]),
         "gmg_server_submit": (C.c_int, [vp, vp, C.POINTER(gmg_options), vp, vp, i64, C.POINTER(C.c_uint64)]),
@@ -137,6 +140,7 @@ def exported_symbols():
             "gmg_problem_create", "gmg_problem_clone", "gmg_problem_info", "gmg_problem_array",
             "gmg_problem_workspace_bytes", "gmg_problem_bind", "gmg_problem_destroy", "gmg_rhs",
             "gmg_solve", "gmg_solve_rhs", "gmg_apply_leaf", "gmg_apply_level", "gmg_vcycle", "gmg_vcycle_noalloc", "gmg_vcycle_batch",
+            "gmg_estimator_workspace_bytes", "gmg_estimate", "gmg_mark",
             "gmg_problem_last_timing", "gmg_server_create", "gmg_server_submit", "gmg_server_request_dofs",
             "gmg_server_set_rhs", "gmg_server_poll",
             "gmg_server_wait", "gmg_server_result", "gmg_server_release", "gmg_server_stats",
@@ -310,6 +314,23 @@ class Problem:
 
     def vcycle(self, r, z, stream=None):
         _check(lib().gmg_vcycle(self.h, _ptr(r), _ptr(z), _stream(stream)))
+
+    def estimator_workspace(self, device="cuda"):
+        """device workspace of the error estimator and the marking"""
+        import torch
+        b = C.c_size_t()
+        _check(lib().gmg_estimator_workspace_bytes(self.h, C.byref(b)))
+        return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+    def estimate(self, u, f, eta, workspace, stream=None):
+        """gmg_estimate: eta [n_leaves] from the solution u and the nodal f"""
+        _check(lib().gmg_estimate(self.h, _ptr(u), _ptr(f), _ptr(workspace), workspace.numel(), _ptr(eta),
+                                  _stream(stream)))
+
+    def mark(self, eta, flags, workspace, fraction=0.142, stream=None):
+        """gmg_mark: flags [n_leaves] uint8 of the largest fraction of eta"""
+        _check(lib().gmg_mark(self.h, _ptr(eta), float(fraction), _ptr(flags), _ptr(workspace), workspace.numel(),
+                              _stream(stream)))
 
     def vcycle_noalloc(self, r, z, stream=None):
         """gmg_vcycle with the work memory in the library's fixed scratch

@@ -16,12 +16,14 @@ FLAGS = ["-std=c++20", "-O1", "-g", "-fPIC", "-pthread", "-fsanitize=address", "
 
 def sources():
     host = [os.path.join(CSRC, "host", f) for f in sorted(os.listdir(os.path.join(CSRC, "host"))) if f.endswith(".cpp")]
-    dev = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
-    return host + dev
+    # mark.hip sorts with the device radix sort of hipcub; the emulation
+    # takes mark_emu.cpp (same contract, a host sort) in its place
+    dev = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip") and f != "mark.hip"]
+    return host + dev + [os.path.join(HERE, "mark_emu.cpp")]
 
 
 def _cc(src):
-    obj = os.path.join(OUT, os.path.relpath(src, CSRC).replace(os.sep, "_") + ".o")
+    obj = os.path.join(OUT, os.path.basename(os.path.dirname(src)) + "_" + os.path.basename(src) + ".o")
     cmd = ["g++", *FLAGS, "-x", "c++", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode:

@@ -151,7 +151,7 @@ def main():
         serve_check(int(sys.argv[2]))
         return
     case, prec = sys.argv[1], int(sys.argv[2])
-    checks = sys.argv[3].split(",") if len(sys.argv) > 3 else ["leaf", "level", "vcycle", "solve"]
+    checks = sys.argv[3].split(",") if len(sys.argv) > 3 else ["leaf", "level", "vcycle", "estimate", "solve"]
     rec, k = CASES[case]
     coeff_kind = "checker" if rec.coarse == "fichera" else "one"
     op, coeff = oracle_problem(rec, k, coeff_kind=coeff_kind)
@@ -275,6 +275,25 @@ def main():
         out["batch_equal"] = bool(np.array_equal(za, z)) and bool(np.array_equal(zb, zb2))
         L.gmg_problem_destroy(P2)
         L.gmg_mesh_destroy(m2)
+    if "estimate" in checks:
+        # error estimator and marking (Sec. 4.3) against the oracle's, on a
+        # random u (hanging values from the constraints) and a nodal f
+        from oracle.estimate import estimate, mark_fraction
+        u = rng.standard_normal(N)
+        u[~op.free] = 0
+        fn = 1.0 + rng.standard_normal(N)
+        eps = np.asarray(op.coeff, np.float64)
+        ref = estimate(op.disc, u, fn, eps)
+        nb = C.c_size_t()
+        check(L.gmg_estimator_workspace_bytes(P, C.byref(nb)))
+        wraw, ws = aligned(nb.value)
+        eta = np.full(len(ref), np.nan)
+        for _ in range(2):  # the second call reuses the uploaded tables
+            check(L.gmg_estimate(P, ptr(u), ptr(fn), ptr(ws), nb.value, ptr(eta), None))
+        out["est_rel"] = float(np.abs(eta - ref).max() / max(np.abs(ref).max(), 1e-300))
+        flags = np.zeros(len(ref), np.uint8)
+        check(L.gmg_mark(P, ptr(eta), 0.142, ptr(flags), ptr(ws), nb.value, None))
+        out["mark_equal"] = bool(np.array_equal(flags, mark_fraction(eta, 0.142)))
     if "solve" in checks:
         fn = gi.rhs_nodal("noise", N)
         x, it, hist, ok = op.solve(fn)

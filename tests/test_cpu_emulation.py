@@ -83,5 +83,8 @@ def test_emulated_kernels_match_oracle(emu_results, case, prec):
         assert r["level_rel"] <= 2e-6 and r["edge_rel"] <= 2e-6 and r["vcycle_rel"] <= 1e-5
     assert r["noalloc_equal"]
     assert r["batch_equal"]
+    # error estimator (Sec. 4.3) entry by entry against the largest entry,
+    # and the marking of its 14.2 % largest values
+    assert r["est_rel"] <= 1e-12 and r["mark_equal"]
     assert r["status"] == 0 and r["its"] == r["its_oracle"]
     assert r["solve_rel"] <= 1e-10

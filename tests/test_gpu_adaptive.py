@@ -1,0 +1,114 @@
+"""The adaptive loop of the paper's Laplace comparison (Sec. 4.3) on the GPU:
+the residual error estimator and the 14.2 % marking (gmg_estimate,
+gmg_mark) against the oracle (oracle/estimate.py), entry by entry; and three
+cycles of solve -> estimate -> mark -> refine on the Fichera domain with the
+coefficient eps in {1, 100}, each cycle's solve, estimate and marking
+against the oracle on the same mesh, and the final meshes bit for bit."""
+import numpy as np
+import pytest
+
+import gmg_inputs as gi
+from helpers import CASES, library_problem, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def _near_threshold_ok(flags, ref_flags, eta_ref, rel=1e-12):
+    """flags equal except at leaves whose estimate ties the marking threshold
+    to within rounding (either choice is correct there)"""
+    diff = np.nonzero(flags != ref_flags)[0]
+    if len(diff) == 0:
+        return True
+    m = int(ref_flags.sum())
+    thr = np.sort(eta_ref)[::-1][max(m - 1, 0)]
+    return bool(np.all(np.abs(eta_ref[diff] - thr) <= rel * max(abs(thr), 1e-300)))
+
+
+@pytest.mark.parametrize("case", ["lshape-q1", "lshape-q4", "fichera-q1", "fichera-q2", "fichera-q3", "fichera-q4",
+                                  "cube-q2"])
+def test_estimator_and_marking_match_oracle(case):
+    from oracle.estimate import estimate, mark_fraction
+    rec, k = CASES[case]
+    kind = "checker" if rec.coarse == "fichera" else "one"
+    op, coeff = oracle_problem(rec, k, coeff_kind=kind)
+    m, P, _ = library_problem(rec, k, coeff_kind=kind)
+    P.bind()
+    N = op.n_dofs
+    rng = np.random.default_rng(17)
+    u = rng.standard_normal(N)
+    u[~op.free] = 0
+    f = 1.0 + rng.standard_normal(N)
+    eps = np.asarray(op.coeff, np.float64)
+    ref = estimate(op.disc, u, f, eps)
+    ws = P.estimator_workspace()
+    eta = torch.zeros(len(ref), dtype=torch.float64, device="cuda")
+    P.estimate(_dev(u), _dev(f), eta, ws)
+    P.estimate(_dev(u), _dev(f), eta, ws)   # tables already in the workspace
+    flags = torch.zeros(len(ref), dtype=torch.uint8, device="cuda")
+    P.mark(eta, flags, ws)
+    torch.cuda.synchronize()
+    e = eta.cpu().numpy()
+    rel = np.abs(e - ref).max() / np.abs(ref).max()
+    print(f"[gpu] estimator {case}: {len(ref)} leaves, rel {rel:.2e}", flush=True)
+    assert rel <= 1e-12
+    fl = flags.cpu().numpy()
+    assert np.array_equal(fl, mark_fraction(e, 0.142))            # the marking of its own estimates
+    assert _near_threshold_ok(fl, mark_fraction(ref, 0.142), ref)  # and of the oracle's
+    P.close()
+
+
+def test_adaptive_loop_matches_oracle():
+    """Fichera corner, Q2, eps = 1 if min(x,y,z) > -1/2 else 100, noisy nodal
+    f, FP64 V-cycle: per cycle the GPU solve equals the oracle's (same
+    iteration count, 1e-10), its estimates match the oracle's on the GPU
+    solution (1e-12), the GPU marking matches the oracle's (up to ties at the
+    threshold); both forests refine the GPU's flags and stay identical."""
+    from oracle import problem
+    from oracle.estimate import estimate, mark_fraction
+    from oracle.forest import Forest
+    from paper_1904_03317_amd import gmg
+    rec = gi.MeshRecipe("fichera", 1, 0, "none")
+    mesh = gmg.build_mesh(rec)
+    fo = problem.build_forest(rec)
+    for cycle in range(3):
+        lv, an = mesh.leaves()
+        lo, ao = fo.leaves_arrays()
+        assert np.array_equal(lv, lo) and np.array_equal(an, ao)
+        eps = gi.coeff_cells("eps", lv, an)
+        op = problem.setup(fo, 2, coeff=eps)
+        N = op.n_dofs
+        fn = gi.rhs_nodal("noise", N, seed=7000 + cycle)
+        x, it, hist, ok = op.solve(fn)
+        P = gmg.Problem(mesh, gmg.options(degree=2, mg_precision=64), coeff=eps).bind()
+        assert P.n_dofs == N
+        u = torch.zeros(N, dtype=torch.float64, device="cuda")
+        fd = _dev(fn)
+        st, its, h = P.solve(fd, u)
+        ws = P.estimator_workspace()
+        eta = torch.zeros(len(lv), dtype=torch.float64, device="cuda")
+        P.estimate(u, fd, eta, ws)
+        flags = torch.zeros(len(lv), dtype=torch.uint8, device="cuda")
+        P.mark(eta, flags, ws)
+        torch.cuda.synchronize()
+        uh, e, fl = u.cpu().numpy(), eta.cpu().numpy(), flags.cpu().numpy()
+        ref = estimate(op.disc, uh, fn, eps)
+        print(f"[gpu] adaptive cycle {cycle}: {len(lv)} leaves, N={N}, its {its} (oracle {it}), "
+              f"marked {int(fl.sum())}", flush=True)
+        assert st == 0 and ok and its == it
+        assert np.linalg.norm(uh - x) <= 1e-10 * np.linalg.norm(x)
+        assert np.abs(e - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert _near_threshold_ok(fl, mark_fraction(ref, 0.142), ref)
+        assert int(fl.sum()) == int(np.floor(0.142 * len(lv) + 0.5))
+        P.close()
+        mesh.refine(fl)
+        fo.refine(fl)
+    lv, an = mesh.leaves()
+    lo, ao = fo.leaves_arrays()
+    assert np.array_equal(lv, lo) and np.array_equal(an, ao)
+    assert isinstance(fo, Forest)
