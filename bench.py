@@ -158,10 +158,13 @@ def kernels_only(w, mesh, coeff):
     print(json.dumps(out), flush=True)
 
 
+USE_GRAPH = 1
+
+
 def wopts(w, prec):
     """library options of a workload at a V-cycle precision"""
     from paper_1904_03317_amd import gmg
-    return gmg.options(degree=w.degree, mg_precision=prec, cheb_degree=w.cheb_degree,
+    return gmg.options(degree=w.degree, mg_precision=prec, cheb_degree=w.cheb_degree, use_graph=USE_GRAPH,
                        smoother=gmg.SMOOTHER_JACOBI if w.smoother == "jacobi" else gmg.SMOOTHER_CHEBYSHEV)
 
 
@@ -443,6 +446,8 @@ def main():
     ap.add_argument("--kernels", action="store_true",
                     help="only the unit timings of the largest level and the leaf operator (for counter runs)")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--graph", type=int, default=1, choices=[0, 1],
+                    help="replay the V-cycle as a captured HIP graph (1, the default) or launch it directly (0)")
     ap.add_argument("--serve", type=int, default=512, help="requests in the serving stream (0: skip)")
     ap.add_argument("--adaptive", type=int, default=9, metavar="CYCLES",
                     help="cycles of the Sec. 4.3 adaptive loop (estimate, mark, refine) on the GPU (0: skip)")
@@ -450,6 +455,8 @@ def main():
                     help="a second stream with the C5 job (Q3 checkerboard, G global refinements) as request 128 "
                          "(negative: skip)")
     args = ap.parse_args()
+    global USE_GRAPH
+    USE_GRAPH = args.graph
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU (it has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
