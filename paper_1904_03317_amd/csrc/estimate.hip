@@ -36,7 +36,7 @@ EstLayout est_layout(const Maps& M, const EstTables& T) {
   };
   const size_t nl = (size_t)M.n_leaves;
   L.cmap = take(nl * M.npc * sizeof(int32_t));
-  L.con_off = take((M.con_off.size() + 1) * sizeof(int64_t));
+  L.con_off = take(T.con_off.size() * sizeof(int64_t));
   L.con_mas = take(std::max<size_t>(1, M.con_mas.size()) * sizeof(int32_t));
   L.con_w = take(std::max<size_t>(1, M.con_w.size()) * sizeof(double));
   L.level = take(nl);
@@ -91,9 +91,8 @@ void estimate(Problem& P, const double* u, const double* f, char* ws, size_t byt
     // the tables of this mesh into the workspace (once per workspace)
     EHIPCHECK(hipMemcpyAsync(ws + L.cmap, M.leaf_cellmap.data(), M.leaf_cellmap.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, s));
-    std::vector<int64_t> off(M.con_off);
-    if (off.empty()) off.push_back(0);
-    EHIPCHECK(hipMemcpyAsync(ws + L.con_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    EHIPCHECK(hipMemcpyAsync(ws + L.con_off, T.con_off.data(), T.con_off.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
     if (!M.con_mas.empty()) {
       EHIPCHECK(hipMemcpyAsync(ws + L.con_mas, M.con_mas.data(), M.con_mas.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
@@ -106,8 +105,7 @@ void estimate(Problem& P, const double* u, const double* f, char* ws, size_t byt
     EHIPCHECK(hipMemcpyAsync(ws + L.kind, T.kind.data(), T.kind.size(), hipMemcpyHostToDevice, s));
     EHIPCHECK(hipMemcpyAsync(ws + L.off, T.off.data(), T.off.size(), hipMemcpyHostToDevice, s));
     EHIPCHECK(hipMemcpyAsync(ws + L.nb, T.nb.data(), T.nb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    // the sources are host vectors that outlive the call, but pageable: the
-    // copies complete before the launches below read them (stream order)
+    // the sources are host vectors of the problem, which outlive the copies
   }
   dev::EstView v;
   v.n_cells = M.n_leaves;

@@ -66,6 +66,8 @@ EstTables build_est_tables(const Maps& M) {
   T.kind.assign(size_t(nl) * T.nf, kFaceBoundary);
   T.off.assign(size_t(nl) * T.nf, 0);
   T.nb.assign(size_t(nl) * T.nf * T.nsub, -1);
+  T.con_off = M.con_off;
+  if (T.con_off.empty()) T.con_off.push_back(0);
   LeafIndex idx(M);
   for (int64_t i = 0; i < nl; ++i) {
     const int lv = M.leaf_level[i];

@@ -23,6 +23,8 @@ struct EstTables {
   // touching the face, entry b with bit t of b = upper half along the t-th
   // tangential axis; -1 unused
   std::vector<int32_t> nb;         // [n_leaves * nf * nsub]
+  // the constraint offsets of the leaf mesh, with at least one entry
+  std::vector<int64_t> con_off;
 };
 
 // the face tables of the leaf mesh of M (fails if a face has no consistent

@@ -195,3 +195,47 @@ def test_rhs_length_mismatch_fails_the_request():
     S.wait(rid, 120)
     assert S.result(rid)["status"] == 0
     S.close()
+
+
+def test_batched_iterations_at_degree_3():
+    """Requests whose kernels have no batched form for every step (3D Q3:
+    cooperative level passes, transfers and leaf operator run per request
+    inside the batched iteration) and 2D Q1 requests, each kind in its own
+    group, held until resident: every served result equals its solo solve
+    bit for bit."""
+    from paper_1904_03317_amd import gmg
+
+    def mesh3(r):
+        spec = gi.request_spec(r)
+        spec.g0, spec.target_dofs = 2, 4000.0
+        return gi.build_request_mesh(spec, lambda d, o: gmg.Mesh(d, o), lambda m, f: m.refine(f),
+                                     lambda m: m.leaves())
+
+    def mesh2(g):
+        return gmg.build_mesh(gi.workload("C1", g=g).recipe)
+
+    cases = [(lambda r=r: mesh3(r), gmg.options(degree=3, mg_precision=32)) for r in (1, 2, 3)]
+    cases += [(lambda g=g: mesh2(g), gmg.options(degree=1, mg_precision=64)) for g in (3, 4)]
+    S = gmg.Server(arena_bytes=1 << 30, max_slots=8, host_threads=3)
+    S.hold(True)
+    rids = [S.submit(mk(), o) for mk, o in cases]
+    t0 = time.time()
+    while not all(S.poll(rid)[0] == "RUNNING" for rid in rids) and time.time() - t0 < 120:
+        time.sleep(0.01)
+    S.hold(False)
+    for rid in rids:
+        S.wait(rid, 300)
+    st = S.stats()
+    print(f"[gpu] degree-3 and 2D batches: {st['batched_iterations']} of {st['iterations']} iterations batched "
+          f"in {st['batches']} batches", flush=True)
+    assert st["batched_iterations"] > 0
+    for rid, (mk, o) in zip(rids, cases):
+        res = S.result(rid)
+        P = gmg.Problem(mk(), o).bind()
+        u = torch.zeros(P.n_dofs, dtype=torch.float64, device="cuda")
+        s0, its0, _ = P.solve(torch.ones(P.n_dofs, dtype=torch.float64, device="cuda"), u)
+        torch.cuda.synchronize()
+        assert res["status"] == 0 and s0 == 0 and res["iterations"] == its0
+        assert np.array_equal(res["u"], u.cpu().numpy())
+        P.close()
+    S.close()
