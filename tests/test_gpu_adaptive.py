@@ -112,3 +112,45 @@ def test_adaptive_loop_matches_oracle():
     lo, ao = fo.leaves_arrays()
     assert np.array_equal(lv, lo) and np.array_equal(an, ao)
     assert isinstance(fo, Forest)
+
+
+def test_marking_edge_cases_and_errors():
+    """A mesh of one cell (every face on the boundary), marking fractions 0
+    and 1, equal estimates (ties in leaf order), and the refusals."""
+    from oracle.estimate import estimate, mark_fraction
+    from paper_1904_03317_amd import gmg
+    rec, k = CASES["cube-q1-g0"]
+    op, _ = oracle_problem(rec, k)
+    m, P, _ = library_problem(rec, k)
+    P.bind()
+    N = op.n_dofs
+    u = np.zeros(N)
+    f = np.ones(N)
+    ref = estimate(op.disc, u, f, np.ones(1))
+    ws = P.estimator_workspace()
+    eta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.estimate(_dev(u), _dev(f), eta, ws)
+    torch.cuda.synchronize()
+    assert abs(eta.item() - ref[0]) <= 1e-13 * abs(ref[0])   # the cell term of f = 1 alone
+    P.close()
+    # ties and fractions on a larger mesh: all estimates equal
+    rec, k = CASES["fichera-q2"]
+    m, P, _ = library_problem(rec, k)
+    P.bind()
+    n = P.info().n_leaves
+    ws = P.estimator_workspace()
+    eta = torch.ones(n, dtype=torch.float64, device="cuda")
+    flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    for frac in (0.0, 0.142, 1.0):
+        P.mark(eta, flags, ws, fraction=frac)
+        torch.cuda.synchronize()
+        fl = flags.cpu().numpy()
+        assert np.array_equal(fl, mark_fraction(np.ones(n), frac))
+        mcount = int(np.floor(frac * n + 0.5))
+        assert fl[:mcount].all() and not fl[mcount:].any()       # equal values: leaf order
+    with pytest.raises(gmg.GMGError):
+        P.mark(eta, flags, ws, fraction=1.5)
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gmg.GMGError):
+        P.estimate(eta, eta, eta, small)
+    P.close()
