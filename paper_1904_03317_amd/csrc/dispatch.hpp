@@ -48,18 +48,15 @@ struct LeafView {
   const int32_t* slot = nullptr;    // SoA [npc][n_cells] slot in the node-major buffer
   const int32_t* soff = nullptr;    // [n_dofs + 1]
   const uint8_t* dir = nullptr;     // [n_dofs] Dirichlet flag
-  // tiles of 64 cells (all but 3D at degree >= 3; host/leaftiles.hpp):
-  // per tile the range of its nodes, counts of complete and partial nodes,
-  // first partial slot; node DoFs (~dof: complete Dirichlet node); per
-  // (position, cell) the tile-local node; the second-pass nodes and their
-  // slot lists
-  int64_t n_tiles = 0, n_part = 0, n_p2 = 0;
+  // tiles of 64 cells (all but 3D at degree >= 3; host/leaftiles.hpp): per
+  // tile its own DoF range and its listed nodes (listed entry i writes slot
+  // i); per (position, cell) the tile-local node (own nodes first, then the
+  // listed ones); the second-pass nodes and their slot lists
+  int64_t n_tiles = 0, n_slots = 0, n_p2 = 0;
   int32_t max_nodes = 0;
-  const int64_t* t_off = nullptr;   // [n_tiles + 1]
-  const int32_t* t_na = nullptr;    // [n_tiles]
-  const int32_t* t_nb = nullptr;    // [n_tiles]
-  const int32_t* t_pbase = nullptr; // [n_tiles]
-  const int32_t* t_node = nullptr;
+  const int32_t* t_own = nullptr;   // [n_tiles + 1]
+  const int64_t* t_loff = nullptr;  // [n_tiles + 1]
+  const int32_t* t_list = nullptr;  // [n_slots]
   const uint16_t* lmap = nullptr;   // SoA [npc][n_cells]
   const int32_t* p2_dof = nullptr;  // [n_p2]
   const int32_t* p2_off = nullptr;  // [n_p2 + 1]

@@ -42,13 +42,18 @@ constexpr int kEstLds = 4 * 25 + 10 + 5;
 template <int NP>
 __device__ __forceinline__ void est_gather(const EstView& v, int64_t c, const double* __restrict__ x,
                                            double (&u)[NP]) {
+  // all map entries, then all node values (a hanging position reads node 0
+  // and is overwritten below), so that the loads issue together; then the
+  // hanging positions, interpolated from their constraint rows
+  int32_t mm[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) mm[j] = v.cmap[c * NP + j];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) u[j] = x[mm[j] >= 0 ? mm[j] : 0];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
-    const int32_t m = v.cmap[c * NP + j];
-    if (m >= 0) {
-      u[j] = x[m];
-    } else {
-      const int64_t h = -(int64_t)m - 1;
+    if (mm[j] < 0) {
+      const int64_t h = -(int64_t)mm[j] - 1;
       double s = 0.0;
       for (int64_t p = v.con_off[h]; p < v.con_off[h + 1]; ++p) s += v.con_w[p] * x[v.con_mas[p]];
       u[j] = s;

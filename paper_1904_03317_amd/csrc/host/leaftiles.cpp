@@ -69,8 +69,9 @@ class TileMap {
 };
 
 struct ChunkOut {
-  std::vector<int32_t> node;
-  std::vector<int32_t> na, nb, ntot;
+  std::vector<int32_t> list;
+  std::vector<int64_t> nlist;
+  int32_t max_nodes = 0;
 };
 
 }  // namespace
@@ -81,132 +82,103 @@ LeafTiles build_leaf_tiles(const Maps& M, int threads) {
   const int npc = M.npc;
   if (npc * TC > 0x8000) fail(-1, "leaf tiles need at most 512 nodes per cell");
   const int64_t nl = M.n_leaves, N = M.n_dofs;
-  const std::vector<int32_t>& cm = M.leaf_cellmap_parent;
+  if (N >= INT32_MAX) fail(-1, "leaf tiles need fewer than 2^31 DoFs");
+  const std::vector<int32_t>& cm = M.leaf_cellmap;          // DoF or -(h+1) (hanging)
+  const std::vector<int32_t>& cp = M.leaf_cellmap_parent;   // DoFs only
   LeafTiles T;
   T.n_tiles = (nl + TC - 1) / TC;
   const int64_t ntl = T.n_tiles;
 
-  // contributions per DoF: the (cell, position) entries targeting it
-  std::vector<uint16_t> total(N, 0);
-  const int nch = (int)std::max<int64_t>(1, std::min<int64_t>(4 * nt, (nl + 4095) / 4096));
-  for_chunks(nch, nt, [&](int ch) {
-    const int64_t c0 = nl * ch / nch, c1 = nl * (ch + 1) / nch;
-    for (int64_t c = c0; c < c1; ++c) {
-      for (int j = 0; j < npc; ++j) {
-        const int32_t d = cm[size_t(c) * npc + j];
-        if (d < 0 || d >= N) fail(-8, "leaf cell map out of range");
-        __atomic_fetch_add(&total[d], (uint16_t)1, __ATOMIC_RELAXED);
+  // own ranges: with first-touch numbering in leaf order, the DoFs numbered
+  // before tile t are 0 .. (largest DoF of a node of the tiles before t);
+  // the ranges partition [0, N) in any case, which is all that correctness
+  // needs (a DoF outside its tile's range is listed by the tiles touching it)
+  std::vector<int32_t> tmax(ntl, -1);
+  const int tch = (int)std::max<int64_t>(1, std::min<int64_t>(8 * nt, (ntl + 63) / 64));
+  for_chunks(tch, nt, [&](int ch) {
+    const int64_t t0 = ntl * ch / tch, t1 = ntl * (ch + 1) / tch;
+    for (int64_t t = t0; t < t1; ++t) {
+      int32_t mx = -1;
+      for (int64_t i = t * TC * npc, e = std::min<int64_t>(nl, (t + 1) * TC) * npc; i < e; ++i) {
+        const int32_t d = cm[size_t(i)];
+        if (d >= N) fail(-8, "leaf cell map out of range");
+        mx = std::max(mx, d);
       }
+      tmax[t] = mx;
     }
   });
+  T.own.assign(ntl + 1, 0);
+  for (int64_t t = 0; t < ntl; ++t) T.own[t + 1] = std::max(T.own[t], tmax[t] + 1);
+  T.own[ntl] = (int32_t)N;
 
-  // per tile: first-touch node list; complete nodes (every contribution in
-  // this tile) first
+  // per tile: local index of every (cell, position), listed nodes in order of
+  // first reference
   T.lmap.assign(size_t(nl) * npc, 0);
-  std::vector<uint8_t> complete(N, 0);
-  const int tch = (int)std::max<int64_t>(1, std::min<int64_t>(8 * nt, (ntl + 63) / 64));
   std::vector<ChunkOut> outs(tch);
   for_chunks(tch, nt, [&](int ch) {
     const int64_t t0 = ntl * ch / tch, t1 = ntl * (ch + 1) / tch;
     ChunkOut& O = outs[ch];
     TileMap tm;
-    std::vector<int32_t> ft, acc, rank;
-    std::vector<int32_t> idx(size_t(TC) * npc);
     for (int64_t t = t0; t < t1; ++t) {
       const int64_t c0 = t * TC, c1 = std::min<int64_t>(nl, c0 + TC);
+      const int32_t lo = T.own[t], R = T.own[t + 1] - lo;
+      const size_t base = O.list.size();
       tm.clear();
-      ft.clear();
-      acc.clear();
       for (int64_t c = c0; c < c1; ++c)
         for (int j = 0; j < npc; ++j) {
-          const int32_t d = cm[size_t(c) * npc + j];
-          const int32_t i = tm.get_or_insert(d, (int32_t)ft.size());
-          if (i == (int32_t)ft.size()) {
-            ft.push_back(d);
-            acc.push_back(0);
+          const int32_t d = cp[size_t(c) * npc + j];
+          if (d < 0 || d >= N) fail(-8, "leaf cell map out of range");
+          int32_t i = d - lo;
+          if (i < 0 || i >= R) {
+            const int32_t n = (int32_t)(O.list.size() - base);
+            const int32_t li = tm.get_or_insert(d, n);
+            if (li == n) O.list.push_back(d);
+            i = R + li;
           }
-          ++acc[i];
-          idx[size_t(c - c0) * npc + j] = i;
+          if (i >= 0x8000) fail(-8, "leaf tile with too many nodes");
+          T.lmap[size_t(c) * npc + j] = (uint16_t)i;
         }
-      const int32_t n = (int32_t)ft.size();
-      if (n >= 0x8000) fail(-8, "leaf tile with too many nodes");
-      rank.assign(n, 0);
-      int32_t na = 0;
-      for (int32_t i = 0; i < n; ++i) na += acc[i] == total[ft[i]];
-      int32_t pa = 0, pb = na;
-      const size_t base = O.node.size();
-      O.node.resize(base + n);
-      for (int32_t i = 0; i < n; ++i) {
-        const int32_t d = ft[i];
-        int32_t r;
-        if (acc[i] == total[d]) {
-          r = pa++;
-          complete[d] = 1;  // this tile is the only one touching d
-          O.node[base + r] = M.dirichlet[d] ? ~d : d;
-        } else {
-          r = pb++;
-          O.node[base + r] = d;
-        }
-        rank[i] = r;
-      }
-      for (int64_t c = c0; c < c1; ++c)
-        for (int j = 0; j < npc; ++j) T.lmap[size_t(c) * npc + j] = (uint16_t)rank[idx[size_t(c - c0) * npc + j]];
-      O.na.push_back(na);
-      O.nb.push_back(n - na);
-      O.ntot.push_back(n);
+      const int64_t L = (int64_t)(O.list.size() - base);
+      O.nlist.push_back(L);
+      O.max_nodes = std::max<int32_t>(O.max_nodes, R + (int32_t)L);
     }
   });
-  T.node_off.assign(ntl + 1, 0);
-  T.n_complete.resize(ntl);
-  T.n_partial.resize(ntl);
-  T.pbase.resize(ntl);
+  T.list_off.assign(ntl + 1, 0);
   {
-    int64_t t = 0, off = 0, pb = 0;
-    for (int ch = 0; ch < tch; ++ch)
-      for (size_t i = 0; i < outs[ch].na.size(); ++i, ++t) {
-        T.node_off[t] = off;
-        T.n_complete[t] = outs[ch].na[i];
-        T.n_partial[t] = outs[ch].nb[i];
-        T.pbase[t] = (int32_t)pb;
-        off += outs[ch].ntot[i];
-        pb += outs[ch].nb[i];
-        T.max_nodes = std::max(T.max_nodes, outs[ch].ntot[i]);
+    int64_t t = 0, off = 0;
+    for (int ch = 0; ch < tch; ++ch) {
+      for (int64_t L : outs[ch].nlist) {
+        T.list_off[t++] = off;
+        off += L;
       }
-    T.node_off[ntl] = off;
-    T.n_part = pb;
-    if (off >= INT32_MAX || pb >= INT32_MAX) fail(-1, "leaf tiles exceed 2^31 entries");
-    T.node.resize(off);
+      T.max_nodes = std::max(T.max_nodes, outs[ch].max_nodes);
+    }
+    T.list_off[ntl] = off;
+    if (off >= INT32_MAX) fail(-1, "leaf tiles exceed 2^31 listed entries");
+    T.list.assign(off + 1, 0);  // one padding entry, read by lanes without a listed node
     int64_t o = 0;
     for (int ch = 0; ch < tch; ++ch) {
-      std::copy(outs[ch].node.begin(), outs[ch].node.end(), T.node.begin() + o);
-      o += (int64_t)outs[ch].node.size();
-      std::vector<int32_t>().swap(outs[ch].node);
+      std::copy(outs[ch].list.begin(), outs[ch].list.end(), T.list.begin() + o);
+      o += (int64_t)outs[ch].list.size();
+      std::vector<int32_t>().swap(outs[ch].list);
     }
   }
 
-  // second pass: every DoF not complete in a tile, with the partial slots
-  // of the tiles touching it, in tile order
+  // second pass: every DoF with listed entries, its slots in ascending order
+  const int64_t ns = T.n_slots();
+  std::vector<int32_t> cnt(N, 0);
+  for (int64_t i = 0; i < ns; ++i) ++cnt[T.list[i]];
   std::vector<int32_t> pos(N, -1);
+  T.p2_off.push_back(0);
   for (int64_t d = 0; d < N; ++d)
-    if (!complete[d]) {
+    if (cnt[d]) {
       pos[d] = (int32_t)T.p2_dof.size();
       T.p2_dof.push_back((int32_t)d);
+      T.p2_off.push_back(T.p2_off.back() + cnt[d]);
     }
-  const int64_t n2 = (int64_t)T.p2_dof.size();
-  std::vector<int64_t> cnt(n2 + 1, 0);
-  for (int64_t t = 0; t < ntl; ++t) {
-    const int64_t i0 = T.node_off[t] + T.n_complete[t];
-    for (int32_t i = 0; i < T.n_partial[t]; ++i) ++cnt[pos[T.node[i0 + i]] + 1];
-  }
-  for (int64_t i = 0; i < n2; ++i) cnt[i + 1] += cnt[i];
-  if (cnt[n2] >= INT32_MAX) fail(-1, "leaf slots exceed 2^31");
-  T.p2_off.assign(cnt.begin(), cnt.end());
-  T.p2_slot.assign(cnt[n2], 0);
-  std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
-  for (int64_t t = 0; t < ntl; ++t) {
-    const int64_t i0 = T.node_off[t] + T.n_complete[t];
-    for (int32_t i = 0; i < T.n_partial[t]; ++i) T.p2_slot[cur[pos[T.node[i0 + i]]]++] = T.pbase[t] + i;
-  }
+  T.p2_slot.assign(ns, 0);
+  std::vector<int32_t> cur(T.p2_off.begin(), T.p2_off.end() - 1);
+  for (int64_t i = 0; i < ns; ++i) T.p2_slot[cur[pos[T.list[i]]]++] = (int32_t)i;
   return T;
 }
 

@@ -858,10 +858,10 @@ Maps build_maps(const Forest& f, int k, const double* coeff, int threads) {
     M.tiles = build_leaf_tiles(M, nthreads);
     T.mark("leaf tiles");
     if (T.on)
-      std::fprintf(stderr, "[gmg maps] leaf tiles: %lld tiles, %lld tile nodes, %zu second-pass DoFs, %lld partial "
-                   "slots, largest tile %d nodes\n",
-                   (long long)M.tiles.n_tiles, (long long)M.tiles.node.size(), M.tiles.p2_dof.size(),
-                   (long long)M.tiles.n_part, M.tiles.max_nodes);
+      std::fprintf(stderr, "[gmg maps] leaf tiles: %lld tiles, %lld listed nodes, %zu second-pass DoFs, largest "
+                   "tile %d nodes\n",
+                   (long long)M.tiles.n_tiles, (long long)M.tiles.n_slots(), M.tiles.p2_dof.size(),
+                   M.tiles.max_nodes);
   }
   return M;
 }

@@ -683,17 +683,17 @@ __global__ void __launch_bounds__(kBlock) cell_to_slots(
 // Leaf operator q = C^T A C p (or the mass matrix) on tiles of 64
 // consecutive leaf cells, one wavefront (block) per tile at a time, the
 // tiles of a block contiguous.  Per tile: the values of all nodes the cells
-// touch are gathered once into LDS; each lane takes one cell (in-cell
+// touch are gathered once into LDS, the tile's own DoFs (a contiguous range)
+// first, then its listed nodes; each lane takes one cell (in-cell
 // constraints forward, operator, constraints transposed) and adds its
 // results into LDS position by position, the results of constrained
 // positions into the parent's nodes.  Only this wave adds into the tile's
 // LDS, its adds issue in a fixed order, and same-address adds within one
 // instruction are resolved by the LDS unit in a fixed order, so every sum is
-// formed in the same order on every run.  Then the tile's complete nodes
-// (all their contributions are in this tile) are written to q, Dirichlet
-// rows as zero, and the others to the tile's partial slots, which
-// leaf_pass2 sums.  DOT: one partial sum of p.q per block over the complete
-// nodes.
+// formed in the same order on every run.  Then the own nodes' sums are
+// written to q (Dirichlet rows zero) and the listed nodes' sums to their
+// slots, which leaf_pass2 adds to q.  DOT: one partial sum of p.q per block
+// over the own nodes' sums (leaf_pass2 adds p.q over the slots).
 
 // one leaf cell: in-cell constraints on the cell reflected to child
 // position 0 (a cell without constrained entities is neither reflected nor
@@ -721,7 +721,23 @@ __device__ __forceinline__ void leaf_cell(const MT& m, uint32_t mk, double* u, d
 
 constexpr int kLeafBlocks = 8192;  // grid of leaf_tiles at most (32 one-wave blocks per CU)
 constexpr int kLeafGB = 16;        // tile nodes per lane whose loads are issued together
+constexpr int kLeafOwn = 8;        // own nodes per lane per write-out round
 
+// LDS ordering between the lanes of a one-wavefront block: the wave's LDS
+// accesses are performed in program order, so the block needs no hardware
+// barrier (which would also wait for its outstanding global stores), only
+// fences that keep the compiler from moving memory accesses across this
+// point
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Every global load below reads a valid address on every lane (indices
+// clamped into their arrays; the listed-node array has one padding entry),
+// and the lanes without a node drop the value: loads under a lane mask were
+// compiled into branches that waited for each load before issuing the next.
 template <int DIM, int N, bool MASS, bool DOT>
 __device__ __forceinline__ void leaf_tiles_at(const LeafView& v, const double* __restrict__ x,
                                               double* __restrict__ y, double* __restrict__ E,
@@ -732,25 +748,39 @@ __device__ __forceinline__ void leaf_tiles_at(const LeafView& v, const double* _
   const int lane = threadIdx.x;
   const int64_t lb = xcd_block_of(b, G);
   const int64_t t0 = v.n_tiles * lb / G, t1 = v.n_tiles * (lb + 1) / G;
+  const int64_t nlast = v.n_dofs - 1;
   double dot = 0.0;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t nb = v.t_off[t];
-    const int nt = (int)(v.t_off[t + 1] - nb);
-    const int na = v.t_na[t], np = v.t_nb[t];
-    // gather, in rounds of kLeafGB nodes per lane: all node ids, then all
-    // values, then the LDS stores (no load waits on another inside a round)
+    const int32_t lo = v.t_own[t];
+    const int R = v.t_own[t + 1] - lo;
+    const int64_t l0 = v.t_loff[t];
+    const int L = (int)(v.t_loff[t + 1] - l0);
+    const int nt = R + L;
+    const int64_t c = t * 64 + lane;
+    const bool live = c < v.n_cells;
+    const int64_t cc = live ? c : v.n_cells - 1;
+    // the cells' local indices, constraint masks and scales first: their
+    // latency passes during the gather
+    uint32_t lu[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) lu[j] = v.lmap[(int64_t)j * v.n_cells + cc];
+    const uint32_t mk = v.mask[cc];
+    const double sc = live ? (MASS ? v.mscale[cc] : v.scale[cc]) : 0.0;
+    // gather, in rounds of kLeafGB nodes per lane: the listed node ids, then
+    // all values, then the LDS stores
     for (int i0 = 0; i0 < nt; i0 += 64 * kLeafGB) {
-      int32_t d[kLeafGB];
+      int32_t li[kLeafGB];
       double xv[kLeafGB];
 #pragma unroll
       for (int k = 0; k < kLeafGB; ++k) {
         const int i = i0 + lane + 64 * k;
-        d[k] = i < nt ? v.t_node[nb + i] : 0;
+        li[k] = v.t_list[l0 + (i < R ? 0 : i - R < L ? i - R : L)];
       }
 #pragma unroll
       for (int k = 0; k < kLeafGB; ++k) {
         const int i = i0 + lane + 64 * k;
-        xv[k] = i < nt ? x[d[k] < 0 ? ~d[k] : d[k]] : 0.0;
+        const int64_t d = i < R ? (int64_t)lo + i : i < nt ? (int64_t)li[k] : 0;
+        xv[k] = x[d];
       }
 #pragma unroll
       for (int k = 0; k < kLeafGB; ++k) {
@@ -758,72 +788,80 @@ __device__ __forceinline__ void leaf_tiles_at(const LeafView& v, const double* _
         if (i < nt) lds[i] = xv[k];
       }
     }
-    __syncthreads();
-    const int64_t c = t * 64 + lane;
-    const bool live = c < v.n_cells;
+    wave_lds_sync();
     double w[NP];
     {
       double u[NP];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const uint32_t l = live ? (uint32_t)v.lmap[(int64_t)j * v.n_cells + c] : 0u;
-        u[j] = live ? lds[l] : 0.0;
-      }
-      const uint32_t mk = live ? (uint32_t)v.mask[c] : 0u;
+      for (int j = 0; j < NP; ++j) u[j] = lds[lu[j]];
       if constexpr (N <= 3)
         leaf_cell<DIM, N, MASS>(Exact1D<N>{}, mk, u, w);
       else
         leaf_cell<DIM, N, MASS>(m, mk, u, w);
-      const double sc = live ? (MASS ? v.mscale[c] : v.scale[c]) : 0.0;
 #pragma unroll
       for (int j = 0; j < NP; ++j) w[j] *= sc;
     }
     // the local indices again (cached) rather than held in registers through
-    // the operator; not scheduled above this point
+    // the operator; not scheduled above this point, and the cell index passed
+    // through an empty asm statement so that the compiler cannot merge this
+    // read with the first one
     __builtin_amdgcn_sched_barrier(0);
+    int64_t cr = cc;
+    asm volatile("" : "+v"(cr));
     uint32_t lm[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) lm[j] = live ? (uint32_t)v.lmap[(int64_t)j * v.n_cells + c] : 0u;
-    __syncthreads();
-    for (int i = lane; i < na + np; i += 64) lds[i] = 0.0;
-    __syncthreads();
+    for (int j = 0; j < NP; ++j) lm[j] = v.lmap[(int64_t)j * v.n_cells + cr];
+    // the first write-out round's Dirichlet flags and p values, loaded now so
+    // that their latency passes during the LDS phase
+    uint8_t dr[kLeafOwn];
+    double xd[kLeafOwn];
+#pragma unroll
+    for (int k = 0; k < kLeafOwn; ++k) {
+      const int64_t d = (int64_t)lo + lane + 64 * k < nlast ? (int64_t)lo + lane + 64 * k : nlast;
+      dr[k] = v.dir[d];
+      if (DOT) xd[k] = x[d];
+    }
+    wave_lds_sync();
+    for (int i = lane; i < nt; i += 64) lds[i] = 0.0;
+    wave_lds_sync();
     if (live) {
 #pragma unroll
       for (int j = 0; j < NP; ++j) atomicAdd(&lds[lm[j]], w[j]);
     }
-    __syncthreads();
-    // write-out in rounds as the gather: complete nodes to y (Dirichlet rows
-    // zero), partial ones to the tile's slots
-    double* pslot = E + v.t_pbase[t] - na;
-    for (int i0 = 0; i0 < na + np; i0 += 64 * kLeafGB) {
-      int32_t d[kLeafGB];
-      double q[kLeafGB], xd[kLeafGB];
+    wave_lds_sync();
+    // write-out: own nodes to y (Dirichlet rows zero) in rounds of kLeafOwn
+    // per lane, then the listed ones to their slots
+    for (int i0 = 0; i0 < R; i0 += 64 * kLeafOwn) {
+      if (i0 > 0) {
 #pragma unroll
-      for (int k = 0; k < kLeafGB; ++k) {
-        const int i = i0 + lane + 64 * k;
-        d[k] = i < na ? v.t_node[nb + i] : -1;
-        q[k] = i < na + np ? lds[i] : 0.0;
-      }
-      if (DOT) {
-#pragma unroll
-        for (int k = 0; k < kLeafGB; ++k) xd[k] = d[k] >= 0 ? x[d[k]] : 0.0;
+        for (int k = 0; k < kLeafOwn; ++k) {
+          const int64_t d = (int64_t)lo + i0 + lane + 64 * k < nlast ? (int64_t)lo + i0 + lane + 64 * k : nlast;
+          dr[k] = v.dir[d];
+          if (DOT) xd[k] = x[d];
+        }
       }
 #pragma unroll
-      for (int k = 0; k < kLeafGB; ++k) {
+      for (int k = 0; k < kLeafOwn; ++k) {
         const int i = i0 + lane + 64 * k;
-        if (i < na) {
-          if (d[k] < 0) {
-            y[~d[k]] = 0.0;
-          } else {
-            y[d[k]] = q[k];
-            if (DOT) dot += xd[k] * q[k];
-          }
-        } else if (i < na + np) {
-          pslot[i] = q[k];
+        if (i < R) {
+          const double qk = dr[k] ? 0.0 : lds[i];
+          y[lo + i] = qk;
+          if (DOT) dot += xd[k] * qk;
         }
       }
     }
-    __syncthreads();
+    double* lslot = E + l0 - R;
+    for (int i0 = R; i0 < nt; i0 += 64 * kLeafGB) {
+      double q[kLeafGB];
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) q[k] = lds[i0 + lane + 64 * k < nt ? i0 + lane + 64 * k : nt - 1];
+#pragma unroll
+      for (int k = 0; k < kLeafGB; ++k) {
+        const int i = i0 + lane + 64 * k;
+        if (i < nt) lslot[i] = q[k];
+      }
+    }
+    wave_lds_sync();
   }
   if (DOT) {
     for (int o = 32; o > 0; o >>= 1) dot += __shfl_down(dot, o, 64);
@@ -1449,9 +1487,10 @@ __global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restric
 // together; one partial per block, summed in fixed order by cg_scalars)
 constexpr int kFuseNPT = 8;
 
-// tiled leaf operator, pass 2: the nodes summed from slots (partial sums of
-// the tiles touching them and constrained contributions, in ascending slot
-// order), Dirichlet rows zero; DOT: partial sums of p.q per block
+// tiled leaf operator, pass 2: the listed nodes' slots (sums of the tiles
+// listing them, in ascending slot order) added to q, which holds the owning
+// tile's sum; Dirichlet rows stay zero; DOT: partial sums of p.q over the
+// added parts per block
 template <bool DOT>
 __device__ __forceinline__ void leaf_pass2_at(const LeafView& v, const double* __restrict__ E,
                                               const double* __restrict__ x, double* __restrict__ y,
@@ -1474,6 +1513,13 @@ __device__ __forceinline__ void leaf_pass2_at(const LeafView& v, const double* _
   for (int k = 0; k < kFuseNPT; ++k)
 #pragma unroll
     for (int j = 0; j < kP2S; ++j) sl[k][j] = o0[k] + j < o1[k] ? v.p2_slot[o0[k] + j] : -1;
+  double y0[kFuseNPT];
+  uint8_t dr[kFuseNPT];
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    y0[k] = d[k] >= 0 ? y[d[k]] : 0.0;
+    dr[k] = d[k] >= 0 ? v.dir[d[k]] : 1;
+  }
   double q[kFuseNPT];
 #pragma unroll
   for (int k = 0; k < kFuseNPT; ++k) {
@@ -1485,10 +1531,9 @@ __device__ __forceinline__ void leaf_pass2_at(const LeafView& v, const double* _
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < kFuseNPT; ++k) {
-    if (d[k] >= 0) {
-      const double qk = v.dir[d[k]] ? 0.0 : q[k];
-      y[d[k]] = qk;
-      if (DOT) s += x[d[k]] * qk;
+    if (!dr[k]) {
+      y[d[k]] = y0[k] + q[k];
+      if (DOT) s += x[d[k]] * q[k];
     }
   }
   if (DOT) {

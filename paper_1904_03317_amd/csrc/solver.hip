@@ -194,19 +194,17 @@ size_t plan_workspace(Problem& P, char* base) {
   int64_t e_leaf = 0;
   if (tiled) {
     P.leaf.n_tiles = LT.n_tiles;
-    P.leaf.n_part = LT.n_part;
+    P.leaf.n_slots = LT.n_slots();
     P.leaf.n_p2 = (int64_t)LT.p2_dof.size();
     P.leaf.max_nodes = LT.max_nodes;
-    P.leaf.t_off = pl.take<int64_t>(LT.node_off.size());
-    P.leaf.t_na = pl.take<int32_t>(LT.n_tiles);
-    P.leaf.t_nb = pl.take<int32_t>(LT.n_tiles);
-    P.leaf.t_pbase = pl.take<int32_t>(LT.n_tiles);
-    P.leaf.t_node = pl.take<int32_t>(LT.node.size());
+    P.leaf.t_own = pl.take<int32_t>(LT.own.size());
+    P.leaf.t_loff = pl.take<int64_t>(LT.list_off.size());
+    P.leaf.t_list = pl.take<int32_t>(LT.list.size());
     P.leaf.lmap = pl.take<uint16_t>(LT.lmap.size());
     P.leaf.p2_dof = pl.take<int32_t>(LT.p2_dof.size());
     P.leaf.p2_off = pl.take<int32_t>(LT.p2_off.size());
     P.leaf.p2_slot = pl.take<int32_t>(LT.p2_slot.size());
-    e_leaf = LT.n_part;
+    e_leaf = LT.n_slots();
   } else {
     P.leaf.cmap = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
     P.leaf.slot = pl.take<int32_t>(size_t(M.n_leaves) * M.npc);
@@ -537,11 +535,9 @@ void bind_problem(Problem& P, void* ws, size_t bytes, hipStream_t s) {
     h2d(P.leaf.dir, M.dirichlet, s);
     if (P.leaf.n_tiles) {
       const LeafTiles& LT = M.tiles;
-      h2d(P.leaf.t_off, LT.node_off, s);
-      h2d(P.leaf.t_na, LT.n_complete, s);
-      h2d(P.leaf.t_nb, LT.n_partial, s);
-      h2d(P.leaf.t_pbase, LT.pbase, s);
-      h2d(P.leaf.t_node, LT.node, s);
+      h2d(P.leaf.t_own, LT.own, s);
+      h2d(P.leaf.t_loff, LT.list_off, s);
+      h2d(P.leaf.t_list, LT.list, s);
       h2d(P.leaf.lmap, soa(LT.lmap, M.n_leaves, M.npc), s);
       h2d(P.leaf.p2_dof, LT.p2_dof, s);
       h2d(P.leaf.p2_off, LT.p2_off, s);
@@ -649,7 +645,7 @@ void apply_leaf(Problem& P, const double* x, double* y, bool mass, hipStream_t s
 }
 
 int64_t leaf_slots(const Problem& P) {
-  return P.leaf.n_tiles ? P.maps->tiles.n_part : P.maps->n_leaves * P.maps->npc;
+  return P.leaf.n_tiles ? P.maps->tiles.n_slots() : P.maps->n_leaves * P.maps->npc;
 }
 
 

@@ -184,6 +184,11 @@ inline T __shfl_xor(T v, int mask, int w = 64) {
 // every thread of the block must take part
 // scheduling barrier of the device compiler: nothing to do on the host
 inline void __builtin_amdgcn_sched_barrier(int) {}
+// a wavefront-wide barrier: the lanes of the emulated block (the kernels use
+// it only in one-wavefront blocks) meet here, as the hardware wave executes
+// them in lockstep
+inline void __builtin_amdgcn_wave_barrier() { __syncthreads(); }
+inline void __builtin_amdgcn_fence(int, const char*) {}
 inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool) {
   const unsigned t = threadIdx.x;
   emu::g_shfl[t] = (double)v;

@@ -62,6 +62,25 @@ def test_leaf_nodes_distinct_per_local_position(name, g):
         assert len(np.unique(col)) == len(col), j
 
 
+# The tiled leaf operator reads and writes the DoFs first touched by the
+# cells of a tile (64 consecutive leaf cells) as one contiguous range, with no
+# index list: the first-touch numbering in leaf order must give each tile a
+# contiguous run of new DoFs, i.e. the tile of a DoF's first touch is
+# non-decreasing in the DoF number, and consecutive tiles' runs are adjacent.
+@pytest.mark.parametrize("name,g", [("C1", None), ("C2", 2), ("C5", 2)])
+def test_first_touch_tiles_are_contiguous_ranges(name, g):
+    w = gi.workload(name, g=g)
+    m, P, _ = library_problem(w.recipe, w.degree)
+    npc = (w.degree + 1) ** m.dim
+    cm = P.array("LEAF_CELLMAP").reshape(-1, npc)
+    tile = np.repeat(np.arange(len(cm)) // 64, npc).reshape(cm.shape)
+    real = cm >= 0
+    first = np.full(P.n_dofs, np.iinfo(np.int64).max)
+    np.minimum.at(first, cm[real], tile[real])
+    assert first.max() < len(cm)  # every DoF is a node of some leaf
+    assert np.all(np.diff(first) >= 0)
+
+
 def test_closure_matches_oracle_random_flags():
     rng = np.random.default_rng(11)
     origins = gi.coarse_mesh("fichera")[1]
