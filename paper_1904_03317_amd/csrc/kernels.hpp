@@ -1486,6 +1486,8 @@ __global__ void __launch_bounds__(kBlock) update_xr(int64_t n, double* __restric
 // consecutive block-strided nodes, unrolled so that their loads issue
 // together; one partial per block, summed in fixed order by cg_scalars)
 constexpr int kFuseNPT = 8;
+// nodes per thread of the leaf operator's second pass
+constexpr int kP2NPT = 4;
 
 // tiled leaf operator, pass 2: the listed nodes' slots (sums of the tiles
 // listing them, in ascending slot order) added to q, which holds the owning
@@ -1495,45 +1497,58 @@ template <bool DOT>
 __device__ __forceinline__ void leaf_pass2_at(const LeafView& v, const double* __restrict__ E,
                                               const double* __restrict__ x, double* __restrict__ y,
                                               double* __restrict__ part, int64_t b) {
-  // the first kP2S slots of every node unrolled, so that the loads of all
-  // nodes of a thread issue together; longer lists (rare) continue in a loop
-  constexpr int kP2S = 4;
-  const int64_t base = b * blockDim.x * kFuseNPT + threadIdx.x;
-  int32_t d[kFuseNPT], o0[kFuseNPT], o1[kFuseNPT];
+  // kP2NPT nodes per thread, the first kP2S slots of each unrolled so that
+  // the loads of all of them issue together; longer lists continue in a
+  // loop.  Every load reads a valid address (node index clamped to the last
+  // node, slot index to the node's last slot: every node has one) and the
+  // unused values are dropped, since loads under a lane mask were compiled
+  // into branches that waited for each load before issuing the next.
+  constexpr int kP2S = 2;
+  const int64_t base = b * blockDim.x * kP2NPT + threadIdx.x;
+  const int64_t last = v.n_p2 - 1;
+  bool in[kP2NPT];
+  int32_t d[kP2NPT], o0[kP2NPT], o1[kP2NPT];
 #pragma unroll
-  for (int k = 0; k < kFuseNPT; ++k) {
+  for (int k = 0; k < kP2NPT; ++k) {
     const int64_t i = base + (int64_t)k * blockDim.x;
-    const bool in = i < v.n_p2;
-    d[k] = in ? v.p2_dof[i] : -1;
-    o0[k] = in ? v.p2_off[i] : 0;
-    o1[k] = in ? v.p2_off[i + 1] : 0;
+    in[k] = i <= last;
+    const int64_t ic = in[k] ? i : last;
+    d[k] = v.p2_dof[ic];
+    o0[k] = v.p2_off[ic];
+    o1[k] = v.p2_off[ic + 1];
   }
-  int32_t sl[kFuseNPT][kP2S];
+  int32_t sl[kP2NPT][kP2S];
 #pragma unroll
-  for (int k = 0; k < kFuseNPT; ++k)
+  for (int k = 0; k < kP2NPT; ++k)
 #pragma unroll
-    for (int j = 0; j < kP2S; ++j) sl[k][j] = o0[k] + j < o1[k] ? v.p2_slot[o0[k] + j] : -1;
-  double y0[kFuseNPT];
-  uint8_t dr[kFuseNPT];
+    for (int j = 0; j < kP2S; ++j) sl[k][j] = v.p2_slot[o0[k] + j < o1[k] ? o0[k] + j : o1[k] - 1];
+  double y0[kP2NPT], xd[kP2NPT];
+  uint8_t dr[kP2NPT];
 #pragma unroll
-  for (int k = 0; k < kFuseNPT; ++k) {
-    y0[k] = d[k] >= 0 ? y[d[k]] : 0.0;
-    dr[k] = d[k] >= 0 ? v.dir[d[k]] : 1;
+  for (int k = 0; k < kP2NPT; ++k) {
+    y0[k] = y[d[k]];
+    dr[k] = v.dir[d[k]];
+    if (DOT) xd[k] = x[d[k]];
   }
-  double q[kFuseNPT];
+  double ev[kP2NPT][kP2S];
 #pragma unroll
-  for (int k = 0; k < kFuseNPT; ++k) {
+  for (int k = 0; k < kP2NPT; ++k)
+#pragma unroll
+    for (int j = 0; j < kP2S; ++j) ev[k][j] = E[sl[k][j]];
+  double q[kP2NPT];
+#pragma unroll
+  for (int k = 0; k < kP2NPT; ++k) {
     q[k] = 0.0;
 #pragma unroll
-    for (int j = 0; j < kP2S; ++j) q[k] += sl[k][j] >= 0 ? E[sl[k][j]] : 0.0;
+    for (int j = 0; j < kP2S; ++j) q[k] += o0[k] + j < o1[k] ? ev[k][j] : 0.0;
     for (int32_t o = o0[k] + kP2S; o < o1[k]; ++o) q[k] += E[v.p2_slot[o]];
   }
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < kFuseNPT; ++k) {
-    if (!dr[k]) {
+  for (int k = 0; k < kP2NPT; ++k) {
+    if (in[k] && !dr[k]) {
       y[d[k]] = y0[k] + q[k];
-      if (DOT) s += x[d[k]] * q[k];
+      if (DOT) s += xd[k] * q[k];
     }
   }
   if (DOT) {
@@ -1573,15 +1588,28 @@ __device__ __forceinline__ void copy_from_levels_dot_at(int64_t n, const int32_t
                                                         const T* __restrict__ lx, double* __restrict__ z,
                                                         const double* __restrict__ r, double* __restrict__ part,
                                                         int64_t b) {
+  // every load reads a valid address (index clamped to the last node; the
+  // lanes past the end drop their values), so that the loads of all nodes of
+  // a thread issue together instead of one masked branch after another
   const int64_t base = b * blockDim.x * kFuseNPT + threadIdx.x;
+  int32_t cp[kFuseNPT];
+  double rv[kFuseNPT], v[kFuseNPT];
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    const int64_t ic = i < n ? i : n - 1;
+    cp[k] = copy[ic];
+    rv[k] = r[ic];
+  }
+#pragma unroll
+  for (int k = 0; k < kFuseNPT; ++k) v[k] = double(lx[cp[k]]);
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < kFuseNPT; ++k) {
     const int64_t i = base + (int64_t)k * blockDim.x;
     if (i < n) {
-      const double v = double(lx[copy[i]]);
-      z[i] = v;
-      s += r[i] * v;
+      z[i] = v[k];
+      s += rv[k] * v[k];
     }
   }
   s = block_sum(s);

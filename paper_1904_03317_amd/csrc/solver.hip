@@ -44,6 +44,10 @@ static unsigned fuse_grid(int64_t n) {
   const int64_t per = (int64_t)dev::kBlock * dev::kFuseNPT;
   return (unsigned)std::max<int64_t>(1, (n + per - 1) / per);
 }
+static unsigned p2_grid(int64_t n) {
+  const int64_t per = (int64_t)dev::kBlock * dev::kP2NPT;
+  return (unsigned)std::max<int64_t>(1, (n + per - 1) / per);
+}
 static unsigned dot_grid(int64_t n) {
   return (unsigned)std::min<int64_t>(dev::kDotBlocks, std::max<int64_t>(1, (n + dev::kBlock - 1) / dev::kBlock));
 }
@@ -233,7 +237,7 @@ size_t plan_workspace(Problem& P, char* base) {
   // dot partials: the fixed dot grid, or one per block of the fused kernels
   {
     int64_t np = std::max<int64_t>(dev::kDotBlocks, (N + dev::kBlock - 1) / dev::kBlock);
-    if (tiled) np = std::max<int64_t>(np, std::min<int64_t>(LT.n_tiles, dev::kLeafBlocks) + fuse_grid(P.leaf.n_p2));
+    if (tiled) np = std::max<int64_t>(np, std::min<int64_t>(LT.n_tiles, dev::kLeafBlocks) + p2_grid(P.leaf.n_p2));
     P.part = pl.take<double>(np);
   }
   int n0 = 0;
@@ -620,7 +624,7 @@ static int leaf_op(Problem& P, const double* x, double* y, bool mass, double* pa
       return (int)g1 + 1;
     }
     if (n2 == 0) return (int)g1;
-    const unsigned g2 = fuse_grid(n2);
+    const unsigned g2 = p2_grid(n2);
     if (part)
       hipLaunchKernelGGL(dev::leaf_pass2<true>, dim3(g2), dim3(dev::kBlock), 0, s, P.leaf, (const double*)E, x, y,
                          part + g1);
@@ -1251,7 +1255,7 @@ static void plan_cg_tail_batch(const std::vector<Problem*>& ps, hipStream_t s, B
         lz.add(fill_body<double>(1, P->part + g1, 0.0), 1);
         nq = (int)g1 + 1;
       } else {
-        const unsigned g2 = fuse_grid(P->leaf.n_p2);
+        const unsigned g2 = p2_grid(P->leaf.n_p2);
         l2.add(pass2_body(P->leaf, P->E, P->cp, P->cq, P->part + g1), g2);
         nq = (int)(g1 + g2);
       }
