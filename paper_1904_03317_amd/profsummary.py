@@ -10,6 +10,16 @@ operator come last for each precision).
 
 --per-iteration: kernel time per CG iteration inside the last timed solve of
 each precision, delimited by the update_xr dispatches (one per iteration).
+
+--small-grid T (with --per-iteration): also the share of that time in
+level-kernel dispatches (transfers, level operator passes, coarse solve,
+level vector kernels) of fewer than T threads: the coarse levels, since those
+kernels launch about one thread per cell, shared node or family, so a
+threshold between two levels' sizes splits the V-cycle by level.
+
+--layout W,S,K (with --per-iteration): the bench run had W warm-up and S
+timed solves per precision of K iterations each (default 1,2,12); the last
+timed solve of each precision is summarised.
 """
 import argparse
 import collections
@@ -51,7 +61,10 @@ def summarize(db_path, top=30, by_grid=None, last=20):
     return "\n".join(out)
 
 
-def per_iteration(db_path, top=24, solves=(("FP64-MG", 24, 35), ("FP32-MG", 60, 71))):
+LEVEL_KERNEL = re.compile(r"(fam_|coarse_solve|seg_residual|seg_restrict_start|cheb_step|fill<)")
+
+
+def per_iteration(db_path, top=24, solves=(("FP64-MG", 24, 35), ("FP32-MG", 60, 71)), small_grid=None):
     """Kernels between the update_xr dispatches a..b (bench.py with --steps 2
     --warmup 1: dispatches 24..35 are the second timed FP64-MG solve, 60..71
     the second timed FP32-MG solve), per iteration and grid size."""
@@ -73,6 +86,11 @@ def per_iteration(db_path, top=24, solves=(("FP64-MG", 24, 35), ("FP32-MG", 60, 
         span = rows[i1][4] - rows[i0][4]
         out.append(f"{label}: {its} iterations, kernel time {tot / 1e6 / its:.3f} ms/iteration, "
                    f"wall {span / 1e6 / its:.3f} ms/iteration")
+        if small_grid:
+            sm = [v for k, v in agg.items() if k[1] < small_grid and LEVEL_KERNEL.match(k[0])]
+            st = sum(v[1] for v in sm)
+            out.append(f"  dispatches of fewer than {small_grid} threads: {sum(v[0] for v in sm) / its:.1f} per "
+                       f"iteration, {st / 1e6 / its:.3f} ms/iteration, {100 * st / tot:.1f} % of the kernel time")
         out.append(f"{'us/it':>9} {'calls':>5} {'avg_us':>8} {'grid_x':>9}  kernel")
         for k, v in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
             out.append(f"{v[1] / 1e3 / its:9.1f} {v[0] / its:5.1f} {v[1] / v[0] / 1e3:8.1f} {k[1]:9d}  {k[0]}")
@@ -87,8 +105,13 @@ if __name__ == "__main__":
     ap.add_argument("--by-grid", default=None)
     ap.add_argument("--per-iteration", action="store_true")
     ap.add_argument("--last", type=int, default=20)
+    ap.add_argument("--small-grid", type=int, default=None)
+    ap.add_argument("--layout", default="1,2,12")
     a = ap.parse_args()
     print(summarize(a.db, a.top, a.by_grid, a.last))
     if a.per_iteration:
+        w, st, k = (int(t) for t in a.layout.split(","))
+        n = w + st  # solves per precision; the last one of each is summarised
+        solves = (("FP64-MG", (n - 1) * k, n * k - 1), ("FP32-MG", (2 * n - 1) * k, 2 * n * k - 1))
         print()
-        print(per_iteration(a.db))
+        print(per_iteration(a.db, a.top, solves, small_grid=a.small_grid))
