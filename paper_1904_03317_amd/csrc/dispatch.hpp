@@ -124,8 +124,9 @@ struct KernelTable {
   // pass 1 of the leaf operator (or mass matrix): cell results into slots
   // (3D at degree >= 3)
   void (*leaf_e)(const LeafView&, const double* x, double* E, bool mass, const MatsH<double>&, hipStream_t);
-  // tiled leaf operator, pass 1: complete nodes into y, the rest into the
-  // slots E; with part, one partial sum of x.y per block; returns the grid
+  // tiled leaf operator, pass 1: each tile's own nodes into y, its listed
+  // nodes into the slots E; with part, one partial sum of x.y per block over
+  // the own nodes (pass 2 adds the listed nodes' share); returns the grid
   unsigned (*leaf_t)(const LeafView&, const double* x, double* y, double* E, double* part, bool mass,
                      const MatsH<double>&, hipStream_t);
   // level 0: diagonal of the operator accumulated per node
