@@ -1466,8 +1466,30 @@ __device__ __forceinline__ void update_xr_at(int64_t n, double* __restrict__ x, 
                                              const double* __restrict__ sc, double* __restrict__ part, int64_t b,
                                              int64_t nb) {
   const double alpha = sc[kAlpha];
+  const int64_t st = nb * blockDim.x;
   double s = 0.0;
-  for (int64_t i = b * blockDim.x + threadIdx.x; i < n; i += nb * blockDim.x) {
+  int64_t i = b * blockDim.x + threadIdx.x;
+  // four strided nodes per step, their loads issued together (the fixed grid
+  // otherwise has too few loads in flight to reach the copy rate); the sum of
+  // r.r is formed in the same order as one node at a time
+  for (; i + 3 * st < n; i += 4 * st) {
+    double xv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = x[i + k * st];
+      pv[k] = p[i + k * st];
+      rv[k] = r[i + k * st];
+      qv[k] = q[i + k * st];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[i + k * st] = xv[k] + alpha * pv[k];
+      const double ri = rv[k] - alpha * qv[k];
+      r[i + k * st] = ri;
+      s += ri * ri;
+    }
+  }
+  for (; i < n; i += st) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
