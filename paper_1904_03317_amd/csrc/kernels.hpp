@@ -719,7 +719,7 @@ __device__ __forceinline__ void leaf_cell(const MT& m, uint32_t mk, double* u, d
   }
 }
 
-constexpr int kLeafBlocks = 8192;  // grid of leaf_tiles at most (32 one-wave blocks per CU)
+constexpr int kLeafBlocks = 32768;  // grid of leaf_tiles at most (128 one-wave blocks per CU)
 constexpr int kLeafGB = 16;        // tile nodes per lane whose loads are issued together
 constexpr int kLeafOwn = 8;        // own nodes per lane per write-out round
 
