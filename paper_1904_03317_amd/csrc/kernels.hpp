@@ -1426,8 +1426,19 @@ enum ScalarSlot { kRho = 0, kRhoOld, kAlpha, kBeta, kPq, kRr, kBb, kFirst, kNumS
 // sums the partials (fixed order) and updates the CG scalars
 __device__ __forceinline__ void cg_scalars_at(int nparts, const double* __restrict__ part,
                                               double* __restrict__ sc, int op) {
+  // each thread adds its strided partials in ascending order, eight loads
+  // issued at a time (the order of the additions is that of one at a time)
   double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[i];
+  const int st = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * st < nparts; i += 8 * st) {
+    double a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = part[i + k * st];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += a[k];
+  }
+  for (; i < nparts; i += st) v += part[i];
   v = block_sum(v);
   if (threadIdx.x != 0) return;
   if (op == 0) {  // rho = r.z ; beta
